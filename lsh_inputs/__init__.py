@@ -1,0 +1,121 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module only builds inputs: isotropic phase stiffnesses from (E, nu),
+phase maps from point coordinates (laminates, spheres, random sequential
+addition sphere packings) and load cases.  It holds none of the solver's
+arithmetic: point coordinates are passed in by the caller, who takes them from
+its own pattern code.
+
+Geometry: the unit cell is the torus [-1/2, 1/2)^3; a point is inside a sphere
+if its periodic minimum-image distance to the centre is below the radius.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def lame(E, nu):
+    """Lame constants (lambda, mu) of an isotropic material."""
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    return lam, mu
+
+
+def isotropic_voigt(E, nu):
+    """6x6 Voigt stiffness (order 11,22,33,23,13,12; tensor components)."""
+    lam, mu = lame(E, nu)
+    C = np.zeros((6, 6))
+    C[:3, :3] = lam
+    C[0, 0] = C[1, 1] = C[2, 2] = lam + 2 * mu
+    C[3, 3] = C[4, 4] = C[5, 5] = mu
+    return C
+
+
+def mean_reference(C_phases):
+    """Reference stiffness C0 = arithmetic mean of the phase stiffnesses."""
+    return np.mean(np.asarray(C_phases, dtype=np.float64), axis=0)
+
+
+def laminate_phase(points, axis=0):
+    """Two-phase laminate: phase 1 where y_axis >= 0, else phase 0 (layers normal to e_axis)."""
+    y = np.asarray(points)
+    return (y[:, axis] >= 0).astype(np.uint8)
+
+
+def _periodic_dist2(points, center):
+    d = np.asarray(points, dtype=np.float64) - np.asarray(center, dtype=np.float64)[None, :]
+    d -= np.round(d)
+    return np.einsum("ij,ij->i", d, d)
+
+
+def sphere_phase(points, center, radius):
+    """Phase 1 inside the periodic sphere, 0 outside."""
+    return (_periodic_dist2(points, center) < radius * radius).astype(np.uint8)
+
+
+def centred_sphere_radius(fraction):
+    """Radius (cell units) of one sphere of the given volume fraction."""
+    return (3.0 * fraction / (4.0 * np.pi)) ** (1.0 / 3.0)
+
+
+def rsa_spheres(seed, lattice_unit, fraction, rmin=6.0, rmax=12.0, max_attempts=1_000_000):
+    """Random sequential addition of non-overlapping periodic spheres.
+
+    Radii r ~ U[rmin, rmax] * lattice_unit, centres ~ U[-1/2, 1/2)^3, PRNG
+    numpy PCG64(seed).  A sphere is accepted if its periodic distance to every
+    accepted sphere is at least the sum of radii.  Stops when the summed
+    sphere volume reaches ``fraction``; the last radius is shrunk to hit it
+    exactly while it stays >= rmin * lattice_unit.  Returns (centres (k,3), radii (k,)).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    centres, radii = [], []
+    vol = 0.0
+    target = float(fraction)
+    rlo = rmin * lattice_unit
+    for _ in range(max_attempts):
+        if vol >= target:
+            break
+        r = rng.uniform(rmin, rmax) * lattice_unit
+        c = rng.uniform(-0.5, 0.5, size=3)
+        rest = target - vol
+        v = 4.0 / 3.0 * np.pi * r ** 3
+        if v > rest:
+            r_fit = (3.0 * rest / (4.0 * np.pi)) ** (1.0 / 3.0)
+            if r_fit >= rlo:
+                r = r_fit
+                v = rest
+        if centres:
+            C = np.array(centres)
+            d = C - c[None, :]
+            d -= np.round(d)
+            if np.any(np.sqrt(np.einsum("ij,ij->i", d, d)) < np.array(radii) + r):
+                continue
+        centres.append(c)
+        radii.append(r)
+        vol += v
+    return np.array(centres).reshape(-1, 3), np.array(radii)
+
+
+def spheres_phase(points, centres, radii):
+    """Phase 1 inside any of the spheres."""
+    y = np.asarray(points, dtype=np.float64)
+    ph = np.zeros(len(y), dtype=np.uint8)
+    for c, r in zip(np.asarray(centres), np.asarray(radii)):
+        ph |= (_periodic_dist2(y, c) < r * r).astype(np.uint8)
+    return ph
+
+
+def unit_loads():
+    """The six unit Voigt strains (engineering shear); columns of C^eff."""
+    return np.eye(6)
+
+
+def random_unit_load(rng):
+    """A Voigt strain drawn uniformly on the unit 6-sphere."""
+    v = rng.standard_normal(6)
+    return v / np.linalg.norm(v)
+
+
+def lattice_unit(m):
+    """Length of one lattice step of an m-point pattern in cell units: m^{-1/3}."""
+    return float(m) ** (-1.0 / 3.0)

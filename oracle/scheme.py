@@ -1,0 +1,147 @@
+"""The Basic Scheme for the discretised Lippmann-Schwinger equation.
+
+Test infrastructure (oracle); see the package docstring.
+
+Thm. (pde_discretization), eq. (pde_coefficients): the sample values E_y of the
+strain fluctuation satisfy
+    E_y + Gamma^p_y (C(y) - C0) : (E_y + eps0) = 0,   y in P(M),
+where Gamma^p acts as a Fourier multiplier on the pattern (the proof shows the
+condition is an inverse pattern DFT of Gamma^p_h B_hat_h, B_y the polarisation).
+Sec. 4 solves it by the fixed-point iteration of Moulinec and Suquet on E_y,
+stopped by a relative Cauchy criterion.  Readings used here:
+
+* polarisation form  E^{k+1} = -Re F^{-1}[ Gamma^p_h F[(C - C0):(E^k + eps0)]_h ],
+  E^0 = 0 (or a given start with its mean removed);
+* Cauchy residual  r_{k+1} = ||E^{k+1} - E^k|| / ||E^{k+1} + eps0||, Frobenius
+  norms summed over all points (the paper names neither norm nor denominator);
+* effective stress  sigma_bar = (1/m) sum_y C(y):(E_y + eps0), the pattern mean
+  of the definition of C^eff (Sec. 3.1) at the samples;
+* the real part: strain fields are real (Sym_d(R)); for every kernel except the
+  literal Dirichlet one Gamma^p is even in h and the real part changes nothing.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import dft
+from . import green
+from .lattice import Pattern
+
+
+def stiffness_field(C_phases_voigt, phase):
+    """Per-point Mandel stiffness (m, 6, 6) from per-phase Voigt matrices."""
+    Cm = green.voigt_stiffness_to_mandel(np.asarray(C_phases_voigt, dtype=np.float64))
+    return Cm[np.asarray(phase, dtype=np.int64)]
+
+
+def basic_scheme(P: Pattern, Gamma, C_phases_voigt, C0_voigt, phase, eps0_voigt,
+                 tol=1e-10, max_iter=1000, E_init=None, n_iter=None):
+    """Run the fixed point of eq. (pde_coefficients).
+
+    Parameters
+    ----------
+    Gamma : (m, 6, 6) Gamma^p_h in frequency storage order (``green.gamma_periodised``).
+    eps0_voigt : macroscopic strain, Voigt with engineering shear.
+    E_init : optional start (m, 6) Mandel; its mean is removed.
+    n_iter : if given, run exactly this many iterations (no stopping test).
+
+    Returns dict(E (m,6) Mandel, sigma_voigt (6,), iterations, history).
+    """
+    m = P.m
+    C = stiffness_field(C_phases_voigt, phase)
+    C0 = green.voigt_stiffness_to_mandel(C0_voigt)
+    Delta = C - C0[None]
+    eps0 = green.voigt_strain_to_mandel(eps0_voigt)
+    if E_init is None:
+        E = np.zeros((m, 6))
+    else:
+        E = np.array(E_init, dtype=np.float64).reshape(m, 6)
+        E = E - E.mean(axis=0, keepdims=True)
+    history = []
+    it = 0
+    limit = n_iter if n_iter is not None else max_iter
+    while it < limit:
+        tau = np.einsum("yij,yj->yi", Delta, E + eps0)          # (C - C0):(E + eps0)
+        tau_hat = dft.pattern_dft(P, tau)                          # F(M), unnormalised
+        E_hat = -np.einsum("bij,bj->bi", Gamma, tau_hat)           # -Gamma^p_h tau_hat_h
+        E_new = dft.pattern_idft(P, E_hat).real                    # inverse pattern DFT
+        num = np.sqrt(np.sum((E_new - E) ** 2))
+        den = np.sqrt(np.sum((E_new + eps0) ** 2))
+        r = num / den
+        E = E_new
+        it += 1
+        history.append(r)
+        if n_iter is None and r <= tol:
+            break
+    sigma = np.einsum("yij,yj->i", C, E + eps0) / m
+    return dict(E=E, sigma_voigt=green.mandel_stress_to_voigt(sigma), iterations=it,
+                history=np.array(history))
+
+
+def effective_stiffness(P: Pattern, Gamma, C_phases_voigt, C0_voigt, phase, tol=1e-10,
+                        max_iter=1000, n_iter=None):
+    """C^eff in Voigt form: column j is sigma_bar for the unit Voigt load e_j (Sec. 3.1)."""
+    Ceff = np.zeros((6, 6))
+    its = []
+    for j in range(6):
+        e = np.zeros(6)
+        e[j] = 1.0
+        res = basic_scheme(P, Gamma, C_phases_voigt, C0_voigt, phase, e, tol=tol,
+                           max_iter=max_iter, n_iter=n_iter)
+        Ceff[:, j] = res["sigma_voigt"]
+        its.append(res["iterations"])
+    return Ceff, its
+
+
+def dense_fixed_point(M, C0_voigt, kind, params, C_phases_voigt, phase_by_point, eps0_voigt):
+    """Solve eq. (pde_coefficients) directly as a dense linear system (tiny m).
+
+    Independent of the SNF path: the pattern DFT is the matrix of
+    eq. (Fouriermatrix) over brute-force enumerations of P(M) and G(M^T), and
+    Gamma^p_h is evaluated at those h.  Unknowns are E_y (6 per point):
+        (I + R) E = -R eps0,   R = Re F^H diag(Gamma_h) F (C - C0).
+    ``phase_by_point`` maps each brute-force point (tuple of Fractions) to its
+    phase.  Returns (Y, E) with Y the points and E (m, 6) Mandel.
+    """
+    F, H, Y = dft.fourier_matrix(M)
+    from .lattice import brute_force_points
+    Yf = brute_force_points(M)
+    m = len(Yf)
+    P = Pattern(M)
+    C0 = green.voigt_stiffness_to_mandel(C0_voigt)
+    Cm = green.voigt_stiffness_to_mandel(np.asarray(C_phases_voigt, dtype=np.float64))
+    ph = np.array([phase_by_point[y] for y in Yf], dtype=np.int64)
+    Delta = Cm[ph] - C0[None]
+    # Gamma^p at the brute-force rows h: sum over aliases of the weights
+    MT = np.array(P.MT, dtype=np.int64)
+    Minv_T = np.linalg.inv(np.array(P.M, dtype=np.float64)).T
+    g = green.weight_fn(kind, params)
+    Z = green.alias_offsets(kind, params, P.d)
+    G = np.zeros((m, 6, 6))
+    for r, h in enumerate(H):
+        if not np.any(h):
+            continue
+        x = Minv_T @ h
+        num = np.zeros((6, 6))
+        den = 0.0
+        for z in Z:
+            w = g((x + z)[None])[0] ** 2
+            if w > 0:
+                num += w * green.gamma0(C0_voigt, (h + MT @ z)[None])[0]
+                den += w
+        G[r] = num / den
+    # operator A: E (m*6) -> Re F^H Gamma F (Delta E), F unitary
+    Fh = F.conj().T
+    A = np.zeros((m * 6, m * 6))
+    for p in range(m):
+        for j in range(6):
+            v = np.zeros((m, 6))
+            v[p] = Delta[p][:, j]          # column j of Delta at point p
+            vh = F @ v                       # (m, 6) spectrum
+            out = -(Fh @ np.einsum("hij,hj->hi", G, vh)).real
+            A[:, p * 6 + j] = out.reshape(-1)
+    eps0 = green.voigt_strain_to_mandel(eps0_voigt)
+    rhs = (A @ np.tile(eps0, m))
+    # E = A (E + eps0)  ->  (I - A) E = A eps0
+    E = np.linalg.solve(np.eye(m * 6) - A, rhs).reshape(m, 6)
+    return Y, E

@@ -1,0 +1,156 @@
+"""Pins for the oracle's Basic Scheme (Thm. (pde_discretization), Sec. 4)."""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import green, scheme
+from oracle.lattice import Pattern
+import lsh_inputs as li
+
+HERE = os.path.dirname(__file__)
+BOX4 = {"Xi": np.array([[1, 0, 0, 1], [0, 1, 0, 1], [0, 0, 1, 0]], float), "R": 3}
+KERNELS = [("dirichlet", {}), ("dirichlet_modified", {}), ("dlvp", {"alpha": [0.75] * 3}), ("box", BOX4)]
+
+
+def two_phase(E1=1.0, E2=10.0, nu=0.3):
+    Cp = np.stack([li.isotropic_voigt(E1, nu), li.isotropic_voigt(E2, nu)])
+    return Cp, li.mean_reference(Cp)
+
+
+@pytest.mark.parametrize("kind,params", KERNELS)
+def test_homogeneous_material_one_iteration(kind, params):
+    """C constant: the polarisation is constant, only h = 0 is excited, and
+    Gamma^p_0 = 0, so E^1 = 0 exactly and sigma_bar = C eps0."""
+    P = Pattern([[4, 1, 0], [0, 4, 0], [0, 0, 2]])
+    Cp = np.stack([li.isotropic_voigt(3.0, 0.2)])
+    C0 = li.isotropic_voigt(1.0, 0.3)
+    G, _ = green.gamma_periodised(P, C0, kind, params)
+    eps0 = np.array([0.3, -0.1, 0.2, 0.05, -0.4, 0.1])
+    res = scheme.basic_scheme(P, G, Cp, C0, np.zeros(P.m, np.uint8), eps0, tol=1e-12)
+    assert res["iterations"] == 1
+    assert np.abs(res["E"]).max() < 1e-15
+    np.testing.assert_allclose(res["sigma_voigt"], Cp[0] @ eps0, rtol=1e-14)
+
+
+def _laminate_closed_form():
+    gold = json.load(open(os.path.join(HERE, "golden", "laminate.json")))
+    C = np.zeros((6, 6))
+    names = {"C11": (0, 0), "C12": (0, 1), "C13": (0, 2), "C22": (1, 1), "C33": (2, 2),
+             "C23": (1, 2), "C44": (3, 3), "C55": (4, 4), "C66": (5, 5)}
+    for k, (i, j) in names.items():
+        C[i, j] = C[j, i] = gold[k][0] / gold[k][1]
+    return C, gold
+
+
+def _laminate_formulas(E=(1.0, 10.0), nu=0.3):
+    """Rank-one laminate, f = 1/2, normal e1 (textbook formulas, independent of the scheme)."""
+    lam = np.array([li.lame(e, nu)[0] for e in E])
+    mu = np.array([li.lame(e, nu)[1] for e in E])
+    Pm = lam + 2 * mu
+    av = lambda v: v.mean()
+    C11 = 1 / av(1 / Pm)
+    C12 = av(lam / Pm) * C11
+    C22 = av(Pm - lam ** 2 / Pm) + av(lam / Pm) ** 2 * C11
+    C23 = av(lam - lam ** 2 / Pm) + av(lam / Pm) ** 2 * C11
+    return dict(C11=C11, C12=C12, C22=C22, C23=C23, C44=av(mu), C55=1 / av(1 / mu))
+
+
+def test_laminate_golden_matches_formulas():
+    C, _ = _laminate_closed_form()
+    f = _laminate_formulas()
+    for k, (i, j) in {"C11": (0, 0), "C12": (0, 1), "C22": (1, 1), "C23": (1, 2), "C44": (3, 3), "C55": (4, 4)}.items():
+        assert abs(C[i, j] - f[k]) < 1e-14
+
+
+@pytest.mark.parametrize("kind,params", KERNELS)
+def test_laminate_closed_form(kind, params):
+    """16^3 laminate (layers normal to x1, f = 1/2, E = 1/10, nu = 0.3, C0 = mean):
+    the Basic Scheme reproduces the closed-form C^eff for every kernel and stops
+    after 2 iterations (the first iterate is exact)."""
+    C_ref, gold = _laminate_closed_form()
+    P = Pattern(np.diag([16, 16, 16]))
+    ph = li.laminate_phase(P.points(), 0)
+    Cp, C0 = two_phase()
+    G, _ = green.gamma_periodised(P, C0, kind, params)
+    Ceff, its = scheme.effective_stiffness(P, G, Cp, C0, ph, tol=1e-10)
+    np.testing.assert_allclose(Ceff, C_ref, rtol=0, atol=1e-12 * np.abs(C_ref).max())
+    assert its[0] == gold["iterations_dirichlet_C0_mean"]
+
+
+@pytest.mark.parametrize("M", [[[4, 1, 0], [0, 4, 0], [0, 0, 2]], [[3, 1, 0], [-1, 2, 1], [0, 1, 4]]])
+@pytest.mark.parametrize("kind,params", KERNELS)
+def test_fixed_point_equals_dense_solve(M, kind, params):
+    """The Basic Scheme limit solves eq. (pde_coefficients): compare with a dense
+    linear solve assembled from the Fourier matrix written out entry by entry."""
+    P = Pattern(M)
+    rng = np.random.default_rng(4)
+    ph = rng.integers(0, 2, size=P.m).astype(np.uint8)
+    Cp, C0 = two_phase(1.0, 5.0, 0.3)
+    eps0 = np.array([0.2, -0.1, 0.05, 0.3, 0.1, -0.2])
+    G, _ = green.gamma_periodised(P, C0, kind, params)
+    res = scheme.basic_scheme(P, G, Cp, C0, ph, eps0, tol=1e-15, max_iter=5000)
+    Ynum = P.point_numerators()
+    by_point = {tuple(Fraction(int(v), P.m) for v in row): int(p) for row, p in zip(Ynum, ph)}
+    Y, Ed = scheme.dense_fixed_point(M, C0, kind, params, Cp, by_point, eps0)
+    key = {tuple(Fraction(int(v), P.m) for v in row): i for i, row in enumerate(Ynum)}
+    from oracle.lattice import brute_force_points
+    order = [key[y] for y in brute_force_points(M)]
+    np.testing.assert_allclose(res["E"][order], Ed, atol=1e-11 * max(1, np.abs(Ed).max()))
+
+
+@pytest.mark.parametrize("kind,params", [("dirichlet", {}), ("dlvp", {"alpha": [0.5] * 3}), ("box", BOX4)])
+def test_effective_tensor_symmetric(kind, params):
+    """C^eff is symmetric at the fixed point for every kernel (Gamma^p C0 is
+    C0-self-adjoint, Sec. 3.2 adjointness theorem), up to the iteration error."""
+    P = Pattern(np.diag([6, 6, 6]))
+    rng = np.random.default_rng(6)
+    ph = rng.integers(0, 2, size=P.m).astype(np.uint8)
+    Cp, C0 = two_phase(1.0, 10.0, 0.3)
+    G, _ = green.gamma_periodised(P, C0, kind, params)
+    Ceff, _ = scheme.effective_stiffness(P, G, Cp, C0, ph, tol=1e-13, max_iter=3000)
+    asym = np.linalg.norm(Ceff - Ceff.T) / np.linalg.norm(Ceff)
+    assert asym < 1e-11
+
+
+def test_dirichlet_between_reuss_and_voigt_bounds():
+    """The Dirichlet discretisation is a Galerkin method on compatible fields,
+    so C_Reuss <= C^eff <= C_Voigt in the Loewner order (Mandel form)."""
+    P = Pattern(np.diag([6, 6, 6]))
+    rng = np.random.default_rng(7)
+    ph = rng.integers(0, 2, size=P.m).astype(np.uint8)
+    Cp, C0 = two_phase(1.0, 10.0, 0.3)
+    G, _ = green.gamma_periodised(P, C0, "dirichlet")
+    Ceff, _ = scheme.effective_stiffness(P, G, Cp, C0, ph, tol=1e-13, max_iter=3000)
+    Cm = green.voigt_stiffness_to_mandel(Cp)
+    f = ph.mean()
+    voigt = (1 - f) * Cm[0] + f * Cm[1]
+    reuss = np.linalg.inv((1 - f) * np.linalg.inv(Cm[0]) + f * np.linalg.inv(Cm[1]))
+    Ce = green.voigt_stiffness_to_mandel(0.5 * (Ceff + Ceff.T))
+    assert np.linalg.eigvalsh(voigt - Ce).min() > -1e-10
+    assert np.linalg.eigvalsh(Ce - reuss).min() > -1e-10
+
+
+def test_ls_and_variational_differ_for_dlvp_only():
+    """Remark (constants): eps_M - Gamma^p C0 eps_M = eps0 holds only for the
+    Dirichlet space.  Check on the fixed point: the residual of the identity
+    vanishes for Dirichlet and not for dlVP.  Odd axes: there the Dirichlet
+    multiplier is even and no real-part projection is involved."""
+    P = Pattern(np.diag([5, 5, 7]))
+    rng = np.random.default_rng(8)
+    ph = rng.integers(0, 2, size=P.m).astype(np.uint8)
+    Cp, C0 = two_phase(1.0, 10.0, 0.3)
+    C0m = green.voigt_stiffness_to_mandel(C0)
+    from oracle import dft
+    eps0 = np.array([1.0, 0, 0, 0, 0, 0])
+    out = {}
+    for kind, params in [("dirichlet", {}), ("dlvp", {"alpha": [0.75] * 3})]:
+        G, _ = green.gamma_periodised(P, C0, kind, params)
+        res = scheme.basic_scheme(P, G, Cp, C0, ph, eps0, tol=1e-14, max_iter=3000)
+        eps = res["E"] + green.voigt_strain_to_mandel(eps0)
+        GCe = dft.pattern_idft(P, np.einsum("bij,bj->bi", G @ C0m, dft.pattern_dft(P, eps))).real
+        out[kind] = np.abs(eps - GCe - green.voigt_strain_to_mandel(eps0)).max()
+    assert out["dirichlet"] < 1e-12
+    assert out["dlvp"] > 1e-4
