@@ -1,0 +1,176 @@
+"""Benchmark: Basic Scheme voxel-iterations per second on one MI355X.
+
+Workload (default): the FP64 single-GPU configuration -- pattern
+M = diag(128,128,128) (m = 2,097,152 points), de la Vallee Poussin kernel with
+flat-top width 1/4 (alpha = 3/4 per axis), one centred spherical inclusion of
+volume fraction 0.2, contrast E_incl/E_matrix = 10 (nu = 0.3 both), reference
+stiffness the mean of the phases, all six unit load cases side by side.
+
+A step is one Basic Scheme iteration of all six load cases: stress, forward
+pattern FFT, Green multiply with on-the-fly alias sums, inverse FFT, update
+and the double-precision Cauchy residual.  Inputs are resident in HBM before
+the timed region.  The timed region runs exactly --steps iterations
+(fixed-count mode); per-kernel GPU times come from HIP events recorded on the
+solver's stream inside that region.
+
+Also reported: the time to the configuration's tolerance 1e-8 (a converged
+solve) and the FP64 oracle timed on a bounded sample on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Basic Scheme voxel-iters/s (%HBM roofline); time-to-1e-6 learned vs plain start"
+HBM_PEAK_GBS = 8000.0
+KERNEL_NAMES = ["axis1_stress", "axis2_forward", "green_axis3", "residual_reduce", "axis2_inverse", "final_sigma"]
+
+
+def build_problem(lsh, li):
+    M = np.diag([128, 128, 128])
+    P = lsh.Pattern(M)
+    Y = P.points()
+    phase = li.sphere_phase(Y, np.zeros(3), li.centred_sphere_radius(0.2))
+    Cp = np.stack([li.isotropic_voigt(1.0, 0.3), li.isotropic_voigt(10.0, 0.3)])
+    C0 = li.mean_reference(Cp)
+    P.set_kernel("dlvp", {"alpha": [0.75, 0.75, 0.75]})
+    P.set_stiffness(Cp, C0, phase)
+    P.bind("fp64")
+    return P, Cp, C0, phase
+
+
+def algorithmic_bytes(P, nload, s=8):
+    """Bytes each kernel must move per launch (complex scalar 2s, 6 components)."""
+    e = P.e
+    spec = (e[0] // 2 + 1) * e[1] * e[2]
+    field = nload * 6 * spec * 2 * s
+    return {
+        "axis1_stress": 2 * field + nload * P.m,   # read E, write tau, read phase
+        "axis2_forward": 2 * field,
+        "green_axis3": 3 * field,                  # read tau, read previous E, write E
+        "axis2_inverse": 2 * field,
+    }
+
+
+def cpu_baseline(iters=6):
+    """The FP64 oracle on one load case of the same 128^3 problem (Gamma table
+    built first, outside the timed part)."""
+    from oracle import green, scheme
+    from oracle.lattice import Pattern as OP
+    import lsh_inputs as li
+    O = OP(np.diag([128, 128, 128]))
+    ph = li.sphere_phase(O.points(), np.zeros(3), li.centred_sphere_radius(0.2))
+    Cp = np.stack([li.isotropic_voigt(1.0, 0.3), li.isotropic_voigt(10.0, 0.3)])
+    C0 = li.mean_reference(Cp)
+    G, _ = green.gamma_periodised(O, C0, "dlvp", {"alpha": [0.75] * 3}, chunk=1 << 16)
+    c0 = os.times()
+    t0 = time.perf_counter()
+    scheme.basic_scheme(O, G, Cp, C0, ph, np.array([1.0, 0, 0, 0, 0, 0]), n_iter=iters)
+    wall = time.perf_counter() - t0
+    c1 = os.times()
+    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    return {"value": O.m * iters / wall, "unit": "voxel-iters/s", "cores": max(1, int(round(cpu / wall))),
+            "kind": "oracle",
+            "sample": f"one load case (e11), {iters} Basic Scheme iterations of the 128^3 dlVP problem, "
+                      f"Gamma^p table precomputed outside the timing; {wall:.1f} s wall, {cpu:.1f} s CPU"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the converged (time-to-tol) solve")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU kernel path "
+              "(multi-GPU sharding is described in DESIGN.md, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1701_04685_amd import lsh
+    import lsh_inputs as li
+
+    torch.cuda.set_device(0)
+    P, Cp, C0, phase = build_problem(lsh, li)
+    nload = 6
+    loads = np.eye(6)
+    ws = torch.empty(P.workspace_bytes(nload), dtype=torch.uint8, device="cuda")
+
+    # warm-up (untimed)
+    P.solve(loads, tol=-1.0, max_iter=max(1, args.warmup), workspace=ws)
+    torch.cuda.synchronize()
+
+    # timed region: exactly `steps` iterations, per-kernel events on the solver's stream
+    lsh.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.solve(loads, tol=-1.0, max_iter=args.steps, workspace=ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, cnt = lsh.profile_read()
+    lsh.profile_enable(False)
+
+    voxel_iters = nload * P.m * args.steps
+    value = voxel_iters / wall
+    per_kernel = {}
+    for i, name in enumerate(KERNEL_NAMES):
+        if cnt[i] > 0:
+            per_kernel[name] = {"avg_ms": ms[i] / cnt[i], "launches": int(cnt[i]), "total_ms": ms[i]}
+    algo = algorithmic_bytes(P, nload)
+    dom = max((k for k in algo if k in per_kernel), key=lambda k: per_kernel[k]["total_ms"])
+    achieved = algo[dom] / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "alg_bytes_per_launch": int(algo[dom]), "avg_launch_ms": round(per_kernel[dom]["avg_ms"], 5)}
+    bytes_per_vi = sum(algo.values()) / (nload * P.m)
+
+    solve_info = None
+    if not args.no_solve:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = P.solve(loads, tol=1e-8, max_iter=2000, workspace=ws)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        C = res["sigma"].T
+        solve_info = {"tol": 1e-8, "iterations": [int(v) for v in res["iterations"]], "seconds": round(ts, 4),
+                      "voxel_iters_per_s": float(P.m * res["iterations"].sum() / ts),
+                      "C_eff_voigt_diag": [round(float(v), 8) for v in np.diag(C)],
+                      "C_eff_asym": float(np.linalg.norm(C - C.T) / np.linalg.norm(C))}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "voxel-iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "128^3 diagonal pattern, dlVP alpha=3/4, centred sphere f=0.2, contrast 10, "
+                               "6 unit load cases, FP64 Basic Scheme", "m": P.m, "snf": list(P.e),
+                   "nload": nload, "kernel": "dlvp", "precision": "fp64"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "per_kernel": per_kernel,
+        "bytes_per_voxel_iter_algorithmic": round(bytes_per_vi, 1),
+        "hbm_roofline_voxel_iters_per_s": HBM_PEAK_GBS * 1e9 / bytes_per_vi,
+        "solve_to_tol": solve_info,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

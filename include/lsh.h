@@ -1,0 +1,196 @@
+/*
+ * lsh.h -- Lippmann-Schwinger homogenisation on the pattern P(M), MI355X (gfx950).
+ *
+ * C ABI of liblsh.so.  The library solves the discretised Lippmann-Schwinger
+ * equation of Bergmann & Merkert, "FFT-based homogenization on periodic
+ * anisotropic translation invariant spaces" (arXiv 1701.04685),
+ * Thm. (pde_discretization), eq. (pde_coefficients):
+ *
+ *     E_y + Gamma^p_y (C(y) - C0) : (E_y + eps0) = 0,      y in P(M),
+ *
+ * with the fixed-point iteration of Moulinec and Suquet ("Basic Scheme",
+ * Sec. 4) and returns the effective stress C^eff : eps0 (Sec. 3.1).
+ *
+ * Conventions (all entry points)
+ *  - Every function returns an lsh_status; nothing throws across the ABI.
+ *    On error, lsh_last_error() returns a thread-local message.
+ *  - Host arrays passed in are copied; the caller keeps ownership.
+ *  - Device memory is always allocated by the caller (for example as a torch
+ *    uint8 tensor) and must outlive the work queued on `stream`.  The library
+ *    itself never allocates device memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *  - Voigt order is (11, 22, 33, 23, 13, 12).  Strains use engineering shear
+ *    (gamma_23 = 2 eps_23); stresses and stiffness matrices are tensor
+ *    components.  Internally the library works in Mandel form.
+ *  - Real-space device fields are laid out [load][component][a1][a2][a3] with
+ *    a = (a1, a2, a3) the SNF grid index of the point (lsh_pattern_points),
+ *    a3 fastest.
+ */
+#ifndef LSH_H
+#define LSH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lsh_pattern lsh_pattern; /* opaque; created/destroyed by the library */
+
+typedef enum {
+  LSH_OK = 0,
+  LSH_EINVAL = -1,        /* bad argument (null pointer, size, range)                        */
+  LSH_ESINGULAR = -2,     /* det M == 0: P(M) needs a regular M (Sec. 2.1)                   */
+  LSH_ENOINTERP = -3,     /* a bracket sum of |c_k(f)|^2 vanishes: translates not linearly
+                             independent (Lemma (FI:Props) a/b)                              */
+  LSH_ENOTELLIPTIC = -4,  /* a stiffness is not symmetric positive definite (Sec. 3.1)       */
+  LSH_ENOTCONVERGED = -5, /* max_iter reached before the Cauchy residual met tol             */
+  LSH_ENONFINITE = -6,    /* NaN/Inf in the iteration                                        */
+  LSH_EDEVICE = -7,       /* a HIP runtime call failed                                       */
+  LSH_EWORKSPACE = -8,    /* device buffer smaller than the *_bytes query returned           */
+  LSH_EUNSUPPORTED = -9,  /* SNF factor or size outside what the GPU path supports           */
+  LSH_ESTATE = -10        /* call order: kernel/stiffness not set or device data not bound  */
+} lsh_status;
+
+typedef enum {
+  LSH_DIRICHLET = 0,          /* D_M, g = 1 on [-1/2,1/2)^d (Sec. 2.2, Def. (dlVP) remark)   */
+  LSH_DIRICHLET_MODIFIED = 1, /* f_{M,0}: limit alpha -> 0 of the dlVP means (Sec. 2.2)       */
+  LSH_DLVP = 2,               /* de la Vallee Poussin mean f_{M,g_alpha}, Def. (dlVP)          */
+  LSH_BOXSPLINE = 3           /* periodised pattern Box spline f_{M,Xi} (Sec. 2.2)             */
+} lsh_kernel;
+
+typedef enum {
+  LSH_FP64 = 0,      /* every step in double precision                                       */
+  LSH_FP32_MIXED = 1 /* FFT, Green multiply and stress in float; residual norms, the
+                        effective-stress average and Gamma^p alias sums in double            */
+} lsh_precision;
+
+typedef struct {
+  int32_t iterations; /* Basic Scheme iterations performed for this load case              */
+  int32_t converged;  /* 1 if the Cauchy residual reached tol                              */
+  double residual;    /* last Cauchy residual ||E^k - E^{k-1}|| / ||E^k + eps0||            */
+  double seconds;     /* wall time of the whole iteration loop (same for all loads)         */
+} lsh_stats;
+
+/* ------------------------------------------------------------------ pattern ---
+ * Sec. 2.1: the lattice Lambda(M) = M^{-1} Z^d, the pattern P(M) (points in
+ * [-1/2,1/2)^d) and the generating set G(M^T); m = |det M|.  The library
+ * takes the integer Smith normal form M = U diag(e1,e2,e3) V and orders P(M)
+ * by a in Z_e1 x Z_e2 x Z_e3 (y = M^{-1} U a mod 1) and G(M^T) by b
+ * (h = V^T b mod M^T); the pattern DFT of eq. (Fouriermatrix) is then the
+ * plain 3-D DFT over that grid.
+ *   d      : must be 3 (the GPU path is three-dimensional).
+ *   M      : d*d integers, row-major.
+ *   out    : receives a new pattern; release with lsh_destroy.
+ * Errors: LSH_EINVAL (d != 3, null), LSH_ESINGULAR (det M == 0),
+ *         LSH_EUNSUPPORTED (|det M| beyond int32 grid limits).                     */
+int lsh_create_pattern(int d, const int64_t *M, lsh_pattern **out);
+void lsh_destroy(lsh_pattern *p);
+
+/* m = |det M| and the SNF diagonal e (e1 | e2 | e3).                               */
+int lsh_pattern_info(const lsh_pattern *p, int64_t *m, int64_t e[3]);
+
+/* The unimodular SNF factors, M = U diag(e) V, each 3x3 row-major.                */
+int lsh_pattern_snf(const lsh_pattern *p, int64_t U[9], int64_t V[9]);
+
+/* The points of P(M) in storage order: y = y_num / m, y in [-1/2,1/2)^3 exactly.
+ *   y_num : host int64 array of m*3 entries, caller-allocated.                    */
+int lsh_pattern_points(const lsh_pattern *p, int64_t *y_num);
+
+/* -------------------------------------------------------- generating function ---
+ * Chooses f, and with it the periodised Green operator of
+ * Def. (gamma_tilde_fourier), Gamma^p_h = m [ {Gamma0_k |c_k(f)|^2} ]^M_h, for
+ * orthonormalised translates (Lemma (FI:Props) c):
+ *   Gamma^p_h = sum_z g(x+z)^2 Gamma0_{h+M^T z} / sum_z g(x+z)^2,  x = M^{-T} h.
+ *   LSH_DIRICHLET, LSH_DIRICHLET_MODIFIED : nparams = 0.
+ *   LSH_DLVP      : params = alpha[3], each in (0, 1], the trapezoid of Sec. 2.2
+ *                   (g_alpha = B_Xi, Xi = (diag alpha, I); alpha = 1 is Fejer).
+ *   LSH_BOXSPLINE : params = {s, Xi[3*s] (columns, pattern coordinates, row-major
+ *                   3 x s), R}; the alias sum runs over z in [-R,R]^3
+ *                   (Sec. 4.2 truncates the bracket sums to a box of terms).
+ * Host only.  Errors: LSH_EINVAL (kind, parameter count or range).               */
+int lsh_set_kernel(lsh_pattern *p, lsh_kernel kind, const double *params, int nparams);
+
+/* ------------------------------------------------------------------ stiffness ---
+ * The piecewise-constant stiffness C(y) (Def. (weak_pde)) and the reference C0
+ * of the Green operator (Def. (projection)).
+ *   nphase   : 1..256 phases.
+ *   C_voigt  : nphase*36 doubles, Voigt 6x6 per phase (row-major).
+ *   C0_voigt : 36 doubles.
+ *   phase    : m bytes, phase index of each point in storage order.
+ * Host only (copied).  Errors: LSH_EINVAL, LSH_ENOTELLIPTIC (a matrix not SPD).  */
+int lsh_set_stiffness(lsh_pattern *p, int nphase, const double *C_voigt,
+                      const double *C0_voigt, const uint8_t *phase);
+
+/* ------------------------------------------------------------- device binding ---
+ * Bytes of persistent device memory for this pattern at precision prec: the
+ * phase map, FFT twiddles and, for LSH_BOXSPLINE, the Gamma^p table (21
+ * entries per half-spectrum bin, summed in double, stored at prec).
+ * Needs lsh_set_kernel first.                                                     */
+int lsh_persistent_bytes(const lsh_pattern *p, lsh_precision prec, size_t *bytes);
+
+/* Uploads the phase map and twiddles into dev_persistent and, for tabled
+ * kernels, builds the Gamma^p table on the GPU (synchronises `stream`; checks
+ * every bracket sum is positive).  dev_persistent must stay alive while the
+ * pattern is used at this precision.  Errors: LSH_ESTATE (kernel/stiffness not
+ * set), LSH_EWORKSPACE, LSH_ENOINTERP, LSH_EUNSUPPORTED, LSH_EDEVICE.            */
+int lsh_bind(lsh_pattern *p, lsh_precision prec, void *dev_persistent, size_t bytes,
+             void *stream);
+
+/* Evaluates the (Hermitian-symmetrised) Gamma^p at n frequency bins b
+ * (3 ints each, 0 <= b1 <= e1/2, 0 <= b2 < e2, 0 <= b3 < e3) with the same
+ * device code the solver uses; writes 21 doubles per bin (upper triangle of
+ * the 6x6 Mandel matrix, row by row).  dev_scratch: >= n*(24+21*8) bytes.
+ * Synchronises `stream`.  For tests and diagnostics.                            */
+int lsh_gamma_probe(const lsh_pattern *p, lsh_precision prec, const int64_t *bins, int n,
+                    double *out, void *dev_scratch, size_t scratch_bytes, void *stream);
+
+/* ---------------------------------------------------------------------- solve ---
+ * Workspace bytes for lsh_solve with nload load cases at precision prec.          */
+int lsh_solve_bytes(const lsh_pattern *p, int nload, lsh_precision prec, size_t *bytes);
+
+/* Basic Scheme for eq. (pde_coefficients), Sec. 4:
+ *   E^0 = 0 (or dev_E_init, mean removed);
+ *   E^{k+1} = -F^{-1}[ Gamma^p_h F[(C - C0):(E^k + eps0)]_h ]   (real part);
+ *   stop when ||E^{k+1} - E^k|| / ||E^{k+1} + eps0|| <= tol (Frobenius norms over
+ *   all points; relative Cauchy criterion of Sec. 4).
+ * Load cases run side by side and stop independently.
+ *   nload        : 1..64 load cases.
+ *   eps0_voigt   : host nload*6 macroscopic strains (Voigt, engineering shear).
+ *   tol          : Cauchy tolerance; tol < 0 runs exactly max_iter iterations
+ *                  (fixed-count mode, returns LSH_OK).
+ *   max_iter     : iteration limit, >= 1.
+ *   dev_workspace: >= lsh_solve_bytes(...) bytes.
+ *   dev_E_init   : optional device double [nload][6][m] start fluctuation (Voigt,
+ *                  engineering shear) or NULL for zero.
+ *   dev_E_out    : optional device double [nload][6][m] receiving the final E.
+ *   sigma_out    : host nload*6: sigma_bar = (1/m) sum_y C(y):(E_y + eps0)
+ *                  (Voigt stress) at the final iterate (Sec. 3.1, C^eff : eps0).
+ *   stats        : optional host nload entries.
+ *   history      : optional host nload*max_iter residuals (NaN after stopping).
+ * Runs on `stream` and synchronises it before returning.
+ * Errors: LSH_ESTATE, LSH_EINVAL, LSH_EWORKSPACE, LSH_ENOTCONVERGED (outputs
+ * still filled from the last iterate), LSH_ENONFINITE, LSH_EDEVICE.              */
+int lsh_solve(lsh_pattern *p, int nload, const double *eps0_voigt, double tol, int max_iter,
+              lsh_precision prec, void *dev_workspace, size_t ws_bytes, void *stream,
+              const double *dev_E_init, double *dev_E_out, double *sigma_out,
+              lsh_stats *stats, double *history);
+
+/* --------------------------------------------------------------- diagnostics ---
+ * Per-kernel GPU time, from HIP event pairs recorded on the solve stream around
+ * every launch and read back at the solver's own synchronisation points.
+ * Slots: 0 axis-1 stress pass, 1 axis-2 forward, 2 Green pass (axis 3),
+ * 3 residual reduction, 4 axis-2 inverse, 5 final effective-stress pass.
+ * lsh_profile_enable(1) clears the counters; process-wide, not thread-safe.   */
+int lsh_profile_enable(int on);
+int lsh_profile_read(double *ms, long long *counts, int n);
+
+/* Thread-local message for the last non-zero status returned on this thread.      */
+const char *lsh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSH_H */

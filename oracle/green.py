@@ -243,8 +243,14 @@ def gamma_periodised(P: Pattern, C0_voigt, kind, params=None, b=None, chunk=4096
     Also returns the bracket sum of the weights (Lemma (FI:Props) b: it must be
     positive for linearly independent translates).
     """
+    H, _ = P.frequencies(b)
+    return gamma_at_frequencies(P, C0_voigt, kind, params, H, chunk)
+
+
+def gamma_at_frequencies(P: Pattern, C0_voigt, kind, params, H, chunk=4096):
+    """Gamma^p at integer frequencies H (n, d); each h is first reduced into G(M^T)."""
     params = params or {}
-    H, Xn = P.frequencies(b)
+    H, Xn = P.reduce_frequencies(H)
     X = Xn.astype(np.float64) / P.m
     Z = alias_offsets(kind, params, P.d)
     MT = np.array(P.MT, dtype=np.int64)
@@ -273,6 +279,13 @@ def gamma_periodised(P: Pattern, C0_voigt, kind, params=None, b=None, chunk=4096
     zero = np.all(H == 0, axis=1)
     out[zero] = 0.0
     return out, den_all
+
+
+def gamma_symmetrised_at(P: Pattern, C0_voigt, kind, params, H):
+    """(Gamma^p_h + Gamma^p_{-h}) / 2 at integer frequencies H (see gamma_symmetrised)."""
+    Gp, d1 = gamma_at_frequencies(P, C0_voigt, kind, params, H)
+    Gm, d2 = gamma_at_frequencies(P, C0_voigt, kind, params, -np.asarray(H))
+    return 0.5 * (Gp + Gm), np.minimum(d1, d2)
 
 
 def gamma_symmetrised(P: Pattern, C0_voigt, kind, params=None):

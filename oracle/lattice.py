@@ -231,9 +231,15 @@ class Pattern:
             b = self.grid_indices()
         b = np.asarray(b, dtype=np.int64)
         VT = np.array(self.V, dtype=np.int64).T
-        h = b @ VT.T
+        return self.reduce_frequencies(b @ VT.T)
+
+    def reduce_frequencies(self, h):
+        """Vectorised reduce_frequency for integer frequencies h (n, d)."""
+        h = np.asarray(h, dtype=np.int64)
         A = self.sign * np.array(self.adjMT, dtype=object)
-        self._check_range(np.array(_matmul(A.tolist(), [list(r) for r in VT]), dtype=object), self.e)
+        bound = int(np.abs(h).max(initial=0)) * sum(abs(int(v)) for row in A.tolist() for v in row)
+        if bound >= 2 ** 62:
+            raise OverflowError("frequency too large for int64")
         xn = h @ np.array(A.tolist(), dtype=np.int64).T
         xr = _center_mod_np(xn, self.m)
         z = (xn - xr) // self.m

@@ -1,0 +1,191 @@
+// lsh_green.hpp -- the Green operator and the periodised Green operator on the GPU.
+//
+// Def. (projection), eq. (gamma): Gamma0_k tau = sym(k (x) K(k)^{-1} tau k),
+// K_im(k) = sum_jl C0_ijlm k_j k_l (the acoustic tensor), Gamma0_0 = 0.
+// Def. (gamma_tilde_fourier) with orthonormalised translates:
+//   Gamma^p_h = sum_z w(x+z) Gamma0_{h+M^T z} / sum_z w(x+z),  w = g^2, x = M^{-T} h,
+// where g is the generating function's weight (Sec. 2.2).  The solver applies
+// the Hermitian part (Gamma^p_h + Gamma^p_{-h})/2, which keeps real strain
+// fields real; it differs from Gamma^p only where the representative of -h is
+// not -h (the -1/2 faces of the cube) for the Dirichlet kernel and for the
+// truncated Box-spline sum.
+//
+// All of this runs in double precision.  Matrices are 6x6 symmetric in Mandel
+// form, stored as the 21-entry upper triangle row by row.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define LSH_MAX_XI 16
+
+struct GreenParams {
+  int kind;          // lsh_kernel
+  int nxi;           // Box spline: number of directions
+  int R;             // Box spline: alias box [-R, R]^3
+  int pad_;
+  int64_t m;         // |det M|
+  int64_t e[3];      // SNF diagonal
+  int64_t VT[9];     // h = V^T b
+  int64_t A[9];      // sign(det M) adj(M^T): m x = A h
+  int64_t MT[9];     // M^T
+  double alpha[3];   // dlVP
+  double Xi[3 * LSH_MAX_XI];  // Box directions, column s at Xi[3 s + i]
+  double C0[81];     // C0_ijkl
+};
+
+// upper-triangle index of (I, J), I <= J, 6x6
+__host__ __device__ constexpr int tri_idx(int I, int J) { return I * 6 - (I * (I - 1)) / 2 + (J - I); }
+
+__device__ __forceinline__ int64_t center_mod(int64_t v, int64_t m) {
+  const int64_t h = m / 2;
+  int64_t r = (v + h) % m;
+  if (r < 0) r += m;
+  return r - h;
+}
+
+// Reduce h into G(M^T): returns h_rep and x_num (x = x_num / m in [-1/2,1/2)^3).
+__device__ __forceinline__ void reduce_freq(const GreenParams& gp, const int64_t h[3], int64_t hr[3],
+                                            int64_t xn[3]) {
+  int64_t z[3];
+  for (int i = 0; i < 3; ++i) {
+    const int64_t v = gp.A[3 * i] * h[0] + gp.A[3 * i + 1] * h[1] + gp.A[3 * i + 2] * h[2];
+    xn[i] = center_mod(v, gp.m);
+    z[i] = (v - xn[i]) / gp.m;
+  }
+  for (int i = 0; i < 3; ++i) hr[i] = h[i] - (gp.MT[3 * i] * z[0] + gp.MT[3 * i + 1] * z[1] + gp.MT[3 * i + 2] * z[2]);
+}
+
+// Mandel index pairs (11,22,33,23,13,12)
+__device__ __forceinline__ void mandel_pair(int I, int& a, int& b) {
+  const int A_[6] = {0, 1, 2, 1, 0, 0};
+  const int B_[6] = {0, 1, 2, 2, 2, 1};
+  a = A_[I];
+  b = B_[I];
+}
+
+// acc += w * Gamma0_k (21 entries).  k need not be normalised.
+__device__ inline void add_gamma0(const GreenParams& gp, const double k[3], double w, double acc[21]) {
+  double K[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int mm = 0; mm < 3; ++mm) {
+      double s = 0.0;
+      for (int j = 0; j < 3; ++j)
+        for (int l = 0; l < 3; ++l) s += gp.C0[((i * 3 + j) * 3 + l) * 3 + mm] * k[j] * k[l];
+      K[i][mm] = s;
+    }
+  // N = K^{-1} (K symmetric positive definite for k != 0 and elliptic C0)
+  const double c00 = K[1][1] * K[2][2] - K[1][2] * K[2][1];
+  const double c01 = K[1][2] * K[2][0] - K[1][0] * K[2][2];
+  const double c02 = K[1][0] * K[2][1] - K[1][1] * K[2][0];
+  const double det = K[0][0] * c00 + K[0][1] * c01 + K[0][2] * c02;
+  const double id = 1.0 / det;
+  double N[3][3];
+  N[0][0] = c00 * id;
+  N[1][0] = c01 * id;
+  N[2][0] = c02 * id;
+  N[0][1] = (K[0][2] * K[2][1] - K[0][1] * K[2][2]) * id;
+  N[1][1] = (K[0][0] * K[2][2] - K[0][2] * K[2][0]) * id;
+  N[2][1] = (K[0][1] * K[2][0] - K[0][0] * K[2][1]) * id;
+  N[0][2] = (K[0][1] * K[1][2] - K[0][2] * K[1][1]) * id;
+  N[1][2] = (K[0][2] * K[1][0] - K[0][0] * K[1][2]) * id;
+  N[2][2] = (K[0][0] * K[1][1] - K[0][1] * K[1][0]) * id;
+  const double SQ2 = 1.41421356237309504880168872420969808;
+  int t = 0;
+  for (int I = 0; I < 6; ++I) {
+    int a, b;
+    mandel_pair(I, a, b);
+    const double cI = I < 3 ? 1.0 : SQ2;
+    for (int J = I; J < 6; ++J, ++t) {
+      int c, d;
+      mandel_pair(J, c, d);
+      const double cJ = J < 3 ? 1.0 : SQ2;
+      const double G = 0.25 * (k[a] * N[b][c] * k[d] + k[b] * N[a][c] * k[d] + k[a] * N[b][d] * k[c] +
+                               k[b] * N[a][d] * k[c]);
+      acc[t] += w * cI * cJ * G;
+    }
+  }
+}
+
+__device__ __forceinline__ double trap_weight(double t, double a) {
+  t = fabs(t);
+  if (a <= 0.0) return t < 0.5 ? 1.0 : (t == 0.5 ? 0.5 : 0.0);
+  double v = ((1.0 + a) * 0.5 - t) / a;
+  return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+}
+
+// g(x)^2 for the analytic kernels and the Box spline
+__device__ inline double kernel_weight(const GreenParams& gp, const double x[3]) {
+  if (gp.kind == 0) {  // Dirichlet
+    return (x[0] >= -0.5 && x[0] < 0.5 && x[1] >= -0.5 && x[1] < 0.5 && x[2] >= -0.5 && x[2] < 0.5) ? 1.0 : 0.0;
+  }
+  if (gp.kind == 1 || gp.kind == 2) {
+    double g = 1.0;
+    for (int i = 0; i < 3; ++i) g *= trap_weight(x[i], gp.kind == 1 ? 0.0 : gp.alpha[i]);
+    return g * g;
+  }
+  // Box spline: prod sinc(pi xi^T x), sinc t = sin t / t
+  double g = 1.0;
+  for (int s = 0; s < gp.nxi; ++s) {
+    const double u = gp.Xi[3 * s] * x[0] + gp.Xi[3 * s + 1] * x[1] + gp.Xi[3 * s + 2] * x[2];
+    if (u != 0.0) g *= sinpi(u) / (3.14159265358979323846264338327950288 * u);
+  }
+  return g * g;
+}
+
+// Weighted alias sum for the representative h_rep (x_num its M^{-T} numerator):
+// acc = sum_z w Gamma0, returns sum_z w.  z over {-1,0,1}^3 (modified
+// Dirichlet, dlVP), {0} (Dirichlet) or [-R,R]^3 (Box).
+__device__ inline double alias_sum(const GreenParams& gp, const int64_t hr[3], const int64_t xn[3], double acc[21]) {
+  for (int t = 0; t < 21; ++t) acc[t] = 0.0;
+  const double invm = 1.0 / (double)gp.m;
+  const double x0[3] = {(double)xn[0] * invm, (double)xn[1] * invm, (double)xn[2] * invm};
+  int r = 0;
+  if (gp.kind == 1 || gp.kind == 2) r = 1;
+  if (gp.kind == 3) r = gp.R;
+  double den = 0.0;
+  for (int z0 = -r; z0 <= r; ++z0)
+    for (int z1 = -r; z1 <= r; ++z1)
+      for (int z2 = -r; z2 <= r; ++z2) {
+        const double x[3] = {x0[0] + z0, x0[1] + z1, x0[2] + z2};
+        const double w = kernel_weight(gp, x);
+        if (w <= 0.0) continue;
+        const int64_t kk[3] = {hr[0] + gp.MT[0] * z0 + gp.MT[1] * z1 + gp.MT[2] * z2,
+                               hr[1] + gp.MT[3] * z0 + gp.MT[4] * z1 + gp.MT[5] * z2,
+                               hr[2] + gp.MT[6] * z0 + gp.MT[7] * z1 + gp.MT[8] * z2};
+        den += w;
+        if (kk[0] == 0 && kk[1] == 0 && kk[2] == 0) continue;  // Gamma0_0 = 0
+        const double kd[3] = {(double)kk[0], (double)kk[1], (double)kk[2]};
+        add_gamma0(gp, kd, w, acc);
+      }
+  return den;
+}
+
+// Hermitian-symmetrised Gamma^p at SNF bin b (b1 may be any index mod e1).
+// Returns the bracket sum of the weights at b (0 => translates degenerate).
+__device__ inline double gamma_sym_at(const GreenParams& gp, int64_t b0, int64_t b1, int64_t b2, double G[21]) {
+  const int64_t b[3] = {b0, b1, b2};
+  int64_t h[3];
+  for (int i = 0; i < 3; ++i) h[i] = gp.VT[3 * i] * b[0] + gp.VT[3 * i + 1] * b[1] + gp.VT[3 * i + 2] * b[2];
+  int64_t hr[3], xn[3];
+  reduce_freq(gp, h, hr, xn);
+  if (hr[0] == 0 && hr[1] == 0 && hr[2] == 0) {
+    for (int t = 0; t < 21; ++t) G[t] = 0.0;
+    return 1.0;
+  }
+  const bool face = (2 * xn[0] == -gp.m) || (2 * xn[1] == -gp.m) || (2 * xn[2] == -gp.m);
+  const double den = alias_sum(gp, hr, xn, G);
+  for (int t = 0; t < 21; ++t) G[t] /= den;
+  // the even kernels on the faces of the modified Dirichlet / dlVP family are
+  // already symmetric (their alias set is mirrored); Dirichlet and the
+  // truncated Box sum are not.
+  if (face && (gp.kind == 0 || gp.kind == 3)) {
+    const int64_t hm[3] = {-hr[0], -hr[1], -hr[2]};
+    int64_t hr2[3], xn2[3];
+    reduce_freq(gp, hm, hr2, xn2);
+    double G2[21];
+    const double den2 = alias_sum(gp, hr2, xn2, G2);
+    for (int t = 0; t < 21; ++t) G[t] = 0.5 * (G[t] + G2[t] / den2);
+    return den < den2 ? den : den2;
+  }
+  return den;
+}

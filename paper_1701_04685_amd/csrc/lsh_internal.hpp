@@ -1,0 +1,50 @@
+// lsh_internal.hpp -- host-side pattern object shared by the library's sources.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "lsh.h"
+#include "lsh_fft.hpp"
+#include "lsh_green.hpp"
+
+struct lsh_pattern {
+  // ---- Sec. 2.1: M, m, SNF M = U diag(e) V
+  int64_t M[9];
+  int64_t det;
+  int64_t m;
+  int64_t U[9], V[9];
+  int64_t e[3];
+  int64_t adjM[9];   // adj(M): M^{-1} = adj(M) / det
+  FftPlan plan[3];   // radix plans per SNF axis (nst = -1 if unsupported)
+
+  // ---- Sec. 2.2: generating function
+  int kind = -1;
+  double alpha[3] = {0, 0, 0};
+  int nxi = 0;
+  double Xi[3 * LSH_MAX_XI];
+  int R = 16;
+
+  // ---- Def. (weak_pde): stiffness field
+  int nphase = 0;
+  std::vector<double> C_voigt;   // nphase * 36
+  double C0_voigt[36];
+  std::vector<uint8_t> phase;    // m, storage order
+
+  // ---- device binding (one precision at a time)
+  int bound_prec = -1;
+  char* dev_persist = nullptr;
+  size_t off_phase = 0, off_tw[3] = {0, 0, 0}, off_table = 0, off_dmat = 0, off_cmat = 0;
+  bool has_table = false;
+};
+
+// ---- helpers implemented in lsh_host.cpp
+void lsh_set_error(const std::string& msg);
+int lsh_fail(int status, const std::string& msg);
+void lsh_green_params(const lsh_pattern* p, GreenParams* gp);
+bool lsh_make_plan(int64_t N, FftPlan* pl);
+void lsh_voigt_to_mandel(const double* Cv, double* Cm);
+void lsh_voigt_to_tensor(const double* Cv, double* C4);
+size_t lsh_align(size_t x);

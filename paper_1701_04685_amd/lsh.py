@@ -1,0 +1,238 @@
+"""ctypes binding of liblsh.so (declared in include/lsh.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  Device memory comes from torch (``torch.empty(..., device='cuda')``)
+and work is queued on torch's current stream.  Importing this module fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblsh.so")
+
+DIRICHLET, DIRICHLET_MODIFIED, DLVP, BOXSPLINE = 0, 1, 2, 3
+FP64, FP32_MIXED = 0, 1
+KINDS = {"dirichlet": DIRICHLET, "dirichlet_modified": DIRICHLET_MODIFIED, "dlvp": DLVP, "box": BOXSPLINE}
+PRECISIONS = {"fp64": FP64, "fp32": FP32_MIXED}
+
+STATUS = {0: "LSH_OK", -1: "LSH_EINVAL", -2: "LSH_ESINGULAR", -3: "LSH_ENOINTERP", -4: "LSH_ENOTELLIPTIC",
+          -5: "LSH_ENOTCONVERGED", -6: "LSH_ENONFINITE", -7: "LSH_EDEVICE", -8: "LSH_EWORKSPACE",
+          -9: "LSH_EUNSUPPORTED", -10: "LSH_ESTATE"}
+
+EXPORTS = ["lsh_create_pattern", "lsh_destroy", "lsh_pattern_info", "lsh_pattern_snf", "lsh_pattern_points",
+           "lsh_set_kernel", "lsh_set_stiffness", "lsh_persistent_bytes", "lsh_bind", "lsh_gamma_probe",
+           "lsh_solve_bytes", "lsh_solve", "lsh_profile_enable", "lsh_profile_read", "lsh_last_error"]
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+
+# torch first: its HIP runtime (SONAME libamdhip64.so.7) then satisfies the
+# library's dependency, so the process holds a single HIP runtime.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+_sig = {
+    "lsh_create_pattern": ([ctypes.c_int, _I64P, ctypes.POINTER(_P)], ctypes.c_int),
+    "lsh_destroy": ([_P], None),
+    "lsh_pattern_info": ([_P, _I64P, _I64P], ctypes.c_int),
+    "lsh_pattern_snf": ([_P, _I64P, _I64P], ctypes.c_int),
+    "lsh_pattern_points": ([_P, _I64P], ctypes.c_int),
+    "lsh_set_kernel": ([_P, ctypes.c_int, _DP, ctypes.c_int], ctypes.c_int),
+    "lsh_set_stiffness": ([_P, ctypes.c_int, _DP, _DP, ctypes.POINTER(ctypes.c_uint8)], ctypes.c_int),
+    "lsh_persistent_bytes": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "lsh_bind": ([_P, ctypes.c_int, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "lsh_gamma_probe": ([_P, ctypes.c_int, _I64P, ctypes.c_int, _DP, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "lsh_solve_bytes": ([_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "lsh_solve": ([_P, ctypes.c_int, _DP, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t, _P,
+                   _P, _P, _DP, ctypes.POINTER(Stats), _DP], ctypes.c_int),
+    "lsh_profile_enable": ([ctypes.c_int], ctypes.c_int),
+    "lsh_profile_read": ([_DP, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int], ctypes.c_int),
+    "lsh_last_error": ([], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class LshError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(rc, allow=()):
+    if rc != 0 and rc not in allow:
+        raise LshError(rc, _lib.lsh_last_error().decode())
+    return rc
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_DP)
+
+
+def exported_symbols():
+    """Names of the C-ABI entry points this binding resolves."""
+    return [n for n in EXPORTS if hasattr(_lib, n)]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _device_bytes(n):
+    torch = _torch()
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device="cuda")
+
+
+class Pattern:
+    """A pattern P(M) with its generating function, stiffness and device data."""
+
+    def __init__(self, M):
+        M = np.ascontiguousarray(np.asarray(M, dtype=np.int64).reshape(3, 3))
+        h = _P()
+        _check(_lib.lsh_create_pattern(3, M.ctypes.data_as(_I64P), ctypes.byref(h)))
+        self._h = h
+        m = ctypes.c_int64()
+        e = np.zeros(3, dtype=np.int64)
+        _check(_lib.lsh_pattern_info(h, ctypes.byref(m), e.ctypes.data_as(_I64P)))
+        self.m = int(m.value)
+        self.e = tuple(int(v) for v in e)
+        self._persist = None
+        self._prec = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.lsh_destroy(h)
+            self._h = None
+
+    def snf(self):
+        U = np.zeros(9, dtype=np.int64)
+        V = np.zeros(9, dtype=np.int64)
+        _check(_lib.lsh_pattern_snf(self._h, U.ctypes.data_as(_I64P), V.ctypes.data_as(_I64P)))
+        return U.reshape(3, 3), V.reshape(3, 3)
+
+    def point_numerators(self):
+        y = np.zeros((self.m, 3), dtype=np.int64)
+        _check(_lib.lsh_pattern_points(self._h, y.ctypes.data_as(_I64P)))
+        return y
+
+    def points(self):
+        return self.point_numerators().astype(np.float64) / self.m
+
+    def set_kernel(self, kind, params=None):
+        k = KINDS[kind] if isinstance(kind, str) else int(kind)
+        if k == BOXSPLINE and isinstance(params, dict):
+            Xi = np.asarray(params["Xi"], dtype=np.float64)
+            flat = [float(Xi.shape[1])] + list(Xi.reshape(-1)) + [float(params.get("R", 16))]
+        elif k == DLVP and isinstance(params, dict):
+            flat = list(np.asarray(params["alpha"], dtype=np.float64))
+        else:
+            flat = [] if params is None else list(np.asarray(params, dtype=np.float64).reshape(-1))
+        arr = np.ascontiguousarray(flat, dtype=np.float64)
+        _check(_lib.lsh_set_kernel(self._h, k, _dptr(arr) if len(arr) else None, len(arr)))
+        self._prec = None
+
+    def set_stiffness(self, C_phases_voigt, C0_voigt, phase):
+        C = np.ascontiguousarray(np.asarray(C_phases_voigt, dtype=np.float64).reshape(-1, 6, 6))
+        C0 = np.ascontiguousarray(np.asarray(C0_voigt, dtype=np.float64).reshape(6, 6))
+        ph = np.ascontiguousarray(np.asarray(phase, dtype=np.uint8).reshape(-1))
+        if ph.size != self.m:
+            raise ValueError("phase map must have m entries")
+        _check(_lib.lsh_set_stiffness(self._h, C.shape[0], _dptr(C), _dptr(C0),
+                                      ph.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        self._prec = None
+
+    def bind(self, precision="fp64"):
+        p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        n = ctypes.c_size_t()
+        _check(_lib.lsh_persistent_bytes(self._h, p, ctypes.byref(n)))
+        buf = _device_bytes(n.value)
+        _check(_lib.lsh_bind(self._h, p, ctypes.c_void_p(buf.data_ptr()), n.value, _stream()))
+        self._persist = buf
+        self._prec = p
+        return n.value
+
+    def gamma_probe(self, bins):
+        bins = np.ascontiguousarray(np.asarray(bins, dtype=np.int64).reshape(-1, 3))
+        n = len(bins)
+        out = np.zeros((n, 21), dtype=np.float64)
+        scratch = _device_bytes(256 + 24 * n + 256 + 168 * n + 512)
+        _check(_lib.lsh_gamma_probe(self._h, self._prec, bins.ctypes.data_as(_I64P), n, _dptr(out),
+                                    ctypes.c_void_p(scratch.data_ptr()), scratch.numel(), _stream()))
+        return out
+
+    def workspace_bytes(self, nload, precision=None):
+        p = self._prec if precision is None else (PRECISIONS[precision] if isinstance(precision, str) else precision)
+        n = ctypes.c_size_t()
+        _check(_lib.lsh_solve_bytes(self._h, int(nload), p, ctypes.byref(n)))
+        return n.value
+
+    def solve(self, eps0_voigt, tol=1e-10, max_iter=1000, E_init=None, return_E=False, history=False,
+              workspace=None, allow_notconverged=False):
+        """Basic Scheme for all load cases (rows of eps0_voigt)."""
+        torch = _torch()
+        eps = np.ascontiguousarray(np.asarray(eps0_voigt, dtype=np.float64).reshape(-1, 6))
+        nload = eps.shape[0]
+        if self._prec is None:
+            raise RuntimeError("call bind() first")
+        need = self.workspace_bytes(nload)
+        ws = workspace if workspace is not None and workspace.numel() >= need else _device_bytes(need)
+        Eout = torch.empty((nload, 6, self.m), dtype=torch.float64, device="cuda") if return_E else None
+        if E_init is not None:
+            if E_init.dtype != torch.float64 or not E_init.is_cuda or E_init.numel() != nload * 6 * self.m:
+                raise ValueError("E_init must be a cuda float64 tensor with nload*6*m entries")
+            E_init = E_init.contiguous()
+        sig = np.zeros((nload, 6), dtype=np.float64)
+        stats = (Stats * nload)()
+        hist = np.full((nload, max_iter), np.nan) if history else None
+        rc = _lib.lsh_solve(self._h, nload, _dptr(eps), float(tol), int(max_iter), self._prec,
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(),
+                            ctypes.c_void_p(E_init.data_ptr()) if E_init is not None else None,
+                            ctypes.c_void_p(Eout.data_ptr()) if Eout is not None else None,
+                            _dptr(sig), stats, _dptr(hist) if hist is not None else None)
+        _check(rc, allow=(-5,) if allow_notconverged else ())
+        out = dict(sigma=sig, status=rc,
+                   iterations=np.array([s.iterations for s in stats]),
+                   converged=np.array([bool(s.converged) for s in stats]),
+                   residual=np.array([s.residual for s in stats]),
+                   seconds=stats[0].seconds)
+        if return_E:
+            out["E"] = Eout
+        if history:
+            out["history"] = hist
+        return out
+
+
+def profile_enable(on=True):
+    _check(_lib.lsh_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    ms = np.zeros(8)
+    cnt = np.zeros(8, dtype=np.int64)
+    _check(_lib.lsh_profile_read(_dptr(ms), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), 8))
+    return ms, cnt

@@ -1,0 +1,116 @@
+"""C-ABI library: loads, exports every declared symbol, host-side entry points.
+
+No GPU work here: only the host half of the library (patterns, SNF, kernel and
+stiffness validation) is called.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.lattice import Pattern as OPattern
+import lsh_inputs as li
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(lsh_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    import ctypes
+    so = ctypes.CDLL(lib.LIB_PATH)
+    missing = [n for n in declared_symbols() if not hasattr(so, n)]
+    assert declared_symbols(), "no declarations found"
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("M", [
+    [[16, 0, 0], [0, 16, 0], [0, 0, 16]],
+    [[128, 32, 0], [0, 128, 0], [0, 0, 64]],
+    [[8, 2, 0], [0, 8, 0], [0, 0, 4]],
+    [[4, 1, 0], [0, 4, 0], [0, 0, 2]],
+    [[3, 1, 0], [-1, 2, 1], [0, 1, 4]],
+    [[-2, 1, 1], [1, -3, 0], [0, 2, 5]],
+    [[5, 0, 0], [0, 5, 0], [0, 0, 7]],
+    [[6, -3, 2], [1, 4, 0], [2, 0, 3]],
+])
+def test_pattern_matches_oracle(lib, M):
+    """SNF diagonal equal; same point set exactly; U diag(e) V == M."""
+    P = lib.Pattern(M)
+    O = OPattern(M)
+    assert list(P.e) == list(O.e)
+    assert P.m == O.m
+    U, V = P.snf()
+    np.testing.assert_array_equal(U @ np.diag(P.e) @ V, np.array(M))
+    assert abs(round(np.linalg.det(U))) == 1 and abs(round(np.linalg.det(V))) == 1
+    if P.m <= 300000:
+        a = sorted(map(tuple, P.point_numerators().tolist()))
+        b = sorted(map(tuple, O.point_numerators().tolist()))
+        assert a == b
+
+
+def test_pattern_point_map_is_snf_map(lib):
+    """y(a) = M^{-1} U a mod 1 in storage order, with the library's own U."""
+    M = np.array([[6, -3, 2], [1, 4, 0], [2, 0, 3]])
+    P = lib.Pattern(M)
+    U, _ = P.snf()
+    a = np.array(np.meshgrid(*[np.arange(k) for k in P.e], indexing="ij")).reshape(3, -1).T
+    y = (np.linalg.inv(M) @ U @ a.T).T
+    y = y - np.floor(y + 0.5)
+    np.testing.assert_allclose(P.points(), y, atol=1e-12)
+
+
+def test_errors_host_side(lib):
+    with pytest.raises(lib.LshError) as e:
+        lib.Pattern([[2, 4, 0], [1, 2, 0], [0, 0, 1]])
+    assert e.value.status == -2  # LSH_ESINGULAR
+    P = lib.Pattern(np.diag([4, 4, 4]))
+    with pytest.raises(lib.LshError) as e:
+        P.set_kernel("dlvp", {"alpha": [0.5, 1.5, 0.5]})
+    assert e.value.status == -1
+    with pytest.raises(lib.LshError) as e:
+        P.set_kernel("box", {"Xi": np.array([[1.0, 1.0, 0.0], [0.0, 0.0, 0.0], [0.0, 0.0, 1.0]])})
+    assert e.value.status == -1  # directions do not span R^3
+    C = li.isotropic_voigt(1.0, 0.3)
+    bad = C.copy()
+    bad[0, 0] = -1.0
+    with pytest.raises(lib.LshError) as e:
+        P.set_stiffness(np.stack([C, bad]), C, np.zeros(64, np.uint8))
+    assert e.value.status == -4  # LSH_ENOTELLIPTIC
+    nan = C.copy()
+    nan[1, 2] = np.nan
+    with pytest.raises(lib.LshError) as e:
+        P.set_stiffness(np.stack([C, nan]), C, np.zeros(64, np.uint8))
+    assert e.value.status == -1
+    with pytest.raises(lib.LshError) as e:
+        P.set_stiffness(np.stack([C]), C, np.full(64, 3, np.uint8))
+    assert e.value.status == -1  # phase index out of range
+    with pytest.raises(lib.LshError) as e:
+        P.workspace_bytes(2, "fp64") if False else lib._check(lib._lib.lsh_solve_bytes(P._h, 0, 0, None))
+    assert e.value.status == -1
+
+
+def test_unsupported_prime_factor_reported(lib):
+    """A prime SNF factor above 13 is refused with LSH_EUNSUPPORTED (host check)."""
+    P = lib.Pattern(np.diag([1, 1, 17]))
+    with pytest.raises(lib.LshError) as e:
+        P.workspace_bytes(1, "fp64")
+    assert e.value.status == -9
+
+
+def test_workspace_sizes_scale(lib):
+    P = lib.Pattern(np.diag([16, 16, 16]))
+    P.set_kernel("dirichlet")
+    b1 = P.workspace_bytes(1, "fp64")
+    b6 = P.workspace_bytes(6, "fp64")
+    f1 = P.workspace_bytes(1, "fp32")
+    assert b6 > 5 * b1 * 0.9 and f1 < b1
