@@ -224,3 +224,88 @@ __device__ void fft_lines(typename cpx<T>::t* buf, const FftPlan& pl, int L, int
     Ns *= R;
   }
 }
+
+// ------------------------------------------------- compile-time line FFT ---
+// The same Stockham stages with the length, line count, layout and block size
+// known at compile time: every index is a constant expression and each
+// thread's butterflies are unrolled into registers.
+struct RadList {
+  int n;
+  int r[LSH_MAX_STAGES];
+};
+
+__host__ __device__ constexpr RadList make_radlist(int N) {
+  RadList L{0, {}};
+  const int rads[8] = {8, 4, 2, 3, 5, 7, 11, 13};
+  for (int i = 0; i < 8; ++i)
+    while (N > 1 && N % rads[i] == 0 && L.n < LSH_MAX_STAGES) {
+      L.r[L.n++] = rads[i];
+      N /= rads[i];
+    }
+  return L;
+}
+
+template <typename T, int DIR, int N, int L, bool LF, int NT, int R, int NS>
+__device__ __forceinline__ void fft_stage_static(typename cpx<T>::t* buf, int ls, int es,
+                                                 const typename cpx<T>::t* __restrict__ tw) {
+  using T2 = typename cpx<T>::t;
+  constexpr int nbl = N / R;
+  constexpr int nb = nbl * L;
+  constexpr int NB = (nb + NT - 1) / NT;
+  constexpr int tstep = N / (NS * R);
+  const int tid = threadIdx.x;
+  T2 v[NB][R];
+  int dst[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int b = tid + q * NT;
+    dst[q] = -1;
+    if (nb % NT == 0 || b < nb) {
+      const int l = LF ? (b % L) : (b / nbl);
+      const int j = LF ? (b / L) : (b % nbl);
+      const T2* src = buf + l * ls;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[(j + r * nbl) * es];
+      const int k = j % NS;
+      if (NS > 1 && k != 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          T2 w = tw[r * tstep * k];
+          if (DIR > 0) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+      Bfly<T, DIR, R>::run(v[q]);
+      dst[q] = l * ls + ((j - k) * R + k) * es;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+    if (nb % NT == 0 || dst[q] >= 0)
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[dst[q] + r * NS * es] = v[q][r];
+  __syncthreads();
+}
+
+template <typename T, int DIR, int N, int L, bool LF, int NT, int S = 0, int NS = 1>
+__device__ __forceinline__ void fft_static(typename cpx<T>::t* buf, int ls, int es,
+                                           const typename cpx<T>::t* __restrict__ tw) {
+  constexpr RadList RL = make_radlist(N);
+  if constexpr (S < RL.n) {
+    constexpr int R = RL.r[S];
+    fft_stage_static<T, DIR, N, L, LF, NT, R, NS>(buf, ls, es, tw);
+    fft_static<T, DIR, N, L, LF, NT, S + 1, NS * R>(buf, ls, es, tw);
+  }
+}
+
+// Dispatch: NC > 0 uses the compile-time path, NC == 0 the runtime plan.
+template <typename T, int DIR, int NC, int L, bool LF, int NT>
+__device__ __forceinline__ void fft_any(typename cpx<T>::t* buf, const FftPlan& pl, int ls, int es,
+                                        const typename cpx<T>::t* __restrict__ tw) {
+  if constexpr (NC > 0) {
+    fft_static<T, DIR, NC, L, LF, NT>(buf, ls, es, tw);
+  } else {
+    fft_lines<T, DIR, 16>(buf, pl, L, ls, es, LF, tw);
+  }
+}

@@ -36,10 +36,16 @@ struct GreenParams {
 // upper-triangle index of (I, J), I <= J, 6x6
 __host__ __device__ constexpr int tri_idx(int I, int J) { return I * 6 - (I * (I - 1)) / 2 + (J - I); }
 
+// Representative of v mod m in [-m/2, m/2) (the half-open cube rule).  The
+// quotient is estimated in double and corrected, which is exact for
+// |v| < 2^52 and avoids 64-bit integer division.
 __device__ __forceinline__ int64_t center_mod(int64_t v, int64_t m) {
   const int64_t h = m / 2;
-  int64_t r = (v + h) % m;
+  const int64_t u = v + h;
+  int64_t q = (int64_t)floor((double)u / (double)m);
+  int64_t r = u - q * m;
   if (r < 0) r += m;
+  if (r >= m) r -= m;
   return r - h;
 }
 
@@ -50,7 +56,8 @@ __device__ __forceinline__ void reduce_freq(const GreenParams& gp, const int64_t
   for (int i = 0; i < 3; ++i) {
     const int64_t v = gp.A[3 * i] * h[0] + gp.A[3 * i + 1] * h[1] + gp.A[3 * i + 2] * h[2];
     xn[i] = center_mod(v, gp.m);
-    z[i] = (v - xn[i]) / gp.m;
+    // (v - xn) is an exact multiple of m: the double quotient rounds to it
+    z[i] = (int64_t)rint((double)(v - xn[i]) / (double)gp.m);
   }
   for (int i = 0; i < 3; ++i) hr[i] = h[i] - (gp.MT[3 * i] * z[0] + gp.MT[3 * i + 1] * z[1] + gp.MT[3 * i + 2] * z[2]);
 }
@@ -188,4 +195,172 @@ __device__ inline double gamma_sym_at(const GreenParams& gp, int64_t b0, int64_t
     return den < den2 ? den : den2;
   }
   return den;
+}
+
+// ------------------------------------------------------ isotropic C0 path ---
+// For an isotropic reference stiffness (Lame lam0, mu0) the Green operator of
+// eq. (gamma) is Gamma0_k = S(n)/mu0 - r Q(n), n = k/|k|, r = (lam0+mu0)/(mu0(lam0+2mu0)),
+// with S(n): tau -> sym(n (x) tau n) and Q(n): tau -> (n.tau n) n (x) n.  Both
+// are linear in the moments n n^T and n n n n, so the weighted alias sum of
+// Def. (gamma_tilde_fourier) only needs the 6 second and 15 fourth moments of
+// the alias directions; the 6x6 matrix follows from them.
+struct IsoMoments {
+  double a[6];   // sum w n_i n_j, Mandel pair order (00,11,22,12,02,01)
+  double q[15];  // sum w n_i n_j n_k n_l, i<=j<=k<=l in lexicographic order
+  double w;      // sum w
+};
+
+__device__ __forceinline__ int q4_index(int i, int j, int k, int l) {
+  // sort (i,j,k,l) ascending, then rank among the 15 multisets of {0,1,2}
+  int s[4] = {i, j, k, l};
+  for (int x = 0; x < 3; ++x)
+    for (int y = 0; y < 3 - x; ++y)
+      if (s[y] > s[y + 1]) {
+        const int t = s[y];
+        s[y] = s[y + 1];
+        s[y + 1] = t;
+      }
+  // counts of 0s, 1s (the rest are 2s) determine the multiset
+  int c0 = 0, c1 = 0;
+  for (int x = 0; x < 4; ++x) {
+    c0 += s[x] == 0;
+    c1 += s[x] == 1;
+  }
+  // enumerate multisets in lexicographic order: c0 from 4 down to 0, then c1 down
+  int idx = 0;
+  for (int a = 4; a > c0; --a) idx += 4 - a + 1;
+  return idx + (4 - c0 - c1);
+}
+
+__device__ __forceinline__ void iso_add(IsoMoments& M, const double k[3], double w) {
+  const double inv = rsqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+  const double n0 = k[0] * inv, n1 = k[1] * inv, n2 = k[2] * inv;
+  const double p00 = n0 * n0, p11 = n1 * n1, p22 = n2 * n2, p12 = n1 * n2, p02 = n0 * n2, p01 = n0 * n1;
+  M.a[0] += w * p00;
+  M.a[1] += w * p11;
+  M.a[2] += w * p22;
+  M.a[3] += w * p12;
+  M.a[4] += w * p02;
+  M.a[5] += w * p01;
+  // 4th moments in the q4_index order: c0 = 4,3,2,1,0 blocks
+  M.q[0] += w * p00 * p00;   // 0000
+  M.q[1] += w * p00 * p01;   // 0001
+  M.q[2] += w * p00 * p02;   // 0002
+  M.q[3] += w * p00 * p11;   // 0011
+  M.q[4] += w * p00 * p12;   // 0012
+  M.q[5] += w * p00 * p22;   // 0022
+  M.q[6] += w * p01 * p11;   // 0111
+  M.q[7] += w * p01 * p12;   // 0112
+  M.q[8] += w * p01 * p22;   // 0122
+  M.q[9] += w * p02 * p22;   // 0222
+  M.q[10] += w * p11 * p11;  // 1111
+  M.q[11] += w * p11 * p12;  // 1112
+  M.q[12] += w * p11 * p22;  // 1122
+  M.q[13] += w * p12 * p22;  // 1222
+  M.q[14] += w * p22 * p22;  // 2222
+  M.w += w;
+}
+
+// 21-entry Mandel matrix from normalised moments
+__device__ inline void iso_matrix(const IsoMoments& M, double mu0, double r, double G[21]) {
+  const double SQ2 = 1.41421356237309504880168872420969808;
+  const double iw = 1.0 / M.w;
+  double A[3][3];
+  A[0][0] = M.a[0] * iw;
+  A[1][1] = M.a[1] * iw;
+  A[2][2] = M.a[2] * iw;
+  A[1][2] = A[2][1] = M.a[3] * iw;
+  A[0][2] = A[2][0] = M.a[4] * iw;
+  A[0][1] = A[1][0] = M.a[5] * iw;
+  const double imu = 1.0 / mu0;
+#pragma unroll
+  for (int I = 0; I < 6; ++I) {
+    int a, b;
+    mandel_pair(I, a, b);
+    const double cI = I < 3 ? 1.0 : SQ2;
+#pragma unroll
+    for (int J = I; J < 6; ++J) {
+      const int t = tri_idx(I, J);
+      int c, d;
+      mandel_pair(J, c, d);
+      const double cJ = J < 3 ? 1.0 : SQ2;
+      const double S = 0.25 * ((b == c) * A[a][d] + (b == d) * A[a][c] + (a == c) * A[b][d] + (a == d) * A[b][c]);
+      const double Q = M.q[q4_index(a, b, c, d)] * iw;
+      G[t] = cI * cJ * (imu * S - r * Q);
+    }
+  }
+}
+
+// Isotropic version of gamma_sym_at for the analytic kernels (Dirichlet,
+// modified Dirichlet, dlVP): same alias sets and symmetrisation.
+__device__ inline void gamma_sym_iso(const GreenParams& gp, double mu0, double r, int64_t b0, int64_t b1, int64_t b2,
+                                     double G[21]) {
+  const int64_t b[3] = {b0, b1, b2};
+  int64_t h[3];
+  for (int i = 0; i < 3; ++i) h[i] = gp.VT[3 * i] * b[0] + gp.VT[3 * i + 1] * b[1] + gp.VT[3 * i + 2] * b[2];
+  int64_t hr[3], xn[3];
+  reduce_freq(gp, h, hr, xn);
+  if (hr[0] == 0 && hr[1] == 0 && hr[2] == 0) {
+    for (int t = 0; t < 21; ++t) G[t] = 0.0;
+    return;
+  }
+  IsoMoments M = {};
+  const double invm = 1.0 / (double)gp.m;
+  const bool face = (2 * xn[0] == -gp.m) || (2 * xn[1] == -gp.m) || (2 * xn[2] == -gp.m);
+  const int nrep = (face && gp.kind == 0) ? 2 : 1;
+  for (int rep = 0; rep < nrep; ++rep) {
+    int64_t hh[3] = {hr[0], hr[1], hr[2]}, xx[3] = {xn[0], xn[1], xn[2]};
+    if (rep == 1) {
+      const int64_t hm[3] = {-hr[0], -hr[1], -hr[2]};
+      reduce_freq(gp, hm, hh, xx);
+    }
+    const double x0[3] = {(double)xx[0] * invm, (double)xx[1] * invm, (double)xx[2] * invm};
+    // per axis: the offsets z_i in {0, +-1} whose weight is non-zero (the
+    // trapezoid of half-width (1+alpha)/2 reaches at most one neighbour)
+    int nz[3];
+    int zz[3][2];
+    double wz[3][2];
+    for (int i = 0; i < 3; ++i) {
+      nz[i] = 1;
+      zz[i][0] = 0;
+      if (gp.kind == 0) {
+        wz[i][0] = 1.0;
+        continue;
+      }
+      const double a = gp.kind == 1 ? 0.0 : gp.alpha[i];
+      const double g0 = trap_weight(x0[i], a);
+      wz[i][0] = g0;
+      const int s = x0[i] < 0.0 ? 1 : -1;
+      const double g1 = trap_weight(x0[i] + s, a);
+      if (g1 > 0.0) {
+        zz[i][1] = s;
+        wz[i][1] = g1;
+        nz[i] = 2;
+      }
+    }
+    IsoMoments Mr = {};
+    for (int i0 = 0; i0 < nz[0]; ++i0)
+      for (int i1 = 0; i1 < nz[1]; ++i1)
+        for (int i2 = 0; i2 < nz[2]; ++i2) {
+          const double g = wz[0][i0] * wz[1][i1] * wz[2][i2];
+          const double w = g * g;
+          if (w <= 0.0) continue;
+          const int z0 = zz[0][i0], z1 = zz[1][i1], z2 = zz[2][i2];
+          const int64_t kk[3] = {hh[0] + gp.MT[0] * z0 + gp.MT[1] * z1 + gp.MT[2] * z2,
+                                 hh[1] + gp.MT[3] * z0 + gp.MT[4] * z1 + gp.MT[5] * z2,
+                                 hh[2] + gp.MT[6] * z0 + gp.MT[7] * z1 + gp.MT[8] * z2};
+          if (kk[0] == 0 && kk[1] == 0 && kk[2] == 0) {
+            Mr.w += w;
+            continue;
+          }
+          const double kd[3] = {(double)kk[0], (double)kk[1], (double)kk[2]};
+          iso_add(Mr, kd, w);
+        }
+    // each representative's sum is normalised by its own weight, then averaged
+    const double f = 1.0 / (Mr.w * nrep);
+    for (int i = 0; i < 6; ++i) M.a[i] += Mr.a[i] * f;
+    for (int i = 0; i < 15; ++i) M.q[i] += Mr.q[i] * f;
+  }
+  M.w = 1.0;
+  iso_matrix(M, mu0, r, G);
 }

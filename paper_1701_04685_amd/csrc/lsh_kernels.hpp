@@ -1,0 +1,537 @@
+// lsh_kernels.hpp -- the Basic Scheme's device kernels for gfx950.
+//
+// Thm. (pde_discretization), eq. (pde_coefficients): E = -Gamma^p[(C - C0):(E + eps0)]
+// on P(M), iterated as in Sec. 4.  In the SNF ordering the pattern DFT of
+// eq. (Fouriermatrix) is a 3-D DFT over Z_n1 x Z_n2 x Z_n3.  The state is kept
+// partially transformed so that every pass is a bundle of 1-D line FFTs held
+// in LDS:
+//
+//   layout     [load][comp][k1 < n1/2+1][i2 < n2][i3 < n3]  complex, R2C along axis 1
+//   S  axis 1  X = D1[E]/n1 --C2R--> E(y) --(C-C0):(E+eps0)--> tau(y) --R2C--> D1[tau]
+//   B  axis 2  D1[tau] --FFT--> D12[tau]
+//   G  axis 3  --FFT--> tau_hat --(-Gamma^p/m)--> E_hat --IFFT--> P = D12[E]/(n1 n2),
+//              Cauchy residual against the previous P (double sums)
+//   Bi axis 2  P --IFFT--> D1[E]/n1
+//
+// Every kernel is templated on the line length NC (> 0: compile-time FFT and
+// fully unrolled loads; 0: runtime plan) and on its tile width W / block size
+// NT.  All global loads of a tile are issued before any of them is used.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lsh_fft.hpp"
+#include "lsh_green.hpp"
+
+#define LSH_HIST 64  // device ring of residuals per load
+
+struct Geo {
+  int n1, n2, n3, h1;
+  long long m;
+  long long spec;  // h1 * n2 * n3 complex values per component and load
+};
+
+template <typename T> using C2 = typename cpx<T>::t;
+
+enum { MODE_STRESS = 0, MODE_FINAL = 1, MODE_INIT = 2 };
+
+// ------------------------------------------------------------ reductions ---
+template <int NV>
+__device__ void block_sum(double v[NV], double* out) {
+  __shared__ double red[16][NV];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] += __shfl_down(v[i], off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[wid][i] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += red[w][i];
+      out[i] = s;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_twiddles(C2<T>* dst, const C2<T>* __restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// tau = D E for one point, D a 6x6 Mandel matrix (C_p - C0)
+template <typename T>
+__device__ __forceinline__ void stress6(const T* D, const T E[6], T t[6]) {
+#pragma unroll
+  for (int I = 0; I < 6; ++I) {
+    T s = 0;
+#pragma unroll
+    for (int J = 0; J < 6; ++J) s += D[6 * I + J] * E[J];
+    t[I] = s;
+  }
+}
+
+// ------------------------------------------------------- axis-1 (stress) ---
+// One block: the axis-1 lines at fixed (load, i2) for W consecutive i3 and all
+// six components; component pairs (0,1), (2,3), (4,5) share one complex line.
+// LDS: twiddles[n1] then Z[k][q*W + w] (k < n1, q < 3, w < W).
+template <typename T, int MODE, int NC, int W, int NT>
+__global__ void __launch_bounds__(NT) k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
+                                              const C2<T>* __restrict__ X, C2<T>* __restrict__ Y,
+                                              const uint8_t* __restrict__ phase, const T* __restrict__ dmat,
+                                              int nphase, const double* __restrict__ cmat,
+                                              const double* __restrict__ eps0, const int* __restrict__ stop_iter,
+                                              int it, const double* __restrict__ Einit,
+                                              const double* __restrict__ means, double* __restrict__ Eout,
+                                              double* __restrict__ partial) {
+  using T2 = C2<T>;
+  constexpr int W3 = 3 * W;
+  constexpr int NDL = 16;  // phases whose (C_p - C0) live in LDS
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n1 = NC > 0 ? NC : g.n1;
+  const int h1 = n1 / 2 + 1;
+  T2* twl = reinterpret_cast<T2*>(smem_raw);
+  T2* Z = twl + n1;
+  T* Dl = reinterpret_cast<T*>(Z + n1 * W3);
+  const int L = blockIdx.y;
+  if (MODE == MODE_STRESS && it >= stop_iter[L]) return;
+  const int ntile3 = (g.n3 + W - 1) / W;
+  const int a2 = blockIdx.x / ntile3;
+  const int a30 = (blockIdx.x % ntile3) * W;
+  const long long n23 = (long long)g.n2 * g.n3;
+  const int tid = threadIdx.x;
+  const long long colbase = (long long)a2 * g.n3 + a30;
+  const int npairs = h1 * W3;
+  constexpr int PT = NC > 0 ? ((NC / 2 + 1) * W3 + NT - 1) / NT : 1;
+  constexpr int QT = NC > 0 ? (NC * W + NT - 1) / NT : 1;
+
+  stage_twiddles<T>(twl, tw, n1);
+  // phase indices of this thread's points: loaded first, used after the C2R
+  int ph[QT];
+  if (MODE == MODE_STRESS) {
+    const int nd = nphase < NDL ? nphase : NDL;
+    for (int i = tid; i < 36 * nd; i += NT) Dl[i] = dmat[i];
+    if constexpr (NC > 0) {
+#pragma unroll
+      for (int i = 0; i < QT; ++i) {
+        const int idx = tid + i * NT;
+        ph[i] = -1;
+        if (((NC * W) % NT == 0 || idx < NC * W) && a30 + idx % W < g.n3)
+          ph[i] = phase[(long long)(idx / W) * n23 + colbase + idx % W];
+      }
+    }
+  }
+
+  if (MODE != MODE_INIT) {
+    // Hermitian extension: Z_q[k] = X_{2q}[k] + i X_{2q+1}[k] on the full line
+    auto put = [&](int idx, T2 a, T2 b) {
+      const int w = idx % W, q = (idx / W) % 3, k = idx / W3;
+      const int col = q * W + w;
+      if (k == 0 || 2 * k == n1) {
+        Z[k * W3 + col] = T2{a.x, b.x};
+      } else {
+        Z[k * W3 + col] = T2{a.x - b.y, a.y + b.x};
+        Z[(n1 - k) * W3 + col] = T2{a.x + b.y, b.x - a.y};
+      }
+    };
+    auto addr = [&](int idx, int c2) -> long long {
+      const int w = idx % W, q = (idx / W) % 3, k = idx / W3;
+      return ((long long)(L * 6 + 2 * q + c2)) * g.spec + (long long)k * n23 + colbase + w;
+    };
+    if constexpr (NC > 0) {
+      T2 ra[PT], rb[PT];
+#pragma unroll
+      for (int i = 0; i < PT; ++i) {
+        const int idx = tid + i * NT;
+        ra[i] = T2{0, 0};
+        rb[i] = T2{0, 0};
+        if ((npairs % NT == 0 || idx < npairs) && a30 + idx % W < g.n3) {
+          ra[i] = X[addr(idx, 0)];
+          rb[i] = X[addr(idx, 1)];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PT; ++i) {
+        const int idx = tid + i * NT;
+        if (npairs % NT == 0 || idx < npairs) put(idx, ra[i], rb[i]);
+      }
+    } else {
+      for (int idx = tid; idx < npairs; idx += NT) {
+        T2 a = T2{0, 0}, b = T2{0, 0};
+        if (a30 + idx % W < g.n3) {
+          a = X[addr(idx, 0)];
+          b = X[addr(idx, 1)];
+        }
+        put(idx, a, b);
+      }
+    }
+    __syncthreads();
+    fft_any<T, +1, NC, W3, true, NT>(Z, pl, 1, W3, twl);
+  }
+
+  if (MODE == MODE_STRESS) {
+    const double* e0 = eps0 + 6 * L;
+    const T ep[6] = {(T)e0[0], (T)e0[1], (T)e0[2], (T)e0[3], (T)e0[4], (T)e0[5]};
+    auto stress = [&](int idx, int p) {
+      const int w = idx % W, a1 = idx / W;
+      T2* z = Z + a1 * W3 + w;
+      const T2 z0 = z[0], z1 = z[W], z2 = z[2 * W];
+      const T E[6] = {z0.x + ep[0], z0.y + ep[1], z1.x + ep[2], z1.y + ep[3], z2.x + ep[4], z2.y + ep[5]};
+      T t[6];
+      if (p < NDL)
+        stress6<T>(Dl + 36 * p, E, t);
+      else
+        stress6<T>(dmat + 36 * p, E, t);
+      z[0] = T2{t[0], t[1]};
+      z[W] = T2{t[2], t[3]};
+      z[2 * W] = T2{t[4], t[5]};
+    };
+    if constexpr (NC > 0) {
+#pragma unroll
+      for (int i = 0; i < QT; ++i)
+        if (ph[i] >= 0) stress(tid + i * NT, ph[i]);
+    } else {
+      for (int idx = tid; idx < n1 * W; idx += NT)
+        if (a30 + idx % W < g.n3) stress(idx, phase[(long long)(idx / W) * n23 + colbase + idx % W]);
+    }
+  } else if (MODE == MODE_INIT) {
+    const double SQ2I = 0.70710678118654752440;
+    for (int idx = tid; idx < n1 * W; idx += NT) {
+      const int w = idx % W, a1 = idx / W;
+      double E[6] = {0, 0, 0, 0, 0, 0};
+      if (a30 + w < g.n3) {
+        const long long pt = (long long)a1 * n23 + colbase + w;
+        for (int c = 0; c < 6; ++c) {
+          const double v = Einit[((long long)(L * 6 + c)) * g.m + pt] * (c < 3 ? 1.0 : SQ2I);
+          // the solver keeps X = D1[E] / n1 (D1: unnormalised DFT along axis 1)
+          E[c] = (v - means[6 * L + c]) / (double)n1;
+        }
+      }
+      T2* z = Z + a1 * W3 + w;
+      z[0] = T2{(T)E[0], (T)E[1]};
+      z[W] = T2{(T)E[2], (T)E[3]};
+      z[2 * W] = T2{(T)E[4], (T)E[5]};
+    }
+  } else {  // MODE_FINAL: sigma = C(y):(E + eps0) summed in double, optional E out
+    const double* e0 = eps0 + 6 * L;
+    const double SQ2 = 1.41421356237309504880;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int idx = tid; idx < n1 * W; idx += NT) {
+      const int w = idx % W, a1 = idx / W;
+      if (a30 + w >= g.n3) continue;
+      const T2* z = Z + a1 * W3 + w;
+      const double E[6] = {(double)z[0].x, (double)z[0].y, (double)z[W].x,
+                           (double)z[W].y, (double)z[2 * W].x, (double)z[2 * W].y};
+      const long long pt = (long long)a1 * n23 + colbase + w;
+      const double* Cm = cmat + 36 * phase[pt];
+      for (int I = 0; I < 6; ++I) {
+        double s = 0.0;
+        for (int J = 0; J < 6; ++J) s += Cm[6 * I + J] * (E[J] + e0[J]);
+        acc[I] += s;
+      }
+      if (Eout)
+        for (int c = 0; c < 6; ++c) Eout[((long long)(L * 6 + c)) * g.m + pt] = E[c] * (c < 3 ? 1.0 : SQ2);
+    }
+    block_sum<6>(acc, partial + ((long long)L * gridDim.x + blockIdx.x) * 6);
+    return;
+  }
+
+  __syncthreads();
+  fft_any<T, -1, NC, W3, true, NT>(Z, pl, 1, W3, twl);
+
+  // unpack the pairs and store the half spectrum k < h1
+  auto store = [&](int idx) {
+    const int w = idx % W, q = (idx / W) % 3, k = idx / W3;
+    if (a30 + w >= g.n3) return;
+    const int col = q * W + w;
+    const T2 zk = Z[k * W3 + col];
+    const T2 zn = Z[((n1 - k) % n1) * W3 + col];
+    const T hf = (T)0.5;
+    const long long off = (long long)k * n23 + colbase + w;
+    Y[((long long)(L * 6 + 2 * q)) * g.spec + off] = T2{hf * (zk.x + zn.x), hf * (zk.y - zn.y)};
+    Y[((long long)(L * 6 + 2 * q + 1)) * g.spec + off] = T2{hf * (zk.y + zn.y), hf * (zn.x - zk.x)};
+  };
+  if constexpr (NC > 0) {
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const int idx = tid + i * NT;
+      if (npairs % NT == 0 || idx < npairs) store(idx);
+    }
+  } else {
+    for (int idx = tid; idx < npairs; idx += NT) store(idx);
+  }
+}
+
+// ----------------------------------------------------------------- axis 2 ---
+// One block: W consecutive i3 columns at fixed (load, comp, k1); lines along
+// axis 2.  LDS: twiddles[n2] then Z[i2*W + w].
+template <typename T, int DIR, int NC, int W, int NT>
+__global__ void __launch_bounds__(NT) k_axis2(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
+                                              const C2<T>* __restrict__ src, C2<T>* __restrict__ dst,
+                                              const int* __restrict__ stop_iter, int it, T scale) {
+  using T2 = C2<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n2 = NC > 0 ? NC : g.n2;
+  T2* twl = reinterpret_cast<T2*>(smem_raw);
+  T2* Z = twl + n2;
+  const int L = blockIdx.z, c = blockIdx.y;
+  if (stop_iter && it >= stop_iter[L]) return;
+  const int ntile3 = (g.n3 + W - 1) / W;
+  const int k1 = blockIdx.x / ntile3;
+  const int a30 = (blockIdx.x % ntile3) * W;
+  const long long base = ((long long)(L * 6 + c)) * g.spec + (long long)k1 * n2 * g.n3 + a30;
+  const int tid = threadIdx.x;
+  const int ne = n2 * W;
+  stage_twiddles<T>(twl, tw, n2);
+  if constexpr (NC > 0) {
+    constexpr int ET = (NC * W + NT - 1) / NT;
+    T2 r[ET];
+#pragma unroll
+    for (int i = 0; i < ET; ++i) {
+      const int idx = tid + i * NT;
+      r[i] = T2{0, 0};
+      if (((NC * W) % NT == 0 || idx < ne) && a30 + idx % W < g.n3) r[i] = src[base + (long long)(idx / W) * g.n3 + idx % W];
+    }
+#pragma unroll
+    for (int i = 0; i < ET; ++i) {
+      const int idx = tid + i * NT;
+      if ((NC * W) % NT == 0 || idx < ne) Z[idx] = r[i];
+    }
+  } else {
+    for (int idx = tid; idx < ne; idx += NT)
+      Z[idx] = (a30 + idx % W < g.n3) ? src[base + (long long)(idx / W) * g.n3 + idx % W] : T2{0, 0};
+  }
+  __syncthreads();
+  fft_any<T, DIR, NC, W, true, NT>(Z, pl, 1, W, twl);
+  for (int idx = tid; idx < ne; idx += NT) {
+    if (a30 + idx % W < g.n3) {
+      T2 v = Z[idx];
+      if (scale != (T)1) v = T2{v.x * scale, v.y * scale};
+      dst[base + (long long)(idx / W) * g.n3 + idx % W] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------ Green pass ---
+// One block per (position (k1,k2), load); blocks of one position are placed
+// on the same XCD back to back (block id mod 8 picks the XCD) so that a
+// position's Gamma table rows, when a table is used, are read from HBM once
+// and then hit that XCD's L2.  LDS: twiddles[n3], lines[6][ls].
+// gmode: 0 isotropic C0 (moment form, on the fly), 1 general C0 on the fly,
+// 2 table [pos][21][n3] built at bind time (double sums, stored at T).
+enum { GREEN_ISO = 0, GREEN_GENERAL = 1, GREEN_TABLE = 2 };
+template <typename T, int NC, int NT>
+__global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __restrict__ tw, GreenParams gp,
+                                              const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
+                                              C2<T>* __restrict__ Pnew, const T* __restrict__ table,
+                                              const int* __restrict__ stop_iter, int it, int nload, int npos,
+                                              double* __restrict__ partial, int ls, int gmode, double mu0,
+                                              double riso) {
+  using T2 = C2<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n3 = NC > 0 ? NC : g.n3;
+  T2* twl = reinterpret_cast<T2*>(smem_raw);
+  T2* lines = twl + n3;
+  // XCD-aware block order
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int pos = (slot / nload) * 8 + xcd;
+  const int L = slot % nload;
+  if (pos >= npos || it >= stop_iter[L]) return;
+  const int k1 = pos / g.n2, k2 = pos % g.n2;
+  const int tid = threadIdx.x;
+  const double scale = -1.0 / (double)g.m;
+  const double wk1 = (k1 == 0 || 2 * k1 == g.n1) ? 1.0 : 2.0;
+  const long long row = (long long)k1 * g.n2 * g.n3 + (long long)k2 * g.n3;
+  const int ne = 6 * n3;
+  constexpr int ET = NC > 0 ? (6 * NC + NT - 1) / NT : 1;
+
+  stage_twiddles<T>(twl, tw, n3);
+  // tau lines (and the table rows) first, all loads in flight together
+  if constexpr (NC > 0) {
+    T2 r[ET];
+#pragma unroll
+    for (int i = 0; i < ET; ++i) {
+      const int idx = tid + i * NT;
+      if ((6 * NC) % NT == 0 || idx < ne) {
+        const int c = idx / NC, k3 = idx % NC;
+        r[i] = tau[((long long)(L * 6 + c)) * g.spec + row + k3];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < ET; ++i) {
+      const int idx = tid + i * NT;
+      if ((6 * NC) % NT == 0 || idx < ne) lines[(idx / NC) * ls + idx % NC] = r[i];
+    }
+  } else {
+    for (int idx = tid; idx < ne; idx += NT) {
+      const int c = idx / n3, k3 = idx - c * n3;
+      lines[c * ls + k3] = tau[((long long)(L * 6 + c)) * g.spec + row + k3];
+    }
+  }
+  __syncthreads();
+  fft_any<T, -1, NC, 6, false, NT>(lines, pl, ls, 1, twl);
+  for (int k3 = tid; k3 < n3; k3 += NT) {
+    T G[21];
+    if (gmode == GREEN_TABLE) {
+      const T* tb = table + (long long)pos * 21 * n3 + k3;
+#pragma unroll
+      for (int t = 0; t < 21; ++t) G[t] = (T)(scale * (double)tb[(long long)t * n3]);
+    } else {
+      double Gd[21];
+      if (gmode == GREEN_ISO)
+        gamma_sym_iso(gp, mu0, riso, k1, k2, k3, Gd);
+      else
+        gamma_sym_at(gp, k1, k2, k3, Gd);
+#pragma unroll
+      for (int t = 0; t < 21; ++t) G[t] = (T)(scale * Gd[t]);
+    }
+    T2 v[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = lines[c * ls + k3];
+#pragma unroll
+    for (int I = 0; I < 6; ++I) {
+      T2 s = T2{0, 0};
+#pragma unroll
+      for (int J = 0; J < 6; ++J) {
+        const T gij = G[I <= J ? tri_idx(I, J) : tri_idx(J, I)];
+        s.x += gij * v[J].x;
+        s.y += gij * v[J].y;
+      }
+      lines[I * ls + k3] = s;
+    }
+  }
+  // previous iterate: issue its loads before the inverse transform
+  T2 po[NC > 0 ? ET : 1];
+  if constexpr (NC > 0) {
+#pragma unroll
+    for (int i = 0; i < ET; ++i) {
+      const int idx = tid + i * NT;
+      if ((6 * NC) % NT == 0 || idx < ne) po[i] = Pold[((long long)(L * 6 + idx / NC)) * g.spec + row + idx % NC];
+    }
+  }
+  __syncthreads();
+  fft_any<T, +1, NC, 6, false, NT>(lines, pl, ls, 1, twl);
+  double acc[2] = {0.0, 0.0};
+  auto finish = [&](int idx, T2 ov) {
+    const int c = idx / n3, k3 = idx - c * n3;
+    const long long gi = ((long long)(L * 6 + c)) * g.spec + row + k3;
+    const T2 nv = lines[c * ls + k3];
+    Pnew[gi] = nv;
+    const double dx = (double)nv.x - (double)ov.x, dy = (double)nv.y - (double)ov.y;
+    acc[0] += wk1 * (dx * dx + dy * dy);
+    acc[1] += wk1 * ((double)nv.x * (double)nv.x + (double)nv.y * (double)nv.y);
+  };
+  if constexpr (NC > 0) {
+#pragma unroll
+    for (int i = 0; i < ET; ++i) {
+      const int idx = tid + i * NT;
+      if ((6 * NC) % NT == 0 || idx < ne) finish(idx, po[i]);
+    }
+  } else {
+    for (int idx = tid; idx < ne; idx += NT) {
+      const int c = idx / n3, k3 = idx - c * n3;
+      finish(idx, Pold[((long long)(L * 6 + c)) * g.spec + row + k3]);
+    }
+  }
+  block_sum<2>(acc, partial + ((long long)L * npos + pos) * 2);
+}
+
+// ------------------------------------------------------------ finalisers ---
+__global__ void k_finalize_resid(const double* __restrict__ partial, int nblk, int nload,
+                                 const double* __restrict__ e0sq, double pscale, double tol, int fixed, int it,
+                                 int* __restrict__ stop_iter, double* __restrict__ hist, int* __restrict__ nonfinite) {
+  const int L = blockIdx.x;
+  if (it >= stop_iter[L]) return;
+  double s[2] = {0.0, 0.0};
+  for (int j = threadIdx.x; j < nblk; j += blockDim.x) {
+    s[0] += partial[((long long)L * nblk + j) * 2];
+    s[1] += partial[((long long)L * nblk + j) * 2 + 1];
+  }
+  double out[2];
+  block_sum<2>(s, out);
+  if (threadIdx.x == 0) {
+    const double num = out[0] * pscale;
+    const double den = out[1] * pscale + e0sq[L];
+    const double r = sqrt(num / den);
+    hist[(it % LSH_HIST) * nload + L] = r;
+    if (!isfinite(r)) {
+      nonfinite[L] = 1;
+      stop_iter[L] = it + 1;
+    } else if (!fixed && r <= tol) {
+      stop_iter[L] = it + 1;
+    }
+  }
+}
+
+__global__ void k_finalize_sum(const double* __restrict__ partial, int nblk, int nv, double scale,
+                               double* __restrict__ out) {
+  const int L = blockIdx.x, i = blockIdx.y;
+  double s[1] = {0.0};
+  for (int j = threadIdx.x; j < nblk; j += blockDim.x) s[0] += partial[((long long)L * nblk + j) * nv + i];
+  double o[1];
+  block_sum<1>(s, o);
+  if (threadIdx.x == 0) out[L * nv + i] = scale * o[0];
+}
+
+// mean of the Mandel components of a start field, per (load, comp) block
+__global__ void k_mean(const double* __restrict__ E, long long m, double* __restrict__ means) {
+  const int L = blockIdx.x, c = blockIdx.y;
+  const double f = c < 3 ? 1.0 : 0.70710678118654752440;
+  double s[1] = {0.0};
+  for (long long i = threadIdx.x; i < m; i += blockDim.x) s[0] += E[((long long)(L * 6 + c)) * m + i];
+  double o[1];
+  block_sum<1>(s, o);
+  if (threadIdx.x == 0) means[6 * L + c] = f * o[0] / (double)m;
+}
+
+// ---------------------------------------------------------- Gamma table ---
+// One thread per half-spectrum bin: the alias sums in double, stored at T.
+template <typename T>
+__global__ void k_gamma_table(Geo g, GreenParams gp, T* __restrict__ table, double* __restrict__ minden) {
+  const long long nb = g.spec;
+  double mn = 1e300;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (long long)gridDim.x * blockDim.x) {
+    const int k3 = (int)(i % g.n3);
+    const int k2 = (int)((i / g.n3) % g.n2);
+    const int k1 = (int)(i / ((long long)g.n2 * g.n3));
+    double G[21];
+    const double den = gamma_sym_at(gp, k1, k2, k3, G);
+    mn = fmin(mn, den);
+    const long long pos = i / g.n3;
+    for (int t = 0; t < 21; ++t) table[(pos * 21 + t) * g.n3 + k3] = (T)G[t];
+  }
+  __shared__ double red[16];
+  for (int off = 32; off > 0; off >>= 1) mn = fmin(mn, __shfl_down(mn, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < (int)((blockDim.x + 63) >> 6); ++w) r = fmin(r, red[w]);
+    minden[blockIdx.x] = r;
+  }
+}
+
+__global__ void k_gamma_probe(GreenParams gp, const long long* __restrict__ bins, int n, double* __restrict__ out,
+                              int gmode, double mu0, double riso) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double G[21];
+  if (gmode == GREEN_ISO)
+    gamma_sym_iso(gp, mu0, riso, bins[3 * i], bins[3 * i + 1], bins[3 * i + 2], G);
+  else
+    gamma_sym_at(gp, bins[3 * i], bins[3 * i + 1], bins[3 * i + 2], G);
+  for (int t = 0; t < 21; ++t) out[21 * i + t] = G[t];
+}
+
+template <typename T>
+__global__ void k_cast_table(const T* __restrict__ src, double* __restrict__ dst, const long long* __restrict__ bins,
+                             int n, Geo g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long long pos = bins[3 * i] * g.n2 + bins[3 * i + 1];
+  for (int t = 0; t < 21; ++t) dst[21 * i + t] = (double)src[(pos * 21 + t) * g.n3 + bins[3 * i + 2]];
+}

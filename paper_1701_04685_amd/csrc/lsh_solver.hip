@@ -28,397 +28,9 @@
 
 #include "lsh_internal.hpp"
 
-#define LSH_MAXE 16
-#define LSH_HIST 64  // device ring of residuals per load
+#include "lsh_kernels.hpp"
 
 namespace {
-
-struct Geo {
-  int n1, n2, n3, h1;
-  long long m;
-  long long spec;  // h1 * n2 * n3
-};
-
-template <typename T> using C2 = typename cpx<T>::t;
-
-// ------------------------------------------------------------ reductions ---
-template <int NV>
-__device__ void block_sum(double v[NV], double* out) {
-  __shared__ double red[16][NV];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] += __shfl_down(v[i], off, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) red[wid][i] = v[i];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int i = 0; i < NV; ++i) {
-      double s = 0.0;
-      for (int w = 0; w < nw; ++w) s += red[w][i];
-      out[i] = s;
-    }
-  }
-  __syncthreads();
-}
-
-// ------------------------------------------------------- axis-1 (stress) ---
-enum { MODE_STRESS = 0, MODE_FINAL = 1, MODE_INIT = 2 };
-
-// One block: lines along axis 1 at fixed (load, a2) for W consecutive a3 and
-// all six components (three complex lines per column).  LDS holds
-// Z[k][q*W + w], k < n1, q < 3, w < W.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(512) k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
-                                               const C2<T>* __restrict__ X, C2<T>* __restrict__ Y,
-                                               const uint8_t* __restrict__ phase, const T* __restrict__ dmat,
-                                               const double* __restrict__ cmat, const double* __restrict__ eps0,
-                                               const int* __restrict__ stop_iter, int it,
-                                               const double* __restrict__ Einit, const double* __restrict__ means,
-                                               double* __restrict__ Eout, double* __restrict__ partial, int W) {
-  using T2 = C2<T>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T2* Z = reinterpret_cast<T2*>(smem_raw);
-  const int L = blockIdx.y;
-  if (MODE == MODE_STRESS && it >= stop_iter[L]) return;
-  const int ntile3 = (g.n3 + W - 1) / W;
-  const int a2 = blockIdx.x / ntile3;
-  const int a30 = (blockIdx.x % ntile3) * W;
-  const int n1 = g.n1, h1 = g.h1, W3 = 3 * W;
-  const long long n23 = (long long)g.n2 * g.n3;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const long long colbase = (long long)a2 * g.n3 + a30;
-
-  if (MODE != MODE_INIT) {
-    // Hermitian extension: Z_q[k] = X_{2q}[k] + i X_{2q+1}[k] on the full line
-    for (int idx = tid; idx < h1 * W3; idx += nthr) {
-      const int w = idx % W, q = (idx / W) % 3, k = idx / W3;
-      T2 a = T2{0, 0}, b = T2{0, 0};
-      if (a30 + w < g.n3) {
-        const long long off = (long long)k * n23 + colbase + w;
-        a = X[((long long)(L * 6 + 2 * q)) * g.spec + off];
-        b = X[((long long)(L * 6 + 2 * q + 1)) * g.spec + off];
-      }
-      const int col = q * W + w;
-      if (k == 0 || 2 * k == n1) {
-        Z[k * W3 + col] = T2{a.x, b.x};
-      } else {
-        Z[k * W3 + col] = T2{a.x - b.y, a.y + b.x};
-        Z[(n1 - k) * W3 + col] = T2{a.x + b.y, b.x - a.y};
-      }
-    }
-    __syncthreads();
-    fft_lines<T, +1, LSH_MAXE>(Z, pl, W3, 1, W3, true, tw);
-  }
-
-  if (MODE == MODE_STRESS) {
-    const double* e0 = eps0 + 6 * L;
-    const T ep[6] = {(T)e0[0], (T)e0[1], (T)e0[2], (T)e0[3], (T)e0[4], (T)e0[5]};
-    for (int idx = tid; idx < n1 * W; idx += nthr) {
-      const int w = idx % W, a1 = idx / W;
-      if (a30 + w >= g.n3) continue;
-      T2* z = Z + a1 * W3 + w;
-      const T2 z0 = z[0], z1 = z[W], z2 = z[2 * W];
-      const T E[6] = {z0.x + ep[0], z0.y + ep[1], z1.x + ep[2], z1.y + ep[3], z2.x + ep[4], z2.y + ep[5]};
-      const int p = phase[(long long)a1 * n23 + colbase + w];
-      const T* D = dmat + 36 * p;
-      T t[6];
-#pragma unroll
-      for (int I = 0; I < 6; ++I) {
-        T s = 0;
-#pragma unroll
-        for (int J = 0; J < 6; ++J) s += D[6 * I + J] * E[J];
-        t[I] = s;
-      }
-      z[0] = T2{t[0], t[1]};
-      z[W] = T2{t[2], t[3]};
-      z[2 * W] = T2{t[4], t[5]};
-    }
-  } else if (MODE == MODE_INIT) {
-    const double SQ2I = 0.70710678118654752440;
-    for (int idx = tid; idx < n1 * W; idx += nthr) {
-      const int w = idx % W, a1 = idx / W;
-      double E[6] = {0, 0, 0, 0, 0, 0};
-      if (a30 + w < g.n3) {
-        const long long pt = (long long)a1 * n23 + colbase + w;
-        for (int c = 0; c < 6; ++c) {
-          const double v = Einit[((long long)(L * 6 + c)) * g.m + pt] * (c < 3 ? 1.0 : SQ2I);
-          // the solver keeps E(k1,a2,a3) = D1[E] / n1 (D1: unnormalised DFT along axis 1)
-          E[c] = (v - means[6 * L + c]) / (double)n1;
-        }
-      }
-      T2* z = Z + a1 * W3 + w;
-      z[0] = T2{(T)E[0], (T)E[1]};
-      z[W] = T2{(T)E[2], (T)E[3]};
-      z[2 * W] = T2{(T)E[4], (T)E[5]};
-    }
-  } else {  // MODE_FINAL: sigma = C(y):(E + eps0) summed in double, optional E out
-    const double* e0 = eps0 + 6 * L;
-    const double SQ2 = 1.41421356237309504880;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int idx = tid; idx < n1 * W; idx += nthr) {
-      const int w = idx % W, a1 = idx / W;
-      if (a30 + w >= g.n3) continue;
-      const T2* z = Z + a1 * W3 + w;
-      const double E[6] = {(double)z[0].x, (double)z[0].y, (double)z[W].x,
-                           (double)z[W].y, (double)z[2 * W].x, (double)z[2 * W].y};
-      const long long pt = (long long)a1 * n23 + colbase + w;
-      const double* Cm = cmat + 36 * phase[pt];
-      for (int I = 0; I < 6; ++I) {
-        double s = 0.0;
-        for (int J = 0; J < 6; ++J) s += Cm[6 * I + J] * (E[J] + e0[J]);
-        acc[I] += s;
-      }
-      if (Eout)
-        for (int c = 0; c < 6; ++c) Eout[((long long)(L * 6 + c)) * g.m + pt] = E[c] * (c < 3 ? 1.0 : SQ2);
-    }
-    block_sum<6>(acc, partial + ((long long)L * gridDim.x + blockIdx.x) * 6);
-    return;
-  }
-
-  __syncthreads();
-  fft_lines<T, -1, LSH_MAXE>(Z, pl, W3, 1, W3, true, tw);
-
-  // unpack the pairs and store the half spectrum k < h1
-  for (int idx = tid; idx < h1 * W3; idx += nthr) {
-    const int w = idx % W, q = (idx / W) % 3, k = idx / W3;
-    if (a30 + w >= g.n3) continue;
-    const int col = q * W + w;
-    const T2 zk = Z[k * W3 + col];
-    const T2 zn = Z[((n1 - k) % n1) * W3 + col];
-    const T hf = (T)0.5;
-    const T2 xa = T2{hf * (zk.x + zn.x), hf * (zk.y - zn.y)};
-    const T2 xb = T2{hf * (zk.y + zn.y), hf * (zn.x - zk.x)};
-    const long long off = (long long)k * n23 + colbase + w;
-    Y[((long long)(L * 6 + 2 * q)) * g.spec + off] = xa;
-    Y[((long long)(L * 6 + 2 * q + 1)) * g.spec + off] = xb;
-  }
-}
-
-// ----------------------------------------------------------------- axis 2 ---
-// One block: W consecutive i3 columns at fixed (load, comp, k1); lines along
-// axis 2, LDS element-major lds[i2*W + w].
-template <typename T, int DIR>
-__global__ void __launch_bounds__(512) k_axis2(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
-                                               const C2<T>* __restrict__ src, C2<T>* __restrict__ dst,
-                                               const int* __restrict__ stop_iter, int it, int W, T scale) {
-  using T2 = C2<T>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T2* Z = reinterpret_cast<T2*>(smem_raw);
-  const int L = blockIdx.z, c = blockIdx.y;
-  if (stop_iter && it >= stop_iter[L]) return;
-  const int ntile3 = (g.n3 + W - 1) / W;
-  const int k1 = blockIdx.x / ntile3;
-  const int a30 = (blockIdx.x % ntile3) * W;
-  const long long base = ((long long)(L * 6 + c)) * g.spec + (long long)k1 * g.n2 * g.n3 + a30;
-  const int n2 = g.n2, tid = threadIdx.x, nthr = blockDim.x;
-  for (int idx = tid; idx < n2 * W; idx += nthr) {
-    const int w = idx % W, e = idx / W;
-    Z[idx] = (a30 + w < g.n3) ? src[base + (long long)e * g.n3 + w] : T2{0, 0};
-  }
-  __syncthreads();
-  fft_lines<T, DIR, LSH_MAXE>(Z, pl, W, 1, W, true, tw);
-  for (int idx = tid; idx < n2 * W; idx += nthr) {
-    const int w = idx % W, e = idx / W;
-    if (a30 + w < g.n3) {
-      T2 v = Z[idx];
-      if (scale != (T)1) v = T2{v.x * scale, v.y * scale};
-      dst[base + (long long)e * g.n3 + w] = v;
-    }
-  }
-}
-
-// ------------------------------------------------------------ Green pass ---
-// One block per (k1, k2): the six axis-3 lines of every load.  Gamma for the
-// block's n3 bins is computed once (double, scaled by -1/m, cast to T) and
-// reused for all loads when it fits in LDS.
-template <typename T>
-__global__ void __launch_bounds__(512) k_green(Geo g, FftPlan pl, const C2<T>* __restrict__ tw, GreenParams gp,
-                                                const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
-                                                C2<T>* __restrict__ Pnew, const T* __restrict__ table,
-                                                const int* __restrict__ stop_iter, int it, int nload,
-                                                double* __restrict__ partial, int ls, int cacheG) {
-  using T2 = C2<T>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T2* lines = reinterpret_cast<T2*>(smem_raw);
-  T* Gs = reinterpret_cast<T*>(smem_raw + sizeof(T2) * 6 * ls);
-  const int n3 = g.n3, tid = threadIdx.x, nthr = blockDim.x;
-  const int k1 = blockIdx.x / g.n2, k2 = blockIdx.x % g.n2;
-  const double scale = -1.0 / (double)g.m;
-  const double wk1 = (k1 == 0 || 2 * k1 == g.n1) ? 1.0 : 2.0;
-  const long long row = (long long)k1 * g.n2 * g.n3 + (long long)k2 * g.n3;
-  bool any = false;
-  for (int L = 0; L < nload; ++L) any = any || (it < stop_iter[L]);
-  if (!any) return;
-  if (cacheG) {
-    for (int k3 = tid; k3 < n3; k3 += nthr) {
-      double G[21];
-      if (table) {
-        const T* tb = table + (row + k3) * 21;
-        for (int t = 0; t < 21; ++t) G[t] = (double)tb[t];
-      } else {
-        gamma_sym_at(gp, k1, k2, k3, G);
-      }
-      for (int t = 0; t < 21; ++t) Gs[k3 * 21 + t] = (T)(scale * G[t]);
-    }
-  }
-  for (int L = 0; L < nload; ++L) {
-    if (it >= stop_iter[L]) continue;
-    __syncthreads();
-    for (int idx = tid; idx < 6 * n3; idx += nthr) {
-      const int c = idx / n3, k3 = idx - c * n3;
-      lines[c * ls + k3] = tau[((long long)(L * 6 + c)) * g.spec + row + k3];
-    }
-    __syncthreads();
-    fft_lines<T, -1, LSH_MAXE>(lines, pl, 6, ls, 1, false, tw);
-    for (int k3 = tid; k3 < n3; k3 += nthr) {
-      T G[21];
-      if (cacheG) {
-        for (int t = 0; t < 21; ++t) G[t] = Gs[k3 * 21 + t];
-      } else {
-        double Gd[21];
-        if (table) {
-          const T* tb = table + (row + k3) * 21;
-          for (int t = 0; t < 21; ++t) Gd[t] = (double)tb[t];
-        } else {
-          gamma_sym_at(gp, k1, k2, k3, Gd);
-        }
-        for (int t = 0; t < 21; ++t) G[t] = (T)(scale * Gd[t]);
-      }
-      T2 v[6];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) v[c] = lines[c * ls + k3];
-#pragma unroll
-      for (int I = 0; I < 6; ++I) {
-        T2 s = T2{0, 0};
-#pragma unroll
-        for (int J = 0; J < 6; ++J) {
-          const T gij = G[I <= J ? tri_idx(I, J) : tri_idx(J, I)];
-          s.x += gij * v[J].x;
-          s.y += gij * v[J].y;
-        }
-        lines[I * ls + k3] = s;
-      }
-    }
-    __syncthreads();
-    fft_lines<T, +1, LSH_MAXE>(lines, pl, 6, ls, 1, false, tw);
-    double acc[2] = {0.0, 0.0};
-    for (int idx = tid; idx < 6 * n3; idx += nthr) {
-      const int c = idx / n3, k3 = idx - c * n3;
-      const long long gi = ((long long)(L * 6 + c)) * g.spec + row + k3;
-      const T2 nv = lines[c * ls + k3];
-      const T2 ov = Pold[gi];
-      Pnew[gi] = nv;
-      const double dx = (double)nv.x - (double)ov.x, dy = (double)nv.y - (double)ov.y;
-      acc[0] += wk1 * (dx * dx + dy * dy);
-      acc[1] += wk1 * ((double)nv.x * (double)nv.x + (double)nv.y * (double)nv.y);
-    }
-    block_sum<2>(acc, partial + ((long long)L * gridDim.x + blockIdx.x) * 2);
-  }
-}
-
-// ------------------------------------------------------------ finalisers ---
-__global__ void k_finalize_resid(const double* __restrict__ partial, int nblk, int nload,
-                                 const double* __restrict__ e0sq, double pscale, double tol, int fixed, int it,
-                                 int* __restrict__ stop_iter, double* __restrict__ hist, int* __restrict__ nonfinite) {
-  const int L = blockIdx.x;
-  if (it >= stop_iter[L]) return;
-  double s[2] = {0.0, 0.0};
-  for (int j = threadIdx.x; j < nblk; j += blockDim.x) {
-    s[0] += partial[((long long)L * nblk + j) * 2];
-    s[1] += partial[((long long)L * nblk + j) * 2 + 1];
-  }
-  double out[2];
-  block_sum<2>(s, out);
-  if (threadIdx.x == 0) {
-    const double num = out[0] * pscale;
-    const double den = out[1] * pscale + e0sq[L];
-    const double r = sqrt(num / den);
-    hist[(it % LSH_HIST) * nload + L] = r;
-    if (!isfinite(r)) {
-      nonfinite[L] = 1;
-      stop_iter[L] = it + 1;
-    } else if (!fixed && r <= tol) {
-      stop_iter[L] = it + 1;
-    }
-  }
-}
-
-__global__ void k_finalize_sum(const double* __restrict__ partial, int nblk, int nv, double scale,
-                               double* __restrict__ out) {
-  // out[L*nv + i] = scale * sum_j partial[(L*nblk + j)*nv + i]; one block per (L, i)
-  const int L = blockIdx.x, i = blockIdx.y;
-  double s[1] = {0.0};
-  for (int j = threadIdx.x; j < nblk; j += blockDim.x) s[0] += partial[((long long)L * nblk + j) * nv + i];
-  double o[1];
-  block_sum<1>(s, o);
-  if (threadIdx.x == 0) out[L * nv + i] = scale * o[0];
-}
-
-// mean of the Mandel components of a start field, per (load, comp) block
-__global__ void k_mean(const double* __restrict__ E, long long m, double* __restrict__ means) {
-  const int L = blockIdx.x, c = blockIdx.y;
-  const double f = c < 3 ? 1.0 : 0.70710678118654752440;
-  double s[1] = {0.0};
-  for (long long i = threadIdx.x; i < m; i += blockDim.x) s[0] += E[((long long)(L * 6 + c)) * m + i];
-  double o[1];
-  block_sum<1>(s, o);
-  if (threadIdx.x == 0) means[6 * L + c] = f * o[0] / (double)m;
-}
-
-// ---------------------------------------------------------- Gamma table ---
-// One thread per half-spectrum bin; double alias sums, stored at T.
-template <typename T>
-__global__ void k_gamma_table(Geo g, GreenParams gp, T* __restrict__ table, double* __restrict__ minden) {
-  const long long nb = g.spec;
-  double mn[1] = {1e300};
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (long long)gridDim.x * blockDim.x) {
-    const int k3 = (int)(i % g.n3);
-    const int k2 = (int)((i / g.n3) % g.n2);
-    const int k1 = (int)(i / ((long long)g.n2 * g.n3));
-    double G[21];
-    const double den = gamma_sym_at(gp, k1, k2, k3, G);
-    mn[0] = fmin(mn[0], den);
-    for (int t = 0; t < 21; ++t) table[i * 21 + t] = (T)G[t];
-  }
-  // block min via the sum helper on negated values is not a min; do it by hand
-  __shared__ double red[16];
-  double v = mn[0];
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double r = red[0];
-    for (int w = 1; w < (int)((blockDim.x + 63) >> 6); ++w) r = fmin(r, red[w]);
-    minden[blockIdx.x] = r;
-  }
-}
-
-__global__ void k_gamma_probe(GreenParams gp, const long long* __restrict__ bins, int n,
-                              const double* __restrict__ table, int use_table, Geo g, double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double G[21];
-  if (use_table) {
-    const long long row = (bins[3 * i] * g.n2 + bins[3 * i + 1]) * g.n3 + bins[3 * i + 2];
-    for (int t = 0; t < 21; ++t) G[t] = table[row * 21 + t];
-  } else {
-    gamma_sym_at(gp, bins[3 * i], bins[3 * i + 1], bins[3 * i + 2], G);
-  }
-  for (int t = 0; t < 21; ++t) out[21 * i + t] = G[t];
-}
-
-template <typename T>
-__global__ void k_cast_table(const T* __restrict__ src, double* __restrict__ dst, const long long* __restrict__ bins,
-                             int n, Geo g) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const long long row = (bins[3 * i] * g.n2 + bins[3 * i + 1]) * g.n3 + bins[3 * i + 2];
-  for (int t = 0; t < 21; ++t) dst[21 * i + t] = (double)src[row * 21 + t];
-}
 
 // ------------------------------------------------------------ host side ---
 #define HIPCHK(x)                                                                          \
@@ -440,95 +52,248 @@ Geo geo_of(const lsh_pattern* p) {
   return g;
 }
 
-// Does an FFT of this plan over L lines fit nthr threads x LSH_MAXE registers?
+// Does a runtime-plan FFT over L lines fit nthr threads x 16 registers?
 bool plan_fits(const FftPlan& pl, int L, int nthr) {
   for (int s = 0; s < pl.nst; ++s) {
     const int R = pl.rad[s];
-    const int maxb = std::max(1, LSH_MAXE / R);
+    const int maxb = std::max(1, 16 / R);
     const long long nb = (long long)(pl.N / R) * L;
     if (nb > (long long)nthr * maxb) return false;
   }
   return true;
 }
 
-struct Launch {
-  int W, nthr;
-  size_t lds;
+int lds_limit() {
+  static int lim = -1;
+  if (lim < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      v = 64 * 1024;
+    lim = v;
+  }
+  return lim;
+}
+
+// The kernel instantiations chosen for one pattern and precision.
+template <typename T>
+struct KernSet {
+  using A1 = void (*)(Geo, FftPlan, const C2<T>*, const C2<T>*, C2<T>*, const uint8_t*, const T*, int,
+                      const double*, const double*, const int*, int, const double*, const double*, double*, double*);
+  using A2 = void (*)(Geo, FftPlan, const C2<T>*, const C2<T>*, C2<T>*, const int*, int, T);
+  using GR = void (*)(Geo, FftPlan, const C2<T>*, GreenParams, const C2<T>*, const C2<T>*, C2<T>*, const T*,
+                      const int*, int, int, int, double*, int, int, double, double);
+  A1 a1[3] = {nullptr, nullptr, nullptr};  // MODE_STRESS, MODE_FINAL, MODE_INIT
+  A2 a2[2] = {nullptr, nullptr};           // forward, inverse
+  GR gr = nullptr;
+  int W1 = 0, NT1 = 0, W2 = 0, NT2 = 0, NTG = 0, lsG = 0;
+  size_t lds1 = 0, lds2 = 0, ldsG = 0;
 };
 
-template <typename T>
-bool choose_axis1(const Geo& g, const FftPlan& pl, Launch* out) {
-  const int targets[] = {16, 8, 4, 2, 1};
-  for (int W : targets) {
-    if (W > 1 && W > g.n3) continue;
-    for (int nthr : {256, 512}) {
-      const size_t lds = sizeof(C2<T>) * (size_t)g.n1 * 3 * W;
-      if (lds > 64 * 1024) continue;
-      if (!plan_fits(pl, 3 * W, nthr)) continue;
-      out->W = W;
-      out->nthr = nthr;
-      out->lds = lds;
-      return true;
-    }
+constexpr int pick_w(int N, int bytes_per_col, int cap, int budget) {
+  int w = cap;
+  while (w > 1 && N * w * bytes_per_col > budget) w /= 2;
+  return w;
+}
+
+// compile-time line lengths; every other length takes the runtime plan
+#define LSH_SPECIAL_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(128) X(256) X(512)
+
+template <typename T, int NC, int W>
+void put_axis1(KernSet<T>& K) {
+  K.a1[0] = k_axis1<T, MODE_STRESS, NC, W, 256>;
+  K.a1[1] = k_axis1<T, MODE_FINAL, NC, W, 256>;
+  K.a1[2] = k_axis1<T, MODE_INIT, NC, W, 256>;
+  K.W1 = W;
+  K.NT1 = 256;
+}
+
+template <typename T, int NC>
+bool axis1_special(const Geo& g, KernSet<T>& K) {
+  constexpr int W = pick_w(NC, 3 * (int)sizeof(C2<T>), 16, 60 * 1024);
+  if (g.n3 < W) return false;
+  if constexpr (NC * 3 * W * sizeof(C2<T>) >= 32768) {
+    K.a1[0] = k_axis1<T, MODE_STRESS, NC, W, 512>;
+    K.a1[1] = k_axis1<T, MODE_FINAL, NC, W, 512>;
+    K.a1[2] = k_axis1<T, MODE_INIT, NC, W, 512>;
+    K.W1 = W;
+    K.NT1 = 512;
+  } else {
+    put_axis1<T, NC, W>(K);
   }
-  return false;
+  return true;
 }
 
 template <typename T>
-bool choose_axis2(const Geo& g, const FftPlan& pl, Launch* out) {
-  const int targets[] = {32, 16, 8, 4, 2, 1};
-  for (int W : targets) {
-    if (W > 1 && W > g.n3) continue;
-    if (sizeof(T) == 8 && W > 16) continue;
-    for (int nthr : {256, 512}) {
-      const size_t lds = sizeof(C2<T>) * (size_t)g.n2 * W;
-      if (lds > 64 * 1024) continue;
-      if (!plan_fits(pl, W, nthr)) continue;
-      out->W = W;
-      out->nthr = nthr;
-      out->lds = lds;
-      return true;
-    }
+bool choose_axis1(const Geo& g, const FftPlan& pl, KernSet<T>& K) {
+  bool ok = false;
+  switch (g.n1) {
+#define X(N) \
+  case N: ok = axis1_special<T, N>(g, K); break;
+    LSH_SPECIAL_SIZES(X)
+#undef X
+    default: break;
   }
-  return false;
+  if (!ok) {
+    // runtime plan: widest tile (16, 4 or 1 columns) that fits
+    if (g.n3 >= 16 && plan_fits(pl, 48, 256) && (size_t)g.n1 * 48 * sizeof(C2<T>) <= 60 * 1024)
+      put_axis1<T, 0, 16>(K);
+    else if (g.n3 >= 4 && plan_fits(pl, 12, 256) && (size_t)g.n1 * 12 * sizeof(C2<T>) <= 60 * 1024)
+      put_axis1<T, 0, 4>(K);
+    else if (plan_fits(pl, 3, 256))
+      put_axis1<T, 0, 1>(K);
+    else
+      return false;
+  }
+  K.lds1 = sizeof(C2<T>) * ((size_t)g.n1 + (size_t)g.n1 * 3 * K.W1) + sizeof(T) * 36 * 16;
+  return K.lds1 <= (size_t)lds_limit();
+}
+
+template <typename T, int NC, int W>
+void put_axis2(KernSet<T>& K) {
+  K.a2[0] = k_axis2<T, -1, NC, W, 256>;
+  K.a2[1] = k_axis2<T, +1, NC, W, 256>;
+  K.W2 = W;
+  K.NT2 = 256;
+}
+
+template <typename T, int NC>
+bool axis2_special(const Geo& g, KernSet<T>& K) {
+  constexpr int W = pick_w(NC, (int)sizeof(C2<T>), sizeof(T) == 8 ? 16 : 32, 32 * 1024);
+  if (g.n3 < W) return false;
+  put_axis2<T, NC, W>(K);
+  return true;
 }
 
 template <typename T>
-bool choose_green(const Geo& g, const FftPlan& pl, Launch* out, int* ls, int* cacheG) {
-  *ls = g.n3 + ((g.n3 % 2 == 0) ? 1 : 0);
-  for (int nthr = 64; nthr <= 512; nthr *= 2) {
-    if (!plan_fits(pl, 6, nthr)) continue;
-    if (nthr < std::min(512, g.n3)) continue;  // about one bin per thread
-    size_t lds = sizeof(C2<T>) * 6 * (size_t)(*ls);
-    const size_t gbytes = sizeof(T) * 21 * (size_t)g.n3;
-    *cacheG = (lds + gbytes <= 64 * 1024) ? 1 : 0;
-    if (*cacheG) lds += gbytes;
-    if (lds > 64 * 1024) return false;
-    out->W = 1;
-    out->nthr = nthr;
-    out->lds = lds;
-    return true;
+bool choose_axis2(const Geo& g, const FftPlan& pl, KernSet<T>& K) {
+  bool ok = false;
+  switch (g.n2) {
+#define X(N) \
+  case N: ok = axis2_special<T, N>(g, K); break;
+    LSH_SPECIAL_SIZES(X)
+#undef X
+    default: break;
   }
-  return false;
+  if (!ok) {
+    if (g.n3 >= 16 && plan_fits(pl, 16, 256) && (size_t)g.n2 * 16 * sizeof(C2<T>) <= 60 * 1024)
+      put_axis2<T, 0, 16>(K);
+    else if (g.n3 >= 4 && plan_fits(pl, 4, 256) && (size_t)g.n2 * 4 * sizeof(C2<T>) <= 60 * 1024)
+      put_axis2<T, 0, 4>(K);
+    else if (plan_fits(pl, 1, 256))
+      put_axis2<T, 0, 1>(K);
+    else
+      return false;
+  }
+  K.lds2 = sizeof(C2<T>) * ((size_t)g.n2 + (size_t)g.n2 * K.W2);
+  return K.lds2 <= (size_t)lds_limit();
 }
 
-struct Plans {
-  Launch a1, a2, gr;
-  int ls, cacheG;
-};
+template <typename T, int NC>
+void green_special(KernSet<T>& K) {
+  constexpr int NT = NC <= 64 ? 64 : (NC <= 128 ? 128 : 256);
+  K.gr = k_green<T, NC, NT>;
+  K.NTG = NT;
+}
 
 template <typename T>
-int make_plans(const lsh_pattern* p, Plans* P) {
+bool choose_green(const Geo& g, const FftPlan& pl, bool table, KernSet<T>& K) {
+  bool ok = false;
+  switch (g.n3) {
+#define X(N) \
+  case N: green_special<T, N>(K); ok = true; break;
+    LSH_SPECIAL_SIZES(X)
+#undef X
+    default: break;
+  }
+  if (!ok) {
+    int nt = 64;
+    while (nt < 256 && (nt < g.n3 || !plan_fits(pl, 6, nt))) nt *= 2;
+    if (!plan_fits(pl, 6, nt)) return false;
+    if (nt == 64) K.gr = k_green<T, 0, 64>;
+    else if (nt == 128) K.gr = k_green<T, 0, 128>;
+    else K.gr = k_green<T, 0, 256>;
+    K.NTG = nt;
+  }
+  K.lsG = g.n3 + ((g.n3 % 2 == 0) ? 1 : 0);
+  (void)table;
+  K.ldsG = sizeof(C2<T>) * ((size_t)g.n3 + 6 * (size_t)K.lsG);
+  return K.ldsG <= (size_t)lds_limit();
+}
+
+// The frequency reduction on the GPU uses double-estimated quotients, exact
+// while |sign(det) adj(M^T) V^T b| < 2^51 for every grid index b.
+bool index_maps_in_range(const lsh_pattern* p) {
+  GreenParams gp;
+  lsh_green_params(p, &gp);
+  long double hmax[3];
+  for (int i = 0; i < 3; ++i) {
+    hmax[i] = 0;
+    for (int k = 0; k < 3; ++k) hmax[i] += fabsl((long double)gp.VT[3 * i + k]) * (long double)(p->e[k] - 1);
+  }
+  for (int i = 0; i < 3; ++i) {
+    long double v = 0;
+    for (int k = 0; k < 3; ++k) v += fabsl((long double)gp.A[3 * i + k]) * (hmax[k] + 1.0L);
+    if (v + (long double)p->m >= 2251799813685248.0L) return false;
+  }
+  return true;
+}
+
+template <typename T>
+int make_kernels(const lsh_pattern* p, bool table, KernSet<T>* K) {
   const Geo g = geo_of(p);
+  if (!index_maps_in_range(p)) return lsh_fail(LSH_EUNSUPPORTED, "frequency index maps exceed 2^51");
   for (int i = 0; i < 3; ++i)
     if (p->plan[i].nst < 0)
       return lsh_fail(LSH_EUNSUPPORTED, "SNF factor e" + std::to_string(i + 1) + " = " + std::to_string(p->e[i]) +
                                             " has a prime factor above 13");
-  if (!choose_axis1<T>(g, p->plan[0], &P->a1)) return lsh_fail(LSH_EUNSUPPORTED, "SNF factor e1 too large for one block");
-  if (!choose_axis2<T>(g, p->plan[1], &P->a2)) return lsh_fail(LSH_EUNSUPPORTED, "SNF factor e2 too large for one block");
-  if (!choose_green<T>(g, p->plan[2], &P->gr, &P->ls, &P->cacheG))
-    return lsh_fail(LSH_EUNSUPPORTED, "SNF factor e3 too large for one block");
+  if (!choose_axis1<T>(g, p->plan[0], *K)) return lsh_fail(LSH_EUNSUPPORTED, "SNF factor e1 too large for one block");
+  if (!choose_axis2<T>(g, p->plan[1], *K)) return lsh_fail(LSH_EUNSUPPORTED, "SNF factor e2 too large for one block");
+  if (!choose_green<T>(g, p->plan[2], table, *K)) return lsh_fail(LSH_EUNSUPPORTED, "SNF factor e3 too large for one block");
   return LSH_OK;
+}
+
+// Allow dynamic LDS beyond the 64 KB default where a launch needs it.
+template <typename F>
+int allow_lds(F fn, size_t lds) {
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return lsh_fail(LSH_EUNSUPPORTED, std::string("LDS request refused: ") + hipGetErrorString(e));
+  }
+  return LSH_OK;
+}
+
+// Isotropic reference stiffness: Lame (lam0, mu0) if C0 has that form.
+bool c0_isotropic(const lsh_pattern* p, double* lam0, double* mu0) {
+  const double* C = p->C0_voigt;
+  const double lam = C[1], mu = C[21];
+  double mx = 0.0;
+  for (int i = 0; i < 36; ++i) mx = std::max(mx, fabs(C[i]));
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) {
+      double want = 0.0;
+      if (I < 3 && J < 3) want = lam + (I == J ? 2.0 * mu : 0.0);
+      if (I >= 3 && I == J) want = mu;
+      if (fabs(C[6 * I + J] - want) > 1e-13 * mx) return false;
+    }
+  *lam0 = lam;
+  *mu0 = mu;
+  return true;
+}
+
+// Which form of the Green operator the solver uses for this pattern.
+int green_mode(const lsh_pattern* p) {
+  double l, m;
+  if (p->kind == LSH_BOXSPLINE) return GREEN_TABLE;
+  if (p->nphase >= 1 && c0_isotropic(p, &l, &m)) return GREEN_ISO;
+  if (p->kind == LSH_DIRICHLET) return GREEN_GENERAL;
+  return GREEN_TABLE;
+}
+
+bool kind_has_table(const lsh_pattern* p) {
+  // before the stiffness is known, size for the table
+  if (p->nphase < 1) return p->kind != LSH_DIRICHLET;
+  return green_mode(p) == GREEN_TABLE;
 }
 
 template <typename T>
@@ -546,7 +311,7 @@ size_t persistent_bytes_t(const lsh_pattern* p, size_t scal) {
   for (int i = 0; i < 3; ++i) b += lsh_align(2 * scal * (size_t)std::max<int64_t>(p->e[i], 1));
   b += lsh_align(scal * 36 * 256) + lsh_align(sizeof(double) * 36 * 256);
   b += lsh_align(sizeof(double) * 4096);  // per-block minima of the bracket sums
-  if (p->kind == LSH_BOXSPLINE) b += lsh_align(scal * 21 * (size_t)g.spec);
+  if (kind_has_table(p)) b += lsh_align(scal * 21 * (size_t)g.spec);
   return b;
 }
 
@@ -559,8 +324,8 @@ Profile g_prof;
 
 template <typename T>
 int bind_t(lsh_pattern* p, void* dev, size_t bytes, hipStream_t st) {
-  Plans P;
-  int rc = make_plans<T>(p, &P);
+  KernSet<T> K;
+  int rc = make_kernels<T>(p, kind_has_table(p), &K);
   if (rc) return rc;
   const size_t need = persistent_bytes_t(p, sizeof(T));
   if (!dev || bytes < need) return lsh_fail(LSH_EWORKSPACE, "persistent buffer too small: need " + std::to_string(need));
@@ -600,7 +365,7 @@ int bind_t(lsh_pattern* p, void* dev, size_t bytes, hipStream_t st) {
   double* mins_dev = (double*)(base + off);
   off += lsh_align(sizeof(double) * 4096);
   p->has_table = false;
-  if (p->kind == LSH_BOXSPLINE) {
+  if (kind_has_table(p)) {
     const Geo g = geo_of(p);
     p->off_table = off;
     off += lsh_align(sizeof(T) * 21 * (size_t)g.spec);
@@ -641,7 +406,7 @@ struct WS {
 };
 
 template <typename T>
-WS ws_layout(const lsh_pattern* p, int nload, const Plans& P, char* base) {
+WS ws_layout(const lsh_pattern* p, int nload, const KernSet<T>& K, char* base) {
   const Geo g = geo_of(p);
   const size_t fb = lsh_align(sizeof(C2<T>) * 6 * (size_t)nload * g.spec);
   WS w;
@@ -650,7 +415,7 @@ WS ws_layout(const lsh_pattern* p, int nload, const Plans& P, char* base) {
   w.TAU = base + off; off += fb;
   w.P[0] = base + off; off += fb;
   w.P[1] = base + off; off += fb;
-  const long long nblkS = (long long)g.n2 * ((g.n3 + P.a1.W - 1) / P.a1.W);
+  const long long nblkS = (long long)g.n2 * ((g.n3 + K.W1 - 1) / K.W1);
   const long long nblkG = (long long)g.h1 * g.n2;
   const long long npart = std::max(nblkS * 6, nblkG * 2) * nload;
   w.partial = (double*)(base + off); off += lsh_align(sizeof(double) * npart);
@@ -723,14 +488,20 @@ int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int
             size_t ws_bytes, hipStream_t st, const double* dev_E_init, double* dev_E_out, double* sigma_out,
             lsh_stats* stats, double* history) {
   using T2 = C2<T>;
-  Plans P;
-  int rc = make_plans<T>(p, &P);
+  KernSet<T> K;
+  int rc = make_kernels<T>(p, p->has_table, &K);
+  if (rc) return rc;
+  rc = allow_lds(K.gr, K.ldsG);
   if (rc) return rc;
   const Geo g = geo_of(p);
-  WS w = ws_layout<T>(p, nload, P, (char*)dev_ws);
+  WS w = ws_layout<T>(p, nload, K, (char*)dev_ws);
   if (!dev_ws || ws_bytes < w.total) return lsh_fail(LSH_EWORKSPACE, "workspace too small: need " + std::to_string(w.total));
   GreenParams gp;
   lsh_green_params(p, &gp);
+  const int gmode = green_mode(p);
+  double lam0 = 0.0, mu0 = 1.0;
+  c0_isotropic(p, &lam0, &mu0);
+  const double riso = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
   char* base = p->dev_persist;
   const uint8_t* phase = (const uint8_t*)(base + p->off_phase);
   const T2* tw[3] = {(const T2*)(base + p->off_tw[0]), (const T2*)(base + p->off_tw[1]),
@@ -758,22 +529,23 @@ int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int
   HIPCHK(hipMemcpyAsync(w.nonfinite, nonfin.data(), sizeof(int) * nload, hipMemcpyHostToDevice, st));
   const size_t fb = sizeof(T2) * 6 * (size_t)nload * g.spec;
 
-  const int nt3a = (g.n3 + P.a1.W - 1) / P.a1.W;
+  const int nt3a = (g.n3 + K.W1 - 1) / K.W1;
   const dim3 gridS(g.n2 * nt3a, nload);
-  const int nt3b = (g.n3 + P.a2.W - 1) / P.a2.W;
+  const int nt3b = (g.n3 + K.W2 - 1) / K.W2;
   const dim3 gridB(g.h1 * nt3b, 6, nload);
-  const dim3 gridG(g.h1 * g.n2);
+  const int npos = g.h1 * g.n2;
+  const int npos8 = (npos + 7) / 8 * 8;
+  const dim3 gridG(npos8 * nload);
   const int nblkS = g.n2 * nt3a;
-  const int nblkG = g.h1 * g.n2;
 
-  int cur = 0;  // P[cur] holds the previous E(k1,k2,a3)
+  int cur = 0;  // P[cur] holds the previous iterate D12[E]/(n1 n2)
   if (dev_E_init) {
     hipLaunchKernelGGL(k_mean, dim3(nload, 6), dim3(1024), 0, st, dev_E_init, (long long)g.m, w.means);
-    hipLaunchKernelGGL((k_axis1<T, MODE_INIT>), gridS, dim3(P.a1.nthr), P.a1.lds, st, g, p->plan[0], tw[0],
-                       (const T2*)nullptr, (T2*)w.X, phase, dmat, cmat, w.eps0, w.stop_iter, 0, dev_E_init, w.means,
-                       (double*)nullptr, (double*)nullptr, P.a1.W);
-    hipLaunchKernelGGL((k_axis2<T, -1>), gridB, dim3(P.a2.nthr), P.a2.lds, st, g, p->plan[1], tw[1],
-                       (const T2*)w.X, (T2*)w.P[cur], (const int*)nullptr, 0, P.a2.W, (T)(1.0 / g.n2));
+    hipLaunchKernelGGL(K.a1[MODE_INIT], gridS, dim3(K.NT1), K.lds1, st, g, p->plan[0], tw[0], (const T2*)nullptr,
+                       (T2*)w.X, phase, dmat, p->nphase, cmat, w.eps0, w.stop_iter, 0, dev_E_init, w.means,
+                       (double*)nullptr, (double*)nullptr);
+    hipLaunchKernelGGL(K.a2[0], gridB, dim3(K.NT2), K.lds2, st, g, p->plan[1], tw[1], (const T2*)w.X,
+                       (T2*)w.P[cur], (const int*)nullptr, 0, (T)(1.0 / g.n2));
     HIPCHK(hipGetLastError());
   } else {
     HIPCHK(hipMemsetAsync(w.X, 0, fb, st));
@@ -793,30 +565,30 @@ int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int
   for (it = 0; it < max_iter; ++it) {
     {
       Timer tm(0, st);
-      hipLaunchKernelGGL((k_axis1<T, MODE_STRESS>), gridS, dim3(P.a1.nthr), P.a1.lds, st, g, p->plan[0], tw[0],
-                         (const T2*)w.X, (T2*)w.TAU, phase, dmat, cmat, w.eps0, w.stop_iter, it,
-                         (const double*)nullptr, (const double*)nullptr, (double*)nullptr, (double*)nullptr, P.a1.W);
+      hipLaunchKernelGGL(K.a1[MODE_STRESS], gridS, dim3(K.NT1), K.lds1, st, g, p->plan[0], tw[0], (const T2*)w.X,
+                         (T2*)w.TAU, phase, dmat, p->nphase, cmat, w.eps0, w.stop_iter, it, (const double*)nullptr,
+                         (const double*)nullptr, (double*)nullptr, (double*)nullptr);
     }
     {
       Timer tm(1, st);
-      hipLaunchKernelGGL((k_axis2<T, -1>), gridB, dim3(P.a2.nthr), P.a2.lds, st, g, p->plan[1], tw[1],
-                         (const T2*)w.TAU, (T2*)w.TAU, w.stop_iter, it, P.a2.W, (T)1);
+      hipLaunchKernelGGL(K.a2[0], gridB, dim3(K.NT2), K.lds2, st, g, p->plan[1], tw[1], (const T2*)w.TAU,
+                         (T2*)w.TAU, w.stop_iter, it, (T)1);
     }
     {
       Timer tm(2, st);
-      hipLaunchKernelGGL((k_green<T>), gridG, dim3(P.gr.nthr), P.gr.lds, st, g, p->plan[2], tw[2], gp,
-                         (const T2*)w.TAU, (const T2*)w.P[cur], (T2*)w.P[1 - cur], table, w.stop_iter, it, nload,
-                         w.partial, P.ls, P.cacheG);
+      hipLaunchKernelGGL(K.gr, gridG, dim3(K.NTG), K.ldsG, st, g, p->plan[2], tw[2], gp, (const T2*)w.TAU,
+                         (const T2*)w.P[cur], (T2*)w.P[1 - cur], table, w.stop_iter, it, nload, npos, w.partial,
+                         K.lsG, gmode, mu0, riso);
     }
     {
       Timer tm(3, st);
-      hipLaunchKernelGGL(k_finalize_resid, dim3(nload), dim3(256), 0, st, w.partial, nblkG, nload, w.e0sq, pscale, tol,
+      hipLaunchKernelGGL(k_finalize_resid, dim3(nload), dim3(256), 0, st, w.partial, npos, nload, w.e0sq, pscale, tol,
                          fixed ? 1 : 0, it, w.stop_iter, w.hist, w.nonfinite);
     }
     {
       Timer tm(4, st);
-      hipLaunchKernelGGL((k_axis2<T, +1>), gridB, dim3(P.a2.nthr), P.a2.lds, st, g, p->plan[1], tw[1],
-                         (const T2*)w.P[1 - cur], (T2*)w.X, w.stop_iter, it, P.a2.W, (T)1);
+      hipLaunchKernelGGL(K.a2[1], gridB, dim3(K.NT2), K.lds2, st, g, p->plan[1], tw[1], (const T2*)w.P[1 - cur],
+                         (T2*)w.X, w.stop_iter, it, (T)1);
     }
     HIPCHK(hipGetLastError());
     cur = 1 - cur;
@@ -826,7 +598,7 @@ int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int
       HIPCHK(hipMemcpyAsync(stop.data(), w.stop_iter, sizeof(int) * nload, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       if (g_prof.on) g_ev.flush();
-      // copy the ring entries of iterations (it+1-k .. it] that are not yet copied
+      // copy the ring entries of iterations (it+1-64 .. it] that are not yet copied
       const int first = std::max(0, it + 1 - LSH_HIST);
       if (history)
         for (int j = first; j <= it; ++j)
@@ -845,9 +617,9 @@ int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int
   // final pass: sigma_bar at the last iterate, optional E out
   {
     Timer tm(5, st);
-    hipLaunchKernelGGL((k_axis1<T, MODE_FINAL>), gridS, dim3(P.a1.nthr), P.a1.lds, st, g, p->plan[0], tw[0],
-                       (const T2*)w.X, (T2*)nullptr, phase, dmat, cmat, w.eps0, w.stop_iter, 0,
-                       (const double*)nullptr, (const double*)nullptr, dev_E_out, w.partial, P.a1.W);
+    hipLaunchKernelGGL(K.a1[MODE_FINAL], gridS, dim3(K.NT1), K.lds1, st, g, p->plan[0], tw[0], (const T2*)w.X,
+                       (T2*)nullptr, phase, dmat, p->nphase, cmat, w.eps0, w.stop_iter, 0, (const double*)nullptr,
+                       (const double*)nullptr, dev_E_out, w.partial);
     hipLaunchKernelGGL(k_finalize_sum, dim3(nload, 6), dim3(256), 0, st, w.partial, nblkS, 6, 1.0 / (double)g.m,
                        w.sigma);
   }
@@ -899,8 +671,10 @@ int probe_t(const lsh_pattern* p, const int64_t* bins, int n, double* out, void*
     const T* table = (const T*)(p->dev_persist + p->off_table);
     hipLaunchKernelGGL((k_cast_table<T>), dim3((n + 127) / 128), dim3(128), 0, st, table, dout, dbins, n, g);
   } else {
-    hipLaunchKernelGGL(k_gamma_probe, dim3((n + 127) / 128), dim3(128), 0, st, gp, dbins, n, (const double*)nullptr,
-                       0, g, dout);
+    double lam0 = 0.0, mu0 = 1.0;
+    c0_isotropic(p, &lam0, &mu0);
+    hipLaunchKernelGGL(k_gamma_probe, dim3((n + 127) / 128), dim3(128), 0, st, gp, dbins, n, dout, green_mode(p), mu0,
+                       (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0)));
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(out, dout, sizeof(double) * 21 * n, hipMemcpyDeviceToHost, st));
@@ -944,15 +718,15 @@ extern "C" int lsh_solve_bytes(const lsh_pattern* p, int nload, lsh_precision pr
   if (!p || !bytes) return lsh_fail(LSH_EINVAL, "null argument");
   if (nload < 1 || nload > 64) return lsh_fail(LSH_EINVAL, "nload must be in [1, 64]");
   if (prec == LSH_FP64) {
-    Plans P;
-    int rc = make_plans<double>(p, &P);
+    KernSet<double> K;
+    int rc = make_kernels<double>(p, kind_has_table(p), &K);
     if (rc) return rc;
-    *bytes = ws_layout<double>(p, nload, P, nullptr).total;
+    *bytes = ws_layout<double>(p, nload, K, nullptr).total;
   } else if (prec == LSH_FP32_MIXED) {
-    Plans P;
-    int rc = make_plans<float>(p, &P);
+    KernSet<float> K;
+    int rc = make_kernels<float>(p, kind_has_table(p), &K);
     if (rc) return rc;
-    *bytes = ws_layout<float>(p, nload, P, nullptr).total;
+    *bytes = ws_layout<float>(p, nload, K, nullptr).total;
   } else {
     return lsh_fail(LSH_EINVAL, "bad precision");
   }

@@ -103,6 +103,40 @@ def test_gamma_table_sampled_cfg3_box():
     np.testing.assert_allclose(got, ref[:, iu[0], iu[1]], rtol=0, atol=5e-12)
 
 
+def _anisotropic_C0():
+    """An elliptic, cubic-anisotropic reference stiffness (not isotropic)."""
+    C = li.isotropic_voigt(4.0, 0.25)
+    C[0, 1] = C[1, 0] = C[0, 1] + 0.3
+    C[3, 3] += 0.4
+    C[5, 5] -= 0.2
+    return C
+
+
+@pytest.mark.parametrize("kind,params", KERNELS)
+def test_gamma_probe_anisotropic_C0(kind, params):
+    """General (non-isotropic) C0: the on-the-fly general form (Dirichlet) and
+    the tabled alias sums (dlVP, Box) against the oracle at every bin."""
+    from oracle import green
+    Cp, _ = two_phase()
+    C0 = _anisotropic_C0()
+    pr = Problem([[6, -3, 2], [1, 4, 0], [2, 0, 3]], kind, params, random_phase(2), Cp, C0)
+    pr.bind("fp64")
+    e = pr.G.e
+    bins = np.array([(a, b, c) for a in range(e[0] // 2 + 1) for b in range(e[1]) for c in range(e[2])])
+    got = pr.G.gamma_probe(bins)
+    _, V = pr.G.snf()
+    ref, _ = green.gamma_symmetrised_at(pr.O, C0, kind, params, bins @ V)
+    iu = np.triu_indices(6)
+    np.testing.assert_allclose(got, ref[:, iu[0], iu[1]], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("kind,params", [KERNELS[0], KERNELS[2]])
+def test_lockstep_anisotropic_C0(kind, params):
+    Cp, _ = two_phase()
+    pr = Problem(np.diag([8, 12, 10]), kind, params, random_phase(9), Cp, _anisotropic_C0())
+    _lockstep(pr, "fp64", np.array([0.3, -0.2, 0.1, 0.4, -0.1, 0.25]), 6, FP64_TOL)
+
+
 # --------------------------------------------------------------- solver ---
 def _lockstep(pr, prec, eps0, n_iter, tol_rel):
     pr.bind(prec)
