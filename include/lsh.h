@@ -177,6 +177,36 @@ int lsh_solve(lsh_pattern *p, int nload, const double *eps0_voigt, double tol, i
               const double *dev_E_init, double *dev_E_out, double *sigma_out,
               lsh_stats *stats, double *history);
 
+/* -------------------------------------------------------------------- batches ---
+ * Many microstructures and load cases in one call (the Basic Scheme of Sec. 4 for
+ * each task, all advanced together).  Tasks whose patterns share M, the SNF
+ * grid and the generating function form one group: each iteration is one set
+ * of launches per group, and the iterations of all groups are captured in one
+ * HIP graph that is replayed (two iterations per replay) on a non-default
+ * stream; on the default stream the launches are issued one by one.
+ *   p          : a pattern bound at prec; within a group either every C0 is
+ *                isotropic (the Green operator is evaluated per instance) or all
+ *                share the same C0.
+ *   nload      : load cases of this task (>= 1).
+ *   eps0_voigt : host nload*6 macroscopic strains; sigma_out host nload*6.
+ *   stats      : optional host nload entries.
+ * No start field and no field output in batch mode.                               */
+typedef struct {
+  lsh_pattern *p;
+  int nload;
+  const double *eps0_voigt;
+  double *sigma_out;
+  lsh_stats *stats;
+} lsh_task;
+
+/* Workspace bytes for lsh_solve_batch over these tasks.                            */
+int lsh_batch_bytes(const lsh_task *tasks, int ntask, lsh_precision prec, size_t *bytes);
+
+/* Solve every task; same tolerance semantics and statuses as lsh_solve.
+ * Synchronises `stream` before returning.                                          */
+int lsh_solve_batch(const lsh_task *tasks, int ntask, double tol, int max_iter, lsh_precision prec,
+                    void *dev_workspace, size_t ws_bytes, void *stream);
+
 /* --------------------------------------------------------------- diagnostics ---
  * Per-kernel GPU time, from HIP event pairs recorded on the solve stream around
  * every launch and read back at the solver's own synchronisation points.

@@ -72,27 +72,55 @@ def rsa_spheres(seed, lattice_unit, fraction, rmin=6.0, rmax=12.0, max_attempts=
     vol = 0.0
     target = float(fraction)
     rlo = rmin * lattice_unit
-    for _ in range(max_attempts):
-        if vol >= target:
-            break
-        r = rng.uniform(rmin, rmax) * lattice_unit
-        c = rng.uniform(-0.5, 0.5, size=3)
-        rest = target - vol
-        v = 4.0 / 3.0 * np.pi * r ** 3
-        if v > rest:
-            r_fit = (3.0 * rest / (4.0 * np.pi)) ** (1.0 / 3.0)
-            if r_fit >= rlo:
-                r = r_fit
-                v = rest
+    attempts = 0
+    batch = 2048
+    while attempts < max_attempts and vol < target:
+        # draws in the same order as one attempt at a time: r, c0, c1, c2
+        u = rng.random((batch, 4))
+        cand_r = (rmin + (rmax - rmin) * u[:, 0]) * lattice_unit
+        cand_c = -0.5 + u[:, 1:]
+        # candidates already overlapping an accepted sphere at their largest radius
         if centres:
             C = np.array(centres)
-            d = C - c[None, :]
+            d = cand_c[:, None, :] - C[None, :, :]
             d -= np.round(d)
-            if np.any(np.sqrt(np.einsum("ij,ij->i", d, d)) < np.array(radii) + r):
-                continue
-        centres.append(c)
-        radii.append(r)
-        vol += v
+            dist = np.sqrt(np.einsum("kij,kij->ki", d, d))
+            hit = np.any(dist < np.array(radii)[None, :] + cand_r[:, None], axis=1)
+        else:
+            hit = np.zeros(batch, dtype=bool)
+        vk = 4.0 / 3.0 * np.pi * cand_r ** 3
+        k = 0
+        while k < batch and attempts < max_attempts and vol < target:
+            # next candidate that is not already excluded (or that the final
+            # shrink could still admit); the skipped ones count as attempts
+            live = np.flatnonzero(~hit[k:] | (vk[k:] > target - vol))
+            if len(live) == 0:
+                attempts += batch - k
+                break
+            j = k + int(live[0])
+            attempts += j - k
+            if attempts >= max_attempts:
+                break
+            attempts += 1
+            k = j + 1
+            r = cand_r[j]
+            c = cand_c[j]
+            rest = target - vol
+            v = vk[j]
+            if v > rest:
+                r_fit = (3.0 * rest / (4.0 * np.pi)) ** (1.0 / 3.0)
+                if r_fit >= rlo:
+                    r = r_fit
+                    v = rest
+            if centres:
+                C = np.array(centres)
+                d = C - c[None, :]
+                d -= np.round(d)
+                if np.any(np.sqrt(np.einsum("ij,ij->i", d, d)) < np.array(radii) + r):
+                    continue
+            centres.append(c)
+            radii.append(r)
+            vol += v
     return np.array(centres).reshape(-1, 3), np.array(radii)
 
 
@@ -119,3 +147,34 @@ def random_unit_load(rng):
 def lattice_unit(m):
     """Length of one lattice step of an m-point pattern in cell units: m^{-1/3}."""
     return float(m) ** (-1.0 / 3.0)
+
+
+def grid_points_numerators(n):
+    """Numerators (over n^3) of the points of the regular n x n x n pattern in
+    row-major index order, each coordinate a_i/n wrapped into [-1/2, 1/2).
+    Used to check that a pattern's storage order is this plain grid order."""
+    a = np.arange(n)
+    c = ((a + n // 2) % n) - n // 2           # a/n wrapped, times n
+    g = np.stack(np.meshgrid(c, c, c, indexing="ij"), -1).reshape(-1, 3)
+    return g.astype(np.int64) * (n * n)
+
+
+def spheres_phase_grid(n, centres, radii):
+    """spheres_phase for the regular n^3 grid in row-major order, touching only
+    each sphere's bounding box (same inside rule: periodic distance < r)."""
+    ph = np.zeros((n, n, n), dtype=np.uint8)
+    for c, r in zip(np.asarray(centres), np.asarray(radii)):
+        rg = int(np.ceil(r * n)) + 1
+        axes = []
+        for i in range(3):
+            k0 = int(np.floor(c[i] * n))
+            ks = np.arange(k0 - rg, k0 + rg + 2)
+            y = ks / n
+            d = y - c[i]
+            d -= np.round(d)
+            axes.append((ks % n, d))
+        (i0, d0), (i1, d1), (i2, d2) = axes
+        inside = (d0[:, None, None] ** 2 + d1[None, :, None] ** 2 + d2[None, None, :] ** 2) < r * r
+        ii = np.ix_(i0, i1, i2)
+        ph[ii] |= inside.astype(np.uint8)
+    return ph.reshape(-1)

@@ -34,6 +34,19 @@ template <typename T> using C2 = typename cpx<T>::t;
 
 enum { MODE_STRESS = 0, MODE_FINAL = 1, MODE_INIT = 2 };
 
+// One microstructure: its phase map and per-phase stiffness, and the isotropic
+// reference constants used by the on-the-fly Green operator.  A solve holds
+// one or many (batched) instances; load case L belongs to instance inst_of[L].
+struct Inst {
+  const uint8_t* phase;  // m phase indices, storage order
+  const void* dmat;      // (C_p - C0) at the working precision, 36 per phase, Mandel
+  const double* cmat;    // C_p in double, 36 per phase, Mandel
+  int nphase;
+  int pad_;
+  double mu0;   // isotropic C0: shear modulus
+  double riso;  // (lam0 + mu0) / (mu0 (lam0 + 2 mu0))
+};
+
 // ------------------------------------------------------------ reductions ---
 template <int NV>
 __device__ void block_sum(double v[NV], double* out) {
@@ -82,10 +95,9 @@ __device__ __forceinline__ void stress6(const T* D, const T E[6], T t[6]) {
 template <typename T, int MODE, int NC, int W, int NT>
 __global__ void __launch_bounds__(NT) k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
                                               const C2<T>* __restrict__ X, C2<T>* __restrict__ Y,
-                                              const uint8_t* __restrict__ phase, const T* __restrict__ dmat,
-                                              int nphase, const double* __restrict__ cmat,
+                                              const Inst* __restrict__ insts, const int* __restrict__ inst_of,
                                               const double* __restrict__ eps0, const int* __restrict__ stop_iter,
-                                              int it, const double* __restrict__ Einit,
+                                              const int* __restrict__ itp, const double* __restrict__ Einit,
                                               const double* __restrict__ means, double* __restrict__ Eout,
                                               double* __restrict__ partial) {
   using T2 = C2<T>;
@@ -98,7 +110,12 @@ __global__ void __launch_bounds__(NT) k_axis1(Geo g, FftPlan pl, const C2<T>* __
   T2* Z = twl + n1;
   T* Dl = reinterpret_cast<T*>(Z + n1 * W3);
   const int L = blockIdx.y;
-  if (MODE == MODE_STRESS && it >= stop_iter[L]) return;
+  if (MODE == MODE_STRESS && *itp >= stop_iter[L]) return;
+  const Inst& in = insts[inst_of[L]];
+  const uint8_t* __restrict__ phase = in.phase;
+  const T* __restrict__ dmat = reinterpret_cast<const T*>(in.dmat);
+  const double* __restrict__ cmat = in.cmat;
+  const int nphase = in.nphase;
   const int ntile3 = (g.n3 + W - 1) / W;
   const int a2 = blockIdx.x / ntile3;
   const int a30 = (blockIdx.x % ntile3) * W;
@@ -272,14 +289,15 @@ __global__ void __launch_bounds__(NT) k_axis1(Geo g, FftPlan pl, const C2<T>* __
 template <typename T, int DIR, int NC, int W, int NT>
 __global__ void __launch_bounds__(NT) k_axis2(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
                                               const C2<T>* __restrict__ src, C2<T>* __restrict__ dst,
-                                              const int* __restrict__ stop_iter, int it, T scale) {
+                                              const int* __restrict__ stop_iter, const int* __restrict__ itp,
+                                              T scale) {
   using T2 = C2<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n2 = NC > 0 ? NC : g.n2;
   T2* twl = reinterpret_cast<T2*>(smem_raw);
   T2* Z = twl + n2;
   const int L = blockIdx.z, c = blockIdx.y;
-  if (stop_iter && it >= stop_iter[L]) return;
+  if (stop_iter && *itp >= stop_iter[L]) return;
   const int ntile3 = (g.n3 + W - 1) / W;
   const int k1 = blockIdx.x / ntile3;
   const int a30 = (blockIdx.x % ntile3) * W;
@@ -328,9 +346,9 @@ template <typename T, int NC, int NT>
 __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __restrict__ tw, GreenParams gp,
                                               const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
                                               C2<T>* __restrict__ Pnew, const T* __restrict__ table,
-                                              const int* __restrict__ stop_iter, int it, int nload, int npos,
-                                              double* __restrict__ partial, int ls, int gmode, double mu0,
-                                              double riso) {
+                                              const Inst* __restrict__ insts, const int* __restrict__ inst_of,
+                                              const int* __restrict__ stop_iter, const int* __restrict__ itp,
+                                              int nload, int npos, double* __restrict__ partial, int ls, int gmode) {
   using T2 = C2<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n3 = NC > 0 ? NC : g.n3;
@@ -340,7 +358,8 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int pos = (slot / nload) * 8 + xcd;
   const int L = slot % nload;
-  if (pos >= npos || it >= stop_iter[L]) return;
+  if (pos >= npos || *itp >= stop_iter[L]) return;
+  const double mu0 = insts[inst_of[L]].mu0, riso = insts[inst_of[L]].riso;
   const int k1 = pos / g.n2, k2 = pos % g.n2;
   const int tid = threadIdx.x;
   const double scale = -1.0 / (double)g.m;
@@ -442,9 +461,11 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
 
 // ------------------------------------------------------------ finalisers ---
 __global__ void k_finalize_resid(const double* __restrict__ partial, int nblk, int nload,
-                                 const double* __restrict__ e0sq, double pscale, double tol, int fixed, int it,
-                                 int* __restrict__ stop_iter, double* __restrict__ hist, int* __restrict__ nonfinite) {
+                                 const double* __restrict__ e0sq, double pscale, double tol, int fixed,
+                                 const int* __restrict__ itp, int* __restrict__ stop_iter, double* __restrict__ hist,
+                                 int* __restrict__ nonfinite) {
   const int L = blockIdx.x;
+  const int it = *itp;
   if (it >= stop_iter[L]) return;
   double s[2] = {0.0, 0.0};
   for (int j = threadIdx.x; j < nblk; j += blockDim.x) {
@@ -465,6 +486,11 @@ __global__ void k_finalize_resid(const double* __restrict__ partial, int nblk, i
       stop_iter[L] = it + 1;
     }
   }
+}
+
+// end of an iteration: advance the device-side iteration counter
+__global__ void k_advance(int* itp) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *itp += 1;
 }
 
 __global__ void k_finalize_sum(const double* __restrict__ partial, int nblk, int nv, double scale,

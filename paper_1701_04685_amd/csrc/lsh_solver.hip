@@ -78,11 +78,11 @@ int lds_limit() {
 // The kernel instantiations chosen for one pattern and precision.
 template <typename T>
 struct KernSet {
-  using A1 = void (*)(Geo, FftPlan, const C2<T>*, const C2<T>*, C2<T>*, const uint8_t*, const T*, int,
-                      const double*, const double*, const int*, int, const double*, const double*, double*, double*);
-  using A2 = void (*)(Geo, FftPlan, const C2<T>*, const C2<T>*, C2<T>*, const int*, int, T);
+  using A1 = void (*)(Geo, FftPlan, const C2<T>*, const C2<T>*, C2<T>*, const Inst*, const int*, const double*,
+                      const int*, const int*, const double*, const double*, double*, double*);
+  using A2 = void (*)(Geo, FftPlan, const C2<T>*, const C2<T>*, C2<T>*, const int*, const int*, T);
   using GR = void (*)(Geo, FftPlan, const C2<T>*, GreenParams, const C2<T>*, const C2<T>*, C2<T>*, const T*,
-                      const int*, int, int, int, double*, int, int, double, double);
+                      const Inst*, const int*, const int*, const int*, int, int, double*, int, int);
   A1 a1[3] = {nullptr, nullptr, nullptr};  // MODE_STRESS, MODE_FINAL, MODE_INIT
   A2 a2[2] = {nullptr, nullptr};           // forward, inverse
   GR gr = nullptr;
@@ -390,7 +390,9 @@ int bind_t(lsh_pattern* p, void* dev, size_t bytes, hipStream_t st) {
   return LSH_OK;
 }
 
-struct WS {
+// One group of load cases that share the SNF grid, M, the generating function
+// and the kernel instantiations: a single solve, or one size class of a batch.
+struct GroupWS {
   char* X;
   char* TAU;
   char* P[2];
@@ -402,14 +404,16 @@ struct WS {
   double* means;
   int* stop_iter;
   int* nonfinite;
+  int* itp;
+  int* inst_of;
+  Inst* insts;
   size_t total;
 };
 
 template <typename T>
-WS ws_layout(const lsh_pattern* p, int nload, const KernSet<T>& K, char* base) {
-  const Geo g = geo_of(p);
+GroupWS group_layout(const Geo& g, int nload, int ninst, const KernSet<T>& K, char* base) {
   const size_t fb = lsh_align(sizeof(C2<T>) * 6 * (size_t)nload * g.spec);
-  WS w;
+  GroupWS w;
   size_t off = 0;
   w.X = base + off; off += fb;
   w.TAU = base + off; off += fb;
@@ -426,6 +430,9 @@ WS ws_layout(const lsh_pattern* p, int nload, const KernSet<T>& K, char* base) {
   w.means = (double*)(base + off); off += lsh_align(sizeof(double) * 6 * nload);
   w.stop_iter = (int*)(base + off); off += lsh_align(sizeof(int) * nload);
   w.nonfinite = (int*)(base + off); off += lsh_align(sizeof(int) * nload);
+  w.itp = (int*)(base + off); off += lsh_align(sizeof(int));
+  w.inst_of = (int*)(base + off); off += lsh_align(sizeof(int) * nload);
+  w.insts = (Inst*)(base + off); off += lsh_align(sizeof(Inst) * ninst);
   w.total = off;
   return w;
 }
@@ -483,173 +490,410 @@ struct Timer {
   }
 };
 
+// Host-side description of one instance (a bound pattern) in a group.
 template <typename T>
-int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int max_iter, void* dev_ws,
-            size_t ws_bytes, hipStream_t st, const double* dev_E_init, double* dev_E_out, double* sigma_out,
-            lsh_stats* stats, double* history) {
-  using T2 = C2<T>;
-  KernSet<T> K;
-  int rc = make_kernels<T>(p, p->has_table, &K);
-  if (rc) return rc;
-  rc = allow_lds(K.gr, K.ldsG);
-  if (rc) return rc;
-  const Geo g = geo_of(p);
-  WS w = ws_layout<T>(p, nload, K, (char*)dev_ws);
-  if (!dev_ws || ws_bytes < w.total) return lsh_fail(LSH_EWORKSPACE, "workspace too small: need " + std::to_string(w.total));
-  GreenParams gp;
-  lsh_green_params(p, &gp);
-  const int gmode = green_mode(p);
+Inst inst_of_pattern(const lsh_pattern* p) {
+  Inst in;
+  char* base = p->dev_persist;
+  in.phase = (const uint8_t*)(base + p->off_phase);
+  in.dmat = (const void*)(base + p->off_dmat);
+  in.cmat = (const double*)(base + p->off_cmat);
+  in.nphase = p->nphase;
+  in.pad_ = 0;
   double lam0 = 0.0, mu0 = 1.0;
   c0_isotropic(p, &lam0, &mu0);
-  const double riso = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
-  char* base = p->dev_persist;
-  const uint8_t* phase = (const uint8_t*)(base + p->off_phase);
-  const T2* tw[3] = {(const T2*)(base + p->off_tw[0]), (const T2*)(base + p->off_tw[1]),
-                     (const T2*)(base + p->off_tw[2])};
-  const T* dmat = (const T*)(base + p->off_dmat);
-  const double* cmat = (const double*)(base + p->off_cmat);
-  const T* table = p->has_table ? (const T*)(base + p->off_table) : nullptr;
+  in.mu0 = mu0;
+  in.riso = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
+  return in;
+}
 
-  // host-side setup: eps0 in Mandel, m |eps0|^2
+// The load cases of one group and where their results go.
+struct GroupSpec {
+  const lsh_pattern* rep;             // geometry, kernel, twiddles, table
+  std::vector<const lsh_pattern*> inst;
+  std::vector<int> inst_of;           // per load
+  std::vector<double> eps0_voigt;     // 6 per load
+  std::vector<double*> sigma_out;     // per load: 6 doubles
+  std::vector<lsh_stats*> stats;      // per load (may be null)
+  std::vector<double*> history;       // per load: max_iter doubles (may be null)
+};
+
+template <typename T>
+struct GroupRun {
+  GroupSpec spec;
+  KernSet<T> K;
+  Geo g;
+  GreenParams gp;
+  int gmode;
+  GroupWS w;
+  int nload;
+  dim3 gridS, gridB, gridG;
+  int npos, nblkS;
+  std::vector<int> stop;
+  std::vector<double> ring;
+};
+
+template <typename T>
+int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
+  const lsh_pattern* p = G.spec.rep;
+  int rc = make_kernels<T>(p, p->has_table, &G.K);
+  if (rc) return rc;
+  rc = allow_lds(G.K.gr, G.K.ldsG);
+  if (rc) return rc;
+  G.g = geo_of(p);
+  lsh_green_params(p, &G.gp);
+  G.gmode = green_mode(p);
+  G.nload = (int)G.spec.inst_of.size();
+  G.w = group_layout<T>(G.g, G.nload, (int)G.spec.inst.size(), G.K, base);
+  if (!base || avail < G.w.total) return lsh_fail(LSH_EWORKSPACE, "workspace too small");
+  *used = G.w.total;
+  const int nt3a = (G.g.n3 + G.K.W1 - 1) / G.K.W1;
+  G.gridS = dim3(G.g.n2 * nt3a, G.nload);
+  const int nt3b = (G.g.n3 + G.K.W2 - 1) / G.K.W2;
+  G.gridB = dim3(G.g.h1 * nt3b, 6, G.nload);
+  G.npos = G.g.h1 * G.g.n2;
+  G.gridG = dim3((G.npos + 7) / 8 * 8 * G.nload);
+  G.nblkS = G.g.n2 * nt3a;
+  return LSH_OK;
+}
+
+// Upload per-load constants and clear the state (zero start) or transform a start field.
+template <typename T>
+int group_init(GroupRun<T>& G, int max_iter, const double* dev_E_init, hipStream_t st) {
+  using T2 = C2<T>;
+  const int nload = G.nload;
   std::vector<double> e0(6 * nload), e0sq(nload);
   for (int L = 0; L < nload; ++L) {
     double s = 0.0;
     for (int c = 0; c < 6; ++c) {
-      const double v = eps0_voigt[6 * L + c] * (c < 3 ? 1.0 : M_SQRT1_2);
+      const double v = G.spec.eps0_voigt[6 * L + c] * (c < 3 ? 1.0 : M_SQRT1_2);
       e0[6 * L + c] = v;
       s += v * v;
     }
-    e0sq[L] = s * (double)p->m;
+    e0sq[L] = s * (double)G.g.m;
   }
-  const bool fixed = tol < 0.0;
-  std::vector<int> stop(nload, max_iter), nonfin(nload, 0);
-  HIPCHK(hipMemcpyAsync(w.eps0, e0.data(), sizeof(double) * 6 * nload, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(w.e0sq, e0sq.data(), sizeof(double) * nload, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(w.stop_iter, stop.data(), sizeof(int) * nload, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(w.nonfinite, nonfin.data(), sizeof(int) * nload, hipMemcpyHostToDevice, st));
-  const size_t fb = sizeof(T2) * 6 * (size_t)nload * g.spec;
-
-  const int nt3a = (g.n3 + K.W1 - 1) / K.W1;
-  const dim3 gridS(g.n2 * nt3a, nload);
-  const int nt3b = (g.n3 + K.W2 - 1) / K.W2;
-  const dim3 gridB(g.h1 * nt3b, 6, nload);
-  const int npos = g.h1 * g.n2;
-  const int npos8 = (npos + 7) / 8 * 8;
-  const dim3 gridG(npos8 * nload);
-  const int nblkS = g.n2 * nt3a;
-
-  int cur = 0;  // P[cur] holds the previous iterate D12[E]/(n1 n2)
+  std::vector<Inst> ins;
+  for (auto* q : G.spec.inst) ins.push_back(inst_of_pattern<T>(q));
+  G.stop.assign(nload, max_iter);
+  std::vector<int> zeros(nload, 0);
+  const int zero = 0;
+  HIPCHK(hipMemcpyAsync(G.w.eps0, e0.data(), sizeof(double) * 6 * nload, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(G.w.e0sq, e0sq.data(), sizeof(double) * nload, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(G.w.stop_iter, G.stop.data(), sizeof(int) * nload, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(G.w.nonfinite, zeros.data(), sizeof(int) * nload, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(G.w.itp, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(G.w.inst_of, G.spec.inst_of.data(), sizeof(int) * nload, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(G.w.insts, ins.data(), sizeof(Inst) * ins.size(), hipMemcpyHostToDevice, st));
+  const size_t fb = sizeof(T2) * 6 * (size_t)nload * G.g.spec;
+  const lsh_pattern* p = G.spec.rep;
+  char* base = p->dev_persist;
+  const T2* tw0 = (const T2*)(base + p->off_tw[0]);
+  const T2* tw1 = (const T2*)(base + p->off_tw[1]);
   if (dev_E_init) {
-    hipLaunchKernelGGL(k_mean, dim3(nload, 6), dim3(1024), 0, st, dev_E_init, (long long)g.m, w.means);
-    hipLaunchKernelGGL(K.a1[MODE_INIT], gridS, dim3(K.NT1), K.lds1, st, g, p->plan[0], tw[0], (const T2*)nullptr,
-                       (T2*)w.X, phase, dmat, p->nphase, cmat, w.eps0, w.stop_iter, 0, dev_E_init, w.means,
+    hipLaunchKernelGGL(k_mean, dim3(nload, 6), dim3(1024), 0, st, dev_E_init, (long long)G.g.m, G.w.means);
+    hipLaunchKernelGGL(G.K.a1[MODE_INIT], G.gridS, dim3(G.K.NT1), G.K.lds1, st, G.g, p->plan[0], tw0,
+                       (const T2*)nullptr, (T2*)G.w.X, (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0,
+                       (const int*)G.w.stop_iter, (const int*)G.w.itp, dev_E_init, (const double*)G.w.means,
                        (double*)nullptr, (double*)nullptr);
-    hipLaunchKernelGGL(K.a2[0], gridB, dim3(K.NT2), K.lds2, st, g, p->plan[1], tw[1], (const T2*)w.X,
-                       (T2*)w.P[cur], (const int*)nullptr, 0, (T)(1.0 / g.n2));
+    hipLaunchKernelGGL(G.K.a2[0], G.gridB, dim3(G.K.NT2), G.K.lds2, st, G.g, p->plan[1], tw1, (const T2*)G.w.X,
+                       (T2*)G.w.P[0], (const int*)nullptr, (const int*)nullptr, (T)(1.0 / G.g.n2));
     HIPCHK(hipGetLastError());
   } else {
-    HIPCHK(hipMemsetAsync(w.X, 0, fb, st));
-    HIPCHK(hipMemsetAsync(w.P[cur], 0, fb, st));
+    HIPCHK(hipMemsetAsync(G.w.X, 0, fb, st));
+    HIPCHK(hipMemsetAsync(G.w.P[0], 0, fb, st));
   }
+  G.ring.assign(LSH_HIST * nload, NAN);
+  return LSH_OK;
+}
 
-  // P(k1,k2,a3) = D12[E] / (n1 n2) (D12: unnormalised DFT over axes 1, 2), so by
-  // Parseval sum_y |E|^2 = n1 n2 sum_{k1,k2,a3} w_k1 |P|^2 (w: half-spectrum weight)
-  const double pscale = (double)g.n1 * (double)g.n2;
-  const auto t0 = std::chrono::steady_clock::now();
-  std::vector<double> ring(LSH_HIST * nload);
-  if (history)
-    for (long long i = 0; i < (long long)nload * max_iter; ++i) history[i] = NAN;
-  int it = 0;
-  int done_iters = 0;
-  const int check = fixed ? LSH_HIST : 8;
-  for (it = 0; it < max_iter; ++it) {
-    {
-      Timer tm(0, st);
-      hipLaunchKernelGGL(K.a1[MODE_STRESS], gridS, dim3(K.NT1), K.lds1, st, g, p->plan[0], tw[0], (const T2*)w.X,
-                         (T2*)w.TAU, phase, dmat, p->nphase, cmat, w.eps0, w.stop_iter, it, (const double*)nullptr,
-                         (const double*)nullptr, (double*)nullptr, (double*)nullptr);
-    }
-    {
-      Timer tm(1, st);
-      hipLaunchKernelGGL(K.a2[0], gridB, dim3(K.NT2), K.lds2, st, g, p->plan[1], tw[1], (const T2*)w.TAU,
-                         (T2*)w.TAU, w.stop_iter, it, (T)1);
-    }
-    {
-      Timer tm(2, st);
-      hipLaunchKernelGGL(K.gr, gridG, dim3(K.NTG), K.ldsG, st, g, p->plan[2], tw[2], gp, (const T2*)w.TAU,
-                         (const T2*)w.P[cur], (T2*)w.P[1 - cur], table, w.stop_iter, it, nload, npos, w.partial,
-                         K.lsG, gmode, mu0, riso);
-    }
-    {
-      Timer tm(3, st);
-      hipLaunchKernelGGL(k_finalize_resid, dim3(nload), dim3(256), 0, st, w.partial, npos, nload, w.e0sq, pscale, tol,
-                         fixed ? 1 : 0, it, w.stop_iter, w.hist, w.nonfinite);
-    }
-    {
-      Timer tm(4, st);
-      hipLaunchKernelGGL(K.a2[1], gridB, dim3(K.NT2), K.lds2, st, g, p->plan[1], tw[1], (const T2*)w.P[1 - cur],
-                         (T2*)w.X, w.stop_iter, it, (T)1);
-    }
-    HIPCHK(hipGetLastError());
-    cur = 1 - cur;
-    done_iters = it + 1;
-    if ((it + 1) % check == 0 || it + 1 == max_iter || (it + 1) % LSH_HIST == 0) {
-      HIPCHK(hipMemcpyAsync(ring.data(), w.hist, sizeof(double) * LSH_HIST * nload, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(stop.data(), w.stop_iter, sizeof(int) * nload, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (g_prof.on) g_ev.flush();
-      // copy the ring entries of iterations (it+1-64 .. it] that are not yet copied
-      const int first = std::max(0, it + 1 - LSH_HIST);
-      if (history)
-        for (int j = first; j <= it; ++j)
-          for (int L = 0; L < nload; ++L)
-            if (j < stop[L]) history[(long long)L * max_iter + j] = ring[(j % LSH_HIST) * nload + L];
-      bool all = true;
-      for (int L = 0; L < nload; ++L) all = all && stop[L] <= it + 1;
-      if (all) break;
-    }
+// Enqueue one Basic Scheme iteration of the group; `cur` picks which P buffer
+// holds the previous iterate.
+template <typename T>
+int group_iterate(GroupRun<T>& G, int cur, double tol, bool fixed, hipStream_t st) {
+  using T2 = C2<T>;
+  const lsh_pattern* p = G.spec.rep;
+  char* base = p->dev_persist;
+  const T2* tw[3] = {(const T2*)(base + p->off_tw[0]), (const T2*)(base + p->off_tw[1]),
+                     (const T2*)(base + p->off_tw[2])};
+  const T* table = p->has_table ? (const T*)(base + p->off_table) : nullptr;
+  const double pscale = (double)G.g.n1 * (double)G.g.n2;
+  {
+    Timer tm(0, st);
+    hipLaunchKernelGGL(G.K.a1[MODE_STRESS], G.gridS, dim3(G.K.NT1), G.K.lds1, st, G.g, p->plan[0], tw[0],
+                       (const T2*)G.w.X, (T2*)G.w.TAU, (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0,
+                       (const int*)G.w.stop_iter, (const int*)G.w.itp, (const double*)nullptr,
+                       (const double*)nullptr, (double*)nullptr, (double*)nullptr);
   }
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  HIPCHK(hipMemcpyAsync(ring.data(), w.hist, sizeof(double) * LSH_HIST * nload, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(stop.data(), w.stop_iter, sizeof(int) * nload, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(nonfin.data(), w.nonfinite, sizeof(int) * nload, hipMemcpyDeviceToHost, st));
+  {
+    Timer tm(1, st);
+    hipLaunchKernelGGL(G.K.a2[0], G.gridB, dim3(G.K.NT2), G.K.lds2, st, G.g, p->plan[1], tw[1], (const T2*)G.w.TAU,
+                       (T2*)G.w.TAU, (const int*)G.w.stop_iter, (const int*)G.w.itp, (T)1);
+  }
+  {
+    Timer tm(2, st);
+    hipLaunchKernelGGL(G.K.gr, G.gridG, dim3(G.K.NTG), G.K.ldsG, st, G.g, p->plan[2], tw[2], G.gp,
+                       (const T2*)G.w.TAU, (const T2*)G.w.P[cur], (T2*)G.w.P[1 - cur], table,
+                       (const Inst*)G.w.insts, (const int*)G.w.inst_of, (const int*)G.w.stop_iter,
+                       (const int*)G.w.itp, G.nload, G.npos, G.w.partial, G.K.lsG, G.gmode);
+  }
+  {
+    Timer tm(3, st);
+    hipLaunchKernelGGL(k_finalize_resid, dim3(G.nload), dim3(256), 0, st, (const double*)G.w.partial, G.npos,
+                       G.nload, (const double*)G.w.e0sq, pscale, tol, fixed ? 1 : 0, (const int*)G.w.itp,
+                       G.w.stop_iter, G.w.hist, G.w.nonfinite);
+  }
+  {
+    Timer tm(4, st);
+    hipLaunchKernelGGL(G.K.a2[1], G.gridB, dim3(G.K.NT2), G.K.lds2, st, G.g, p->plan[1], tw[1],
+                       (const T2*)G.w.P[1 - cur], (T2*)G.w.X, (const int*)G.w.stop_iter, (const int*)G.w.itp, (T)1);
+  }
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, G.w.itp);
+  HIPCHK(hipGetLastError());
+  return LSH_OK;
+}
 
-  // final pass: sigma_bar at the last iterate, optional E out
+// Copy the residual ring and stop flags back; returns true when every load stopped.
+template <typename T>
+int group_poll(GroupRun<T>& G, int done, int max_iter, hipStream_t st, bool* all_done) {
+  HIPCHK(hipMemcpyAsync(G.ring.data(), G.w.hist, sizeof(double) * LSH_HIST * G.nload, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(G.stop.data(), G.w.stop_iter, sizeof(int) * G.nload, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const int first = std::max(0, done - LSH_HIST);
+  for (int L = 0; L < G.nload; ++L) {
+    double* h = G.spec.history[L];
+    if (!h) continue;
+    for (int j = first; j < done && j < G.stop[L]; ++j) h[j] = G.ring[(j % LSH_HIST) * G.nload + L];
+  }
+  bool all = true;
+  for (int L = 0; L < G.nload; ++L) all = all && G.stop[L] <= done;
+  *all_done = all;
+  (void)max_iter;
+  return LSH_OK;
+}
+
+// Final pass: sigma_bar at the last iterate (and E out), stats; returns a status.
+template <typename T>
+int group_finish(GroupRun<T>& G, int done, double tol, bool fixed, double secs, double* dev_E_out, hipStream_t st) {
+  using T2 = C2<T>;
+  const lsh_pattern* p = G.spec.rep;
+  char* base = p->dev_persist;
+  const T2* tw0 = (const T2*)(base + p->off_tw[0]);
+  std::vector<int> nonfin(G.nload, 0);
+  HIPCHK(hipMemcpyAsync(nonfin.data(), G.w.nonfinite, sizeof(int) * G.nload, hipMemcpyDeviceToHost, st));
   {
     Timer tm(5, st);
-    hipLaunchKernelGGL(K.a1[MODE_FINAL], gridS, dim3(K.NT1), K.lds1, st, g, p->plan[0], tw[0], (const T2*)w.X,
-                       (T2*)nullptr, phase, dmat, p->nphase, cmat, w.eps0, w.stop_iter, 0, (const double*)nullptr,
-                       (const double*)nullptr, dev_E_out, w.partial);
-    hipLaunchKernelGGL(k_finalize_sum, dim3(nload, 6), dim3(256), 0, st, w.partial, nblkS, 6, 1.0 / (double)g.m,
-                       w.sigma);
+    hipLaunchKernelGGL(G.K.a1[MODE_FINAL], G.gridS, dim3(G.K.NT1), G.K.lds1, st, G.g, p->plan[0], tw0,
+                       (const T2*)G.w.X, (T2*)nullptr, (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0,
+                       (const int*)G.w.stop_iter, (const int*)G.w.itp, (const double*)nullptr,
+                       (const double*)nullptr, dev_E_out, G.w.partial);
+    hipLaunchKernelGGL(k_finalize_sum, dim3(G.nload, 6), dim3(256), 0, st, (const double*)G.w.partial, G.nblkS, 6,
+                       1.0 / (double)G.g.m, G.w.sigma);
   }
   HIPCHK(hipGetLastError());
-  std::vector<double> sig(6 * nload);
-  HIPCHK(hipMemcpyAsync(sig.data(), w.sigma, sizeof(double) * 6 * nload, hipMemcpyDeviceToHost, st));
+  std::vector<double> sig(6 * G.nload);
+  HIPCHK(hipMemcpyAsync(sig.data(), G.w.sigma, sizeof(double) * 6 * G.nload, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (g_prof.on) g_ev.flush();
   int status = LSH_OK;
-  for (int L = 0; L < nload; ++L) {
-    for (int c = 0; c < 6; ++c) sigma_out[6 * L + c] = sig[6 * L + c] * (c < 3 ? 1.0 : M_SQRT1_2);
-    const int its = std::min(stop[L], done_iters);
+  for (int L = 0; L < G.nload; ++L) {
+    for (int c = 0; c < 6; ++c) G.spec.sigma_out[L][c] = sig[6 * L + c] * (c < 3 ? 1.0 : M_SQRT1_2);
+    const int its = std::min(G.stop[L], done);
     double last = NAN;
-    if (its > 0) last = ring[((its - 1) % LSH_HIST) * nload + L];
-    if (history)
+    if (its > 0) last = G.ring[((its - 1) % LSH_HIST) * G.nload + L];
+    if (G.spec.history[L])
       for (int j = std::max(0, its - LSH_HIST); j < its; ++j)
-        history[(long long)L * max_iter + j] = ring[(j % LSH_HIST) * nload + L];
+        G.spec.history[L][j] = G.ring[(j % LSH_HIST) * G.nload + L];
     const bool conv = !fixed && std::isfinite(last) && last <= tol;
-    if (stats) {
-      stats[L].iterations = its;
-      stats[L].converged = conv ? 1 : 0;
-      stats[L].residual = last;
-      stats[L].seconds = secs;
+    if (G.spec.stats[L]) {
+      G.spec.stats[L]->iterations = its;
+      G.spec.stats[L]->converged = conv ? 1 : 0;
+      G.spec.stats[L]->residual = last;
+      G.spec.stats[L]->seconds = secs;
     }
     if (nonfin[L]) status = LSH_ENONFINITE;
     else if (!fixed && !conv && status == LSH_OK) status = LSH_ENOTCONVERGED;
   }
+  return status;
+}
+
+// Run groups to convergence.  Without per-kernel profiling the iterations are
+// captured once into a HIP graph (two iterations, one per ping-pong parity,
+// all groups as independent branches) and the graph is replayed; the
+// iteration counter and the stop flags live on the device, so a replay after
+// a load has converged only runs early-exit blocks for it.
+template <typename T>
+int run_groups(std::vector<GroupRun<T>>& groups, double tol, int max_iter, const double* dev_E_init,
+               double* dev_E_out, hipStream_t st) {
+  const bool fixed = tol < 0.0;
+  for (auto& G : groups) {
+    for (auto* h : G.spec.history)
+      if (h)
+        for (int j = 0; j < max_iter; ++j) h[j] = NAN;
+    int rc = group_init<T>(G, max_iter, dev_E_init, st);
+    if (rc) return rc;
+  }
+  const int check = fixed ? 32 : 8;
+  const auto t0 = std::chrono::steady_clock::now();
+  int done = 0;
+  bool use_graph = !g_prof.on && st != nullptr;
+  hipGraphExec_t gexec = nullptr;
+  if (use_graph) {
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    int rc = LSH_OK;
+    for (int par = 0; par < 2 && rc == LSH_OK; ++par)
+      for (auto& G : groups) {
+        rc = group_iterate<T>(G, par, tol, fixed, st);
+        if (rc) break;
+      }
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc) return rc;
+    if (e != hipSuccess) return lsh_fail(LSH_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return lsh_fail(LSH_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  while (done < max_iter) {
+    const int step = std::min(check, max_iter - done);
+    int k = 0;
+    for (; k < step; ++k) {
+      if (use_graph && (done + k) % 2 == 0 && k + 1 < step) {
+        hipError_t e = hipGraphLaunch(gexec, st);
+        if (e != hipSuccess) {
+          (void)hipGraphExecDestroy(gexec);
+          return lsh_fail(LSH_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+        }
+        ++k;  // the graph holds two iterations
+      } else {
+        for (auto& G : groups) {
+          int rc = group_iterate<T>(G, (done + k) % 2, tol, fixed, st);
+          if (rc) return rc;
+        }
+      }
+    }
+    done += k;
+    bool all = true;
+    for (auto& G : groups) {
+      bool a = false;
+      int rc = group_poll<T>(G, done, max_iter, st, &a);
+      if (rc) return rc;
+      all = all && a;
+    }
+    if (g_prof.on) g_ev.flush();
+    if (all) break;
+  }
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int status = LSH_OK;
+  for (auto& G : groups) {
+    int rc = group_finish<T>(G, done, tol, fixed, secs, dev_E_out, st);
+    if (rc == LSH_ENONFINITE || (rc && status == LSH_OK)) status = rc;
+  }
   if (status == LSH_ENONFINITE) return lsh_fail(status, "non-finite residual (NaN/Inf) in the iteration");
   if (status == LSH_ENOTCONVERGED) return lsh_fail(status, "max_iter reached before the Cauchy residual met tol");
+  return status;
+}
+
+template <typename T>
+int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int max_iter, void* dev_ws,
+            size_t ws_bytes, hipStream_t st, const double* dev_E_init, double* dev_E_out, double* sigma_out,
+            lsh_stats* stats, double* history) {
+  std::vector<GroupRun<T>> groups(1);
+  GroupSpec& S = groups[0].spec;
+  S.rep = p;
+  S.inst = {p};
+  for (int L = 0; L < nload; ++L) {
+    S.inst_of.push_back(0);
+    for (int c = 0; c < 6; ++c) S.eps0_voigt.push_back(eps0_voigt[6 * L + c]);
+    S.sigma_out.push_back(sigma_out + 6 * L);
+    S.stats.push_back(stats ? stats + L : nullptr);
+    S.history.push_back(history ? history + (long long)L * max_iter : nullptr);
+  }
+  size_t used = 0;
+  int rc = group_prepare<T>(groups[0], (char*)dev_ws, dev_ws ? ws_bytes : 0, &used);
+  if (rc) return rc;
+  return run_groups<T>(groups, tol, max_iter, dev_E_init, dev_E_out, st);
+}
+
+// Batched solve: tasks grouped by SNF grid, M and generating function.
+bool same_group(const lsh_pattern* a, const lsh_pattern* b) {
+  for (int i = 0; i < 9; ++i)
+    if (a->M[i] != b->M[i]) return false;
+  if (a->kind != b->kind || a->R != b->R || a->nxi != b->nxi) return false;
+  for (int i = 0; i < 3; ++i)
+    if (a->alpha[i] != b->alpha[i]) return false;
+  for (int i = 0; i < 3 * LSH_MAX_XI; ++i)
+    if (a->Xi[i] != b->Xi[i]) return false;
+  const int ga = green_mode(a), gb = green_mode(b);
+  if (ga != gb) return false;
+  if (ga != GREEN_ISO)  // the general form and the tables depend on C0
+    for (int i = 0; i < 36; ++i)
+      if (a->C0_voigt[i] != b->C0_voigt[i]) return false;
+  return true;
+}
+
+template <typename T>
+int build_groups(const lsh_task* tasks, int ntask, int max_iter, std::vector<GroupRun<T>>* out) {
+  std::vector<GroupRun<T>>& groups = *out;
+  for (int t = 0; t < ntask; ++t) {
+    const lsh_task& tk = tasks[t];
+    if (!tk.p || !tk.eps0_voigt || !tk.sigma_out || tk.nload < 1) return lsh_fail(LSH_EINVAL, "bad task " + std::to_string(t));
+    for (int i = 0; i < 6 * tk.nload; ++i)
+      if (!std::isfinite(tk.eps0_voigt[i])) return lsh_fail(LSH_EINVAL, "non-finite macroscopic strain");
+    size_t gi = 0;
+    for (; gi < groups.size(); ++gi)
+      if (same_group(groups[gi].spec.rep, tk.p)) break;
+    if (gi == groups.size()) {
+      groups.emplace_back();
+      groups.back().spec.rep = tk.p;
+    }
+    GroupSpec& S = groups[gi].spec;
+    const int ii = (int)S.inst.size();
+    S.inst.push_back(tk.p);
+    for (int L = 0; L < tk.nload; ++L) {
+      S.inst_of.push_back(ii);
+      for (int c = 0; c < 6; ++c) S.eps0_voigt.push_back(tk.eps0_voigt[6 * L + c]);
+      S.sigma_out.push_back(tk.sigma_out + 6 * L);
+      S.stats.push_back(tk.stats ? tk.stats + L : nullptr);
+      S.history.push_back(nullptr);
+    }
+  }
+  (void)max_iter;
   return LSH_OK;
+}
+
+template <typename T>
+int batch_bytes_t(const lsh_task* tasks, int ntask, size_t* bytes) {
+  std::vector<GroupRun<T>> groups;
+  int rc = build_groups<T>(tasks, ntask, 1, &groups);
+  if (rc) return rc;
+  size_t tot = 0;
+  for (auto& G : groups) {
+    KernSet<T> K;
+    rc = make_kernels<T>(G.spec.rep, kind_has_table(G.spec.rep), &K);
+    if (rc) return rc;
+    tot += group_layout<T>(geo_of(G.spec.rep), (int)G.spec.inst_of.size(), (int)G.spec.inst.size(), K, nullptr).total;
+  }
+  *bytes = tot;
+  return LSH_OK;
+}
+
+template <typename T>
+int solve_batch_t(const lsh_task* tasks, int ntask, double tol, int max_iter, void* dev_ws, size_t ws_bytes,
+                  hipStream_t st) {
+  std::vector<GroupRun<T>> groups;
+  int rc = build_groups<T>(tasks, ntask, max_iter, &groups);
+  if (rc) return rc;
+  char* base = (char*)dev_ws;
+  size_t left = dev_ws ? ws_bytes : 0;
+  for (auto& G : groups) {
+    size_t used = 0;
+    rc = group_prepare<T>(G, base, left, &used);
+    if (rc) return rc;
+    base += used;
+    left -= used;
+  }
+  return run_groups<T>(groups, tol, max_iter, nullptr, nullptr, st);
 }
 
 template <typename T>
@@ -721,12 +965,12 @@ extern "C" int lsh_solve_bytes(const lsh_pattern* p, int nload, lsh_precision pr
     KernSet<double> K;
     int rc = make_kernels<double>(p, kind_has_table(p), &K);
     if (rc) return rc;
-    *bytes = ws_layout<double>(p, nload, K, nullptr).total;
+    *bytes = group_layout<double>(geo_of(p), nload, 1, K, nullptr).total;
   } else if (prec == LSH_FP32_MIXED) {
     KernSet<float> K;
     int rc = make_kernels<float>(p, kind_has_table(p), &K);
     if (rc) return rc;
-    *bytes = ws_layout<float>(p, nload, K, nullptr).total;
+    *bytes = group_layout<float>(geo_of(p), nload, 1, K, nullptr).total;
   } else {
     return lsh_fail(LSH_EINVAL, "bad precision");
   }
@@ -765,4 +1009,29 @@ extern "C" int lsh_profile_read(double* ms, long long* counts, int n) {
     counts[i] = g_prof.n[i];
   }
   return LSH_OK;
+}
+
+extern "C" int lsh_batch_bytes(const lsh_task* tasks, int ntask, lsh_precision prec, size_t* bytes) {
+  if (!tasks || ntask < 1 || !bytes) return lsh_fail(LSH_EINVAL, "bad argument");
+  for (int t = 0; t < ntask; ++t)
+    if (!tasks[t].p || tasks[t].p->kind < 0) return lsh_fail(LSH_ESTATE, "task pattern without a kernel");
+  if (prec == LSH_FP64) return batch_bytes_t<double>(tasks, ntask, bytes);
+  if (prec == LSH_FP32_MIXED) return batch_bytes_t<float>(tasks, ntask, bytes);
+  return lsh_fail(LSH_EINVAL, "bad precision");
+}
+
+extern "C" int lsh_solve_batch(const lsh_task* tasks, int ntask, double tol, int max_iter, lsh_precision prec,
+                               void* dev_ws, size_t ws_bytes, void* stream) {
+  if (!tasks || ntask < 1) return lsh_fail(LSH_EINVAL, "bad argument");
+  if (max_iter < 1) return lsh_fail(LSH_EINVAL, "max_iter must be >= 1");
+  if (!(tol == tol)) return lsh_fail(LSH_EINVAL, "tol is NaN");
+  for (int t = 0; t < ntask; ++t) {
+    const lsh_pattern* p = tasks[t].p;
+    if (!p || p->kind < 0 || p->nphase < 1) return lsh_fail(LSH_ESTATE, "task pattern without kernel or stiffness");
+    if (p->bound_prec != (int)prec) return lsh_fail(LSH_ESTATE, "task pattern not bound at this precision");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LSH_FP64) return solve_batch_t<double>(tasks, ntask, tol, max_iter, dev_ws, ws_bytes, st);
+  if (prec == LSH_FP32_MIXED) return solve_batch_t<float>(tasks, ntask, tol, max_iter, dev_ws, ws_bytes, st);
+  return lsh_fail(LSH_EINVAL, "bad precision");
 }

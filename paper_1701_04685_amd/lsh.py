@@ -26,7 +26,8 @@ STATUS = {0: "LSH_OK", -1: "LSH_EINVAL", -2: "LSH_ESINGULAR", -3: "LSH_ENOINTERP
 
 EXPORTS = ["lsh_create_pattern", "lsh_destroy", "lsh_pattern_info", "lsh_pattern_snf", "lsh_pattern_points",
            "lsh_set_kernel", "lsh_set_stiffness", "lsh_persistent_bytes", "lsh_bind", "lsh_gamma_probe",
-           "lsh_solve_bytes", "lsh_solve", "lsh_profile_enable", "lsh_profile_read", "lsh_last_error"]
+           "lsh_solve_bytes", "lsh_solve", "lsh_batch_bytes", "lsh_solve_batch", "lsh_profile_enable",
+           "lsh_profile_read", "lsh_last_error"]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
@@ -47,6 +48,11 @@ class Stats(ctypes.Structure):
                 ("residual", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
+class Task(ctypes.Structure):
+    _fields_ = [("p", _P), ("nload", ctypes.c_int), ("eps0_voigt", _DP), ("sigma_out", _DP),
+                ("stats", ctypes.POINTER(Stats))]
+
+
 _sig = {
     "lsh_create_pattern": ([ctypes.c_int, _I64P, ctypes.POINTER(_P)], ctypes.c_int),
     "lsh_destroy": ([_P], None),
@@ -61,6 +67,10 @@ _sig = {
     "lsh_solve_bytes": ([_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "lsh_solve": ([_P, ctypes.c_int, _DP, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t, _P,
                    _P, _P, _DP, ctypes.POINTER(Stats), _DP], ctypes.c_int),
+    "lsh_batch_bytes": ([ctypes.POINTER(Task), ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+                        ctypes.c_int),
+    "lsh_solve_batch": ([ctypes.POINTER(Task), ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P,
+                         ctypes.c_size_t, _P], ctypes.c_int),
     "lsh_profile_enable": ([ctypes.c_int], ctypes.c_int),
     "lsh_profile_read": ([_DP, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int], ctypes.c_int),
     "lsh_last_error": ([], ctypes.c_char_p),
@@ -100,6 +110,25 @@ def _torch():
 def _stream():
     torch = _torch()
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_SOLVE_STREAM = None
+
+
+def _solve_stream():
+    """A non-default stream for solves (the library captures its iterations in a
+    HIP graph there); ordered after torch's current stream."""
+    global _SOLVE_STREAM
+    torch = _torch()
+    if _SOLVE_STREAM is None:
+        _SOLVE_STREAM = torch.cuda.Stream()
+    _SOLVE_STREAM.wait_stream(torch.cuda.current_stream())
+    return _SOLVE_STREAM, ctypes.c_void_p(_SOLVE_STREAM.cuda_stream)
+
+
+def _done_on(stream):
+    torch = _torch()
+    torch.cuda.current_stream().wait_stream(stream)
 
 
 def _device_bytes(n):
@@ -209,11 +238,13 @@ class Pattern:
         sig = np.zeros((nload, 6), dtype=np.float64)
         stats = (Stats * nload)()
         hist = np.full((nload, max_iter), np.nan) if history else None
+        S, sh = _solve_stream()
         rc = _lib.lsh_solve(self._h, nload, _dptr(eps), float(tol), int(max_iter), self._prec,
-                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), sh,
                             ctypes.c_void_p(E_init.data_ptr()) if E_init is not None else None,
                             ctypes.c_void_p(Eout.data_ptr()) if Eout is not None else None,
                             _dptr(sig), stats, _dptr(hist) if hist is not None else None)
+        _done_on(S)
         _check(rc, allow=(-5,) if allow_notconverged else ())
         out = dict(sigma=sig, status=rc,
                    iterations=np.array([s.iterations for s in stats]),
@@ -225,6 +256,61 @@ class Pattern:
         if history:
             out["history"] = hist
         return out
+
+
+def solve_batch(patterns, eps0_list, tol=1e-6, max_iter=1000, precision="fp32", workspace=None,
+                allow_notconverged=False):
+    """Solve many bound patterns at once (lsh_solve_batch).
+
+    patterns: list of Pattern (bound at `precision`); eps0_list: per pattern an
+    (nload, 6) array of Voigt strains.  Returns per pattern a dict with sigma
+    (nload, 6), iterations, converged, residual, and the call's status.
+    """
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    n = len(patterns)
+    tasks = (Task * n)()
+    keep = []
+    outs = []
+    for i, (P, e) in enumerate(zip(patterns, eps0_list)):
+        e = np.ascontiguousarray(np.asarray(e, dtype=np.float64).reshape(-1, 6))
+        sig = np.zeros_like(e)
+        st = (Stats * e.shape[0])()
+        keep += [e, sig, st]
+        tasks[i].p = P._h
+        tasks[i].nload = e.shape[0]
+        tasks[i].eps0_voigt = _dptr(e)
+        tasks[i].sigma_out = _dptr(sig)
+        tasks[i].stats = st
+        outs.append((sig, st))
+    nb = ctypes.c_size_t()
+    _check(_lib.lsh_batch_bytes(tasks, n, prec, ctypes.byref(nb)))
+    ws = workspace if workspace is not None and workspace.numel() >= nb.value else _device_bytes(nb.value)
+    S, sh = _solve_stream()
+    rc = _lib.lsh_solve_batch(tasks, n, float(tol), int(max_iter), prec, ctypes.c_void_p(ws.data_ptr()),
+                              ws.numel(), sh)
+    _done_on(S)
+    _check(rc, allow=(-5,) if allow_notconverged else ())
+    res = []
+    for sig, st in outs:
+        res.append(dict(sigma=sig, iterations=np.array([s.iterations for s in st]),
+                        converged=np.array([bool(s.converged) for s in st]),
+                        residual=np.array([s.residual for s in st]), status=rc))
+    return res
+
+
+def batch_workspace_bytes(patterns, nloads, precision="fp32"):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    n = len(patterns)
+    tasks = (Task * n)()
+    dummy = np.zeros((max(nloads), 6))
+    for i, (P, k) in enumerate(zip(patterns, nloads)):
+        tasks[i].p = P._h
+        tasks[i].nload = int(k)
+        tasks[i].eps0_voigt = _dptr(dummy)
+        tasks[i].sigma_out = _dptr(dummy)
+    nb = ctypes.c_size_t()
+    _check(_lib.lsh_batch_bytes(tasks, n, prec, ctypes.byref(nb)))
+    return nb.value
 
 
 def profile_enable(on=True):

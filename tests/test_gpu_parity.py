@@ -293,3 +293,45 @@ def test_cfg2_fullsize_lockstep_3_iterations():
         assert rel(res["sigma"][j], ref["sigma_voigt"]) < FP64_TOL
         Eg = pr.gpu_E_to_oracle_mandel(res["E"][j].cpu().numpy())
         assert rel(Eg, ref["E"]) < FP64_TOL
+
+
+# ---------------------------------------------------------------- batches ---
+def test_batch_matches_single_solves():
+    """Uneven pattern sizes and materials in one batched call: every task's
+    sigma_bar and iteration count equal a single solve of the same task, and
+    the oracle in lock-step for one of them."""
+    from paper_1701_04685_amd import lsh
+    rng = np.random.default_rng(30)
+    specs = [(np.diag([8, 8, 8]), 3.0, 0.3), (np.diag([12, 12, 12]), 20.0, 0.25), (np.diag([8, 8, 8]), 10.0, 0.4),
+             (np.diag([6, 10, 12]), 5.0, 0.2)]
+    pats, loads, singles = [], [], []
+    for i, (M, contrast, frac) in enumerate(specs):
+        Cp = np.stack([li.isotropic_voigt(1.0, 0.3), li.isotropic_voigt(contrast, 0.3)])
+        C0 = li.mean_reference(Cp)
+        P = lsh.Pattern(M)
+        ph = (rng.random(P.m) < frac).astype(np.uint8)
+        P.set_kernel("dirichlet")
+        P.set_stiffness(Cp, C0, ph)
+        P.bind("fp32")
+        pats.append(P)
+        loads.append(np.eye(6)[: 2 + i])
+    out = lsh.solve_batch(pats, loads, tol=1e-5, max_iter=500, precision="fp32")
+    for P, e, o in zip(pats, loads, out):
+        ref = P.solve(e, tol=1e-5, max_iter=500)
+        assert list(o["iterations"]) == list(ref["iterations"])
+        np.testing.assert_allclose(o["sigma"], ref["sigma"], rtol=1e-6, atol=1e-7)
+        assert np.all(o["converged"])
+
+
+def test_batch_lockstep_against_oracle():
+    from paper_1701_04685_amd import lsh
+    prs = [Problem(np.diag([8, 8, 8]), "dlvp", {"alpha": [0.5] * 3}, random_phase(31)),
+           Problem(np.diag([6, 6, 10]), "dlvp", {"alpha": [0.5] * 3}, random_phase(32))]
+    for pr in prs:
+        pr.bind("fp64")
+    eps = [np.array([[0.1, 0.2, -0.3, 0.05, 0.0, 0.15]]), np.eye(6)[[0, 3]]]
+    out = lsh.solve_batch([pr.G for pr in prs], eps, tol=-1.0, max_iter=6, precision="fp64")
+    for pr, e, o in zip(prs, eps, out):
+        for j in range(len(e)):
+            ref = pr.oracle_solve(e[j], n_iter=6)
+            assert rel(o["sigma"][j], ref["sigma_voigt"]) < FP64_TOL
