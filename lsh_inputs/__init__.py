@@ -178,3 +178,15 @@ def spheres_phase_grid(n, centres, radii):
         ii = np.ix_(i0, i1, i2)
         ph[ii] |= inside.astype(np.uint8)
     return ph.reshape(-1)
+
+
+def unet_init_params(seed, layers):
+    """Initial U-Net parameters (float32): He-normal weights [t][co][ci] per layer
+    in layer order, then zero biases; layers = [(cin, cout, ks), ...]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ws, bs = [], []
+    for cin, cout, ks in layers:
+        fan_in = ks ** 3 * cin
+        ws.append((rng.standard_normal(ks ** 3 * cin * cout) * np.sqrt(2.0 / fan_in)).astype(np.float32))
+        bs.append(np.zeros(cout, dtype=np.float32))
+    return np.concatenate(ws + bs)

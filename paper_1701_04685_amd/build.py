@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblsh.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["lsh_host.cpp", "lsh_solver.hip"]
+SOURCES = ["lsh_host.cpp", "lsh_solver.hip", "lsh_unet.hip"]
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed FP32 instructions stay off

@@ -27,7 +27,10 @@ STATUS = {0: "LSH_OK", -1: "LSH_EINVAL", -2: "LSH_ESINGULAR", -3: "LSH_ENOINTERP
 EXPORTS = ["lsh_create_pattern", "lsh_destroy", "lsh_pattern_info", "lsh_pattern_snf", "lsh_pattern_points",
            "lsh_set_kernel", "lsh_set_stiffness", "lsh_persistent_bytes", "lsh_bind", "lsh_gamma_probe",
            "lsh_solve_bytes", "lsh_solve", "lsh_batch_bytes", "lsh_solve_batch", "lsh_profile_enable",
-           "lsh_profile_read", "lsh_last_error"]
+           "lsh_profile_read", "lsh_last_error", "lsh_unet_create", "lsh_unet_destroy", "lsh_unet_param_count",
+           "lsh_unet_param_bytes", "lsh_unet_bind", "lsh_unet_get_params", "lsh_unet_act_bytes",
+           "lsh_unet_train_step", "lsh_unet_zero_grad", "lsh_unet_get_grads", "lsh_unet_predict", "lsh_unet_head",
+           "lsh_unet_layers", "lsh_unet_pack_target"]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
@@ -74,6 +77,21 @@ _sig = {
     "lsh_profile_enable": ([ctypes.c_int], ctypes.c_int),
     "lsh_profile_read": ([_DP, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int], ctypes.c_int),
     "lsh_last_error": ([], ctypes.c_char_p),
+    "lsh_unet_create": ([ctypes.c_int, ctypes.POINTER(_P)], ctypes.c_int),
+    "lsh_unet_destroy": ([_P], None),
+    "lsh_unet_param_count": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "lsh_unet_param_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "lsh_unet_bind": ([_P, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_float), _P], ctypes.c_int),
+    "lsh_unet_get_params": ([_P, ctypes.POINTER(ctypes.c_float), _P], ctypes.c_int),
+    "lsh_unet_act_bytes": ([_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "lsh_unet_train_step": ([_P, _P, _P, ctypes.c_int, ctypes.c_float, _P, ctypes.c_size_t, _P, _DP], ctypes.c_int),
+    "lsh_unet_zero_grad": ([_P, _P], ctypes.c_int),
+    "lsh_unet_get_grads": ([_P, ctypes.POINTER(ctypes.c_float), _P], ctypes.c_int),
+    "lsh_unet_predict": ([_P, _P, ctypes.c_int, _DP, ctypes.c_int, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "lsh_unet_head": ([_P, ctypes.c_int, _P, _P], ctypes.c_int),
+    "lsh_unet_layers": ([_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                         ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "lsh_unet_pack_target": ([_P, ctypes.c_int, _P, _P], ctypes.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -322,3 +340,98 @@ def profile_read():
     cnt = np.zeros(8, dtype=np.int64)
     _check(_lib.lsh_profile_read(_dptr(ms), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), 8))
     return ms, cnt
+
+
+class UNet:
+    """Learned warm start (include/lsh_unet.h): a 3-level 3-D U-Net in bf16/MFMA.
+
+    Initial parameters are an input (``lsh_inputs.unet_init_params``).
+    """
+
+    def __init__(self, params):
+        h = _P()
+        _check(_lib.lsh_unet_create(32, ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int64()
+        _check(_lib.lsh_unet_param_count(h, ctypes.byref(n)))
+        self.nparam = int(n.value)
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        if p.size != self.nparam:
+            raise ValueError(f"expected {self.nparam} parameters")
+        nb = ctypes.c_size_t()
+        _check(_lib.lsh_unet_param_bytes(h, ctypes.byref(nb)))
+        self._pbuf = _device_bytes(nb.value)
+        _check(_lib.lsh_unet_bind(h, ctypes.c_void_p(self._pbuf.data_ptr()), nb.value,
+                                  p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream()))
+        self._act = {}
+
+    @staticmethod
+    def layers():
+        h = _P()
+        _check(_lib.lsh_unet_create(32, ctypes.byref(h)))
+        nl = ctypes.c_int()
+        a, b, c = (ctypes.c_int * 16)(), (ctypes.c_int * 16)(), (ctypes.c_int * 16)()
+        _check(_lib.lsh_unet_layers(h, ctypes.byref(nl), a, b, c))
+        _lib.lsh_unet_destroy(h)
+        return [(a[i], b[i], c[i]) for i in range(nl.value)]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.lsh_unet_destroy(h)
+            self._h = None
+
+    def _workspace(self, n, training):
+        key = (n, bool(training))
+        if key not in self._act:
+            nb = ctypes.c_size_t()
+            _check(_lib.lsh_unet_act_bytes(self._h, n, 1 if training else 0, ctypes.byref(nb)))
+            self._act[key] = _device_bytes(nb.value)
+        return self._act[key]
+
+    def train_step(self, phase, target, n, lr):
+        """phase: cuda uint8 (n^3,); target: cuda float32 (n^3, 36).  Returns the loss."""
+        ws = self._workspace(n, True)
+        loss = ctypes.c_double()
+        _check(_lib.lsh_unet_train_step(self._h, ctypes.c_void_p(phase.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+                                        n, float(lr), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(),
+                                        ctypes.byref(loss)))
+        return loss.value
+
+    def zero_grad(self):
+        _check(_lib.lsh_unet_zero_grad(self._h, _stream()))
+
+    def grads(self):
+        g = np.zeros(self.nparam, dtype=np.float32)
+        _check(_lib.lsh_unet_get_grads(self._h, g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream()))
+        return g
+
+    def params(self):
+        p = np.zeros(self.nparam, dtype=np.float32)
+        _check(_lib.lsh_unet_get_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream()))
+        return p
+
+    def head(self, n):
+        torch = _torch()
+        out = torch.empty((n ** 3, 64), dtype=torch.float32, device="cuda")
+        _check(_lib.lsh_unet_head(self._h, n, ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def predict(self, phase, n, eps0_voigt):
+        """Start fluctuations [nload][6][n^3] (Voigt, engineering shear) for lsh_solve."""
+        torch = _torch()
+        eps = np.ascontiguousarray(np.asarray(eps0_voigt, dtype=np.float64).reshape(-1, 6))
+        out = torch.empty((eps.shape[0], 6, n ** 3), dtype=torch.float64, device="cuda")
+        ws = self._workspace(n, False)
+        _check(_lib.lsh_unet_predict(self._h, ctypes.c_void_p(phase.data_ptr()), n, _dptr(eps), eps.shape[0],
+                                     ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                     _stream()))
+        return out
+
+    @staticmethod
+    def pack_target(E6, n):
+        """Six unit-load fields [6][6][n^3] (lsh_solve's E out) -> float32 [n^3][36] (Mandel)."""
+        torch = _torch()
+        T = torch.empty((n ** 3, 36), dtype=torch.float32, device="cuda")
+        _check(_lib.lsh_unet_pack_target(ctypes.c_void_p(E6.data_ptr()), n, ctypes.c_void_p(T.data_ptr()), _stream()))
+        return T

@@ -114,3 +114,33 @@ def test_workspace_sizes_scale(lib):
     b6 = P.workspace_bytes(6, "fp64")
     f1 = P.workspace_bytes(1, "fp32")
     assert b6 > 5 * b1 * 0.9 and f1 < b1
+
+
+def test_unet_host_side(lib):
+    """U-Net network description and size queries (host only) agree with the
+    reference network's layer table; misuse is reported, not run."""
+    import ctypes
+    from oracle import unet
+    assert lib.UNet.layers() == unet.LAYERS
+    so = lib._lib
+    h = ctypes.c_void_p()
+    assert so.lsh_unet_create(16, ctypes.byref(h)) == -1
+    assert so.lsh_unet_create(32, ctypes.byref(h)) == 0
+    try:
+        cnt = ctypes.c_int64()
+        assert so.lsh_unet_param_count(h, ctypes.byref(cnt)) == 0
+        assert cnt.value == unet.param_layout()[2]
+        nb = ctypes.c_size_t()
+        assert so.lsh_unet_act_bytes(h, 12, 1, ctypes.byref(nb)) == -1
+        assert so.lsh_unet_act_bytes(h, 16, 1, ctypes.byref(nb)) == 0
+        train16 = nb.value
+        assert so.lsh_unet_act_bytes(h, 16, 0, ctypes.byref(nb)) == 0
+        assert 0 < nb.value < train16
+        assert so.lsh_unet_act_bytes(h, 32, 1, ctypes.byref(nb)) == 0
+        assert 7.5 * train16 < nb.value < 8.5 * train16
+        loss = ctypes.c_double()
+        # not bound: rejected before any device work
+        assert so.lsh_unet_train_step(h, None, None, 16, 0.0, None, 0, None, ctypes.byref(loss)) == -1
+        assert so.lsh_unet_get_params(h, (ctypes.c_float * 1)(), None) == -10
+    finally:
+        so.lsh_unet_destroy(h)
