@@ -197,6 +197,119 @@ def bench_cfg3(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_cfg5(args):
+    """Learned warm start: U-Net trained on solver-produced 64^3 fields (RSA spheres
+    f = 0.3, radii 6-12 grid steps, contrast 100, dlVP alpha = 3/4, FP32 path),
+    evaluated on unseen 128^3 packings: time to the Cauchy residual 1e-6 from
+    the learned start (inference and the judged fallback included) vs the
+    zero start."""
+    import torch
+    from paper_1701_04685_amd import lsh, warmstart as wst
+    import lsh_inputs as li
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    n_train, n_eval = 64, 128
+    t0 = time.perf_counter()
+    data, its = wst.make_dataset([50000 + i for i in range(args.train_packings)], n_train, 100.0, tol=1e-6, log=log)
+    t_data = time.perf_counter() - t0
+    layers = lsh.UNet.layers()
+    net = lsh.UNet(li.unet_init_params(1, layers))
+    untrained = lsh.UNet(li.unet_init_params(1, layers))
+    t0 = time.perf_counter()
+    losses = wst.train(net, data, n_train, args.epochs, lr=3e-4, lr_final=3e-5, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del data
+    rng = np.random.Generator(np.random.PCG64(7))
+    ws = None
+    rows = []
+    for k in range(args.eval_packings):
+        ph = wst.packing(60000 + k, n_eval)
+        P = wst.grid_pattern(n_eval, ph, 100.0)
+        if k == 0:
+            wst.check_grid_order(P, n_eval)
+            ws = torch.empty(P.workspace_bytes(2), dtype=torch.uint8, device="cuda")
+        phd = torch.from_numpy(ph).cuda()
+        eps = li.random_unit_load(rng)
+        if k == 0:  # untimed warm-up of both paths
+            wst.solve_plain(P, eps, workspace=ws)
+            wst.solve_learned(P, net, phd, n_eval, eps, workspace=ws)
+        a = wst.solve_plain(P, eps, workspace=ws)
+        b = wst.solve_learned(P, net, phd, n_eval, eps, workspace=ws)
+        row = dict(plain_s=a["seconds"], learned_s=b["seconds"], plain_it=a["iterations"],
+                   learned_it=b["iterations"], fell_back=b["fell_back"],
+                   dsig=float(np.abs(a["sigma"] - b["sigma"]).max() / np.abs(a["sigma"]).max()),
+                   converged=a["converged"] and b["converged"])
+        if k < args.ablation_packings:
+            c = wst.solve_learned(P, untrained, phd, n_eval, eps, workspace=ws)
+            row["untrained_s"], row["untrained_it"] = c["seconds"], c["iterations"]
+        rows.append(row)
+        if (k + 1) % 20 == 0:
+            log(f"eval {k + 1}/{args.eval_packings}")
+    ratio = np.array([r["plain_s"] / r["learned_s"] for r in rows])
+    pit = np.array([r["plain_it"] for r in rows])
+    lit = np.array([r["learned_it"] for r in rows])
+    # inference time alone (one prediction of the pair) at the evaluation size
+    phd = torch.from_numpy(wst.packing(60000, n_eval)).cuda()
+    pair = np.stack([np.eye(6)[0], np.zeros(6)])
+    net.predict(phd, n_eval, pair)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        net.predict(phd, n_eval, pair)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / 5
+    abl = [r for r in rows if "untrained_s" in r]
+    # how the iteration count reacts to the start's error: exact field (FP64,
+    # tol 1e-9) scaled, or plus white noise of a given RMS, on the first packing
+    ph = wst.packing(60000, n_eval)
+    P = wst.grid_pattern(n_eval, ph, 100.0)
+    P64 = wst.grid_pattern(n_eval, ph, 100.0, precision="fp64")
+    eps = np.eye(6)[0].reshape(1, 6)
+    Es = P64.solve(eps, tol=1e-9, max_iter=6000, return_E=True)["E"]
+    del P64
+    rms = Es.norm().item() / np.sqrt(Es.numel())
+    nrng = np.random.Generator(np.random.PCG64(8))
+
+    def iters_from(E0):
+        return int(P.solve(eps, tol=1e-6, max_iter=6000, E_init=E0, workspace=ws)["iterations"][0])
+
+    sens = {"zero": iters_from(None), "0.9*exact": iters_from((0.9 * Es).contiguous())}
+    for sg in (1e-1, 1e-2, 1e-3):
+        noise = torch.from_numpy(nrng.standard_normal(tuple(Es.shape)) * (sg * rms)).cuda()
+        sens[f"exact+{sg:g}rms_noise"] = iters_from((Es + noise).contiguous())
+    Ep = net.predict(torch.from_numpy(ph).cuda(), n_eval, eps)
+    sens["learned"] = iters_from(Ep)
+    sens["learned_start_rel_error"] = float(((Ep - Es).norm() / Es.norm()).item())
+    out = {"metric": METRIC, "value": float(np.median(ratio)), "unit": "x (t_plain / t_learned, median)",
+           "n_gpus": 1, "steps": len(rows), "warmup": 1,
+           "ms_per_step": float(np.median([r["learned_s"] for r in rows]) * 1e3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (U-Net) / f32 (solver)", "data": "synthetic",
+           "config": {"workload": f"learned warm start: U-Net trained on {len(its) * 6} fields "
+                                  f"({len(its)} RSA packings 64^3, 6 unit loads), evaluated on {len(rows)} unseen "
+                                  f"128^3 packings, f=0.3, radii 6-12, contrast 100, dlVP alpha=3/4, FP32, tol 1e-6",
+                      "epochs": args.epochs, "train_steps": args.epochs * len(its)},
+           "roofline": None, "cpu_baseline": None,
+           "warm_start": {
+               "ratio_min_median_max": [float(ratio.min()), float(np.median(ratio)), float(ratio.max())],
+               "ratio_mean": float(ratio.mean()),
+               "plain_ms_median": float(np.median([r["plain_s"] for r in rows]) * 1e3),
+               "learned_ms_median": float(np.median([r["learned_s"] for r in rows]) * 1e3),
+               "plain_iterations_median": float(np.median(pit)), "learned_iterations_median": float(np.median(lit)),
+               "fallback_fraction": float(np.mean([r["fell_back"] for r in rows])),
+               "all_converged": bool(all(r["converged"] for r in rows)),
+               "sigma_rel_diff_max": float(max(r["dsig"] for r in rows)),
+               "inference_ms_128": round(t_inf * 1e3, 3),
+               "untrained_ratio_median": (float(np.median([r["plain_s"] / r["untrained_s"] for r in abl]))
+                                          if abl else None),
+               "start_sensitivity_iterations": sens,
+               "dataset_s": round(t_data, 1), "dataset_iterations_median": float(np.median(its)),
+               "train_s": round(t_train, 1), "train_loss_first_last_epoch": [float(losses[0]), float(losses[-1])]}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,8 +317,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the converged (time-to-tol) solve")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4"],
-                    help="cfg2 (default): 128^3 FP64 dlVP; cfg3: non-diagonal Box FP32; cfg4: batched FP32")
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5"],
+                    help="cfg2 (default): 128^3 FP64 dlVP; cfg3: non-diagonal Box FP32; cfg4: batched FP32; "
+                         "cfg5: learned warm start")
+    ap.add_argument("--train-packings", type=int, default=334, help="cfg5: 64^3 training packings (x6 fields)")
+    ap.add_argument("--epochs", type=int, default=12, help="cfg5: training epochs")
+    ap.add_argument("--eval-packings", type=int, default=200, help="cfg5: unseen 128^3 packings")
+    ap.add_argument("--ablation-packings", type=int, default=10, help="cfg5: packings also run with the untrained net")
     ap.add_argument("--instances", type=int, default=256, help="cfg4: number of microstructures")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -223,6 +341,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "cfg3":
         return bench_cfg3(args)
+    if args.workload == "cfg5":
+        return bench_cfg5(args)
 
     P, Cp, C0, phase = build_problem(lsh, li)
     nload = 6

@@ -172,7 +172,7 @@ class Pattern:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.lsh_destroy(h)
             self._h = None
 
@@ -377,7 +377,7 @@ class UNet:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.lsh_unet_destroy(h)
             self._h = None
 
