@@ -310,6 +310,27 @@ def bench_cfg5(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_copy(args):
+    """Calibration for HBM traffic counters: a plain elementwise copy (out = 1.0 * in,
+    float32) of known size, 512 MiB read + 512 MiB written per launch."""
+    import torch
+    n = 128 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"metric": "copy GB/s (counter calibration)", "value": 2 * 4 * n / dt / 1e9, "unit": "GB/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": dt * 1e3,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic", "config": {"workload": "elementwise copy 512 MiB in, 512 MiB out",
+                                                      "bytes_read": 4 * n, "bytes_written": 4 * n}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,9 +338,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the converged (time-to-tol) solve")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5"],
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "copy"],
                     help="cfg2 (default): 128^3 FP64 dlVP; cfg3: non-diagonal Box FP32; cfg4: batched FP32; "
-                         "cfg5: learned warm start")
+                         "cfg5: learned warm start; copy: counter calibration")
     ap.add_argument("--train-packings", type=int, default=334, help="cfg5: 64^3 training packings (x6 fields)")
     ap.add_argument("--epochs", type=int, default=12, help="cfg5: training epochs")
     ap.add_argument("--eval-packings", type=int, default=200, help="cfg5: unseen 128^3 packings")
@@ -343,6 +364,8 @@ def main():
         return bench_cfg3(args)
     if args.workload == "cfg5":
         return bench_cfg5(args)
+    if args.workload == "copy":
+        return bench_copy(args)
 
     P, Cp, C0, phase = build_problem(lsh, li)
     nload = 6

@@ -347,6 +347,7 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
                                               const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
                                               C2<T>* __restrict__ Pnew, const T* __restrict__ table,
                                               const Inst* __restrict__ insts, const int* __restrict__ inst_of,
+                                              const int* __restrict__ chunks_unused,
                                               const int* __restrict__ stop_iter, const int* __restrict__ itp,
                                               int nload, int npos, double* __restrict__ partial, int ls, int gmode) {
   using T2 = C2<T>;
@@ -457,6 +458,325 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
     }
   }
   block_sum<2>(acc, partial + ((long long)L * npos + pos) * 2);
+}
+
+// ------------------------------------------- Green pass, loads amortised ---
+// One block per position (k1, k2) and chunk of GCH load cases.  The Green
+// operator of the position (21 entries per k3, scaled by -1/m) is formed once
+// into LDS and reused for every load of the chunk whose instance it belongs to.
+// Loads run NL at a time.  The axis-3 transforms are Stockham FFTs whose first
+// forward stage reads global memory and whose last inverse stage writes it;
+// the forward radix-2 last stage, the 6x6 multiply and the inverse radix-2
+// first stage run in registers on a thread that holds bins j and j + N/2 of
+// all six components.  LDS lines carry one pad slot per 8 entries (fewer bank
+// conflicts for the strided Stockham writes).
+#define GCH 6
+__host__ __device__ constexpr int gpad(int i) { return i + (i >> 3); }
+
+template <int N> struct GreenPlan {
+  static constexpr RadList RH = make_radlist(N / 2);
+  static constexpr int LP = N + N / 8;
+};
+
+// fixed-radix stage over NLN lines in LDS (in place)
+template <typename T, int DIR, int N, int R, int NS, int NLN, int NT>
+__device__ __forceinline__ void g2_stage(C2<T>* lines, const C2<T>* __restrict__ twl) {
+  using T2 = C2<T>;
+  constexpr int LP = GreenPlan<N>::LP;
+  constexpr int nbl = N / R;
+  constexpr int nu = NLN * nbl;
+  constexpr int NB = (nu + NT - 1) / NT;
+  constexpr int tstep = N / (NS * R);
+  const int tid = threadIdx.x;
+  T2 v[NB][R];
+  int dst[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int u = tid + q * NT;
+    dst[q] = -1;
+    if (nu % NT == 0 || u < nu) {
+      const int l = u / nbl, j = u % nbl;
+      const T2* src = lines + l * LP;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[gpad(j + r * nbl)];
+      const int k = j % NS;
+      if (NS > 1 && k != 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          T2 w = twl[r * tstep * k];
+          if (DIR > 0) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+      Bfly<T, DIR, R>::run(v[q]);
+      dst[q] = l * LP + (j - k) * R + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+    if (nu % NT == 0 || dst[q] >= 0) {
+      const int l = dst[q] / LP, d0 = dst[q] % LP;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lines[l * LP + gpad(d0 + r * NS)] = v[q][r];
+    }
+  __syncthreads();
+}
+
+// forward stages S..n-1 of the half-length radix list (stage 0 came from global)
+template <typename T, int N, int NLN, int NT, int S, int NS>
+__device__ __forceinline__ void g2_fwd_rest(C2<T>* lines, const C2<T>* twl) {
+  constexpr RadList RH = GreenPlan<N>::RH;
+  if constexpr (S < RH.n) {
+    g2_stage<T, -1, N, RH.r[S], NS, NLN, NT>(lines, twl);
+    g2_fwd_rest<T, N, NLN, NT, S + 1, NS * RH.r[S]>(lines, twl);
+  }
+}
+// inverse stages S..n-2 (the last one writes global memory)
+template <typename T, int N, int NLN, int NT, int S, int NS>
+__device__ __forceinline__ void g2_inv_mid(C2<T>* lines, const C2<T>* twl) {
+  constexpr RadList RH = GreenPlan<N>::RH;
+  if constexpr (S + 1 < RH.n) {
+    g2_stage<T, +1, N, RH.r[S], NS, NLN, NT>(lines, twl);
+    g2_inv_mid<T, N, NLN, NT, S + 1, NS * RH.r[S]>(lines, twl);
+  }
+}
+__host__ __device__ constexpr int radprod(RadList L, int upto) {
+  int p = 1;
+  for (int i = 0; i < upto; ++i) p *= L.r[i];
+  return p;
+}
+
+template <typename T, int N, int NL, int NT>
+__global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* __restrict__ tw, GreenParams gp,
+                                               const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
+                                               C2<T>* __restrict__ Pnew, const T* __restrict__ table,
+                                               const Inst* __restrict__ insts, const int* __restrict__ inst_of,
+                                               const int* __restrict__ chunks, const int* __restrict__ stop_iter,
+                                               const int* __restrict__ itp, int nload, int npos,
+                                               double* __restrict__ partial, int ls_unused, int gmode) {
+  using T2 = C2<T>;
+  static_assert(NL == 1 || NL == 2, "one or two loads at a time");
+  (void)pl;
+  (void)ls_unused;
+  (void)nload;
+  constexpr RadList RH = GreenPlan<N>::RH;
+  constexpr int LP = GreenPlan<N>::LP;
+  constexpr int H = N / 2;
+  constexpr int NLN = NL * 6;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* twl = reinterpret_cast<T2*>(smem_raw);
+  T* Gl = reinterpret_cast<T*>(twl + N);           // [21][N]
+  T2* lines = reinterpret_cast<T2*>(Gl + 21 * N);  // [NL][6][LP]
+  const int pos = blockIdx.x;
+  // a chunk holds up to GCH consecutive loads of one instance
+  const int Lbeg = chunks[2 * blockIdx.y], Lend = chunks[2 * blockIdx.y + 1];
+  const int it = *itp;
+  const int k1 = pos / g.n2, k2 = pos % g.n2;
+  const int tid = threadIdx.x;
+  const double wk1 = (k1 == 0 || 2 * k1 == g.n1) ? 1.0 : 2.0;
+  const long long row = (long long)k1 * g.n2 * g.n3 + (long long)k2 * g.n3;
+  {
+    bool any = false;
+    for (int L = Lbeg; L < Lend; ++L) any = any || it < stop_iter[L];
+    if (!any) return;
+  }
+  stage_twiddles<T>(twl, tw, N);
+  // the position's Green operator, scaled by -1/m, formed once for the chunk
+  {
+    const double scale = -1.0 / (double)g.m;
+    const int inst = inst_of[Lbeg];
+    const double mu0 = insts[inst].mu0, riso = insts[inst].riso;
+    for (int k3 = tid; k3 < N; k3 += NT) {
+      if (gmode == GREEN_TABLE) {
+        const T* tb = table + (long long)pos * 21 * N + k3;
+#pragma unroll
+        for (int t = 0; t < 21; ++t) Gl[t * N + k3] = (T)(scale * (double)tb[(long long)t * N]);
+      } else {
+        double Gd[21];
+        if (gmode == GREEN_ISO)
+          gamma_sym_iso(gp, mu0, riso, k1, k2, k3, Gd);
+        else
+          gamma_sym_at(gp, k1, k2, k3, Gd);
+#pragma unroll
+        for (int t = 0; t < 21; ++t) Gl[t * N + k3] = (T)(scale * Gd[t]);
+      }
+    }
+  }
+
+  for (int L0 = Lbeg; L0 < Lend; L0 += NL) {
+    const bool act0 = it < stop_iter[L0];
+    const bool act1 = NL == 2 && L0 + 1 < Lend && it < stop_iter[L0 + 1];
+    if (!act0 && !act1) continue;
+
+    // forward stage 0: global -> registers -> LDS
+    {
+      constexpr int R = RH.r[0];
+      constexpr int nbl = N / R;
+      constexpr int nu = NLN * nbl;
+      constexpr int NB = (nu + NT - 1) / NT;
+      T2 v[NB][R];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int u = tid + q * NT;
+        const int l = u / nbl, j = u % nbl;
+        const int sl = l / 6, c = l % 6;
+        const bool ok = (nu % NT == 0 || u < nu) && (sl == 0 ? act0 : act1);
+        const T2* src = tau + ((long long)((L0 + sl) * 6 + c)) * g.spec + row + j;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = ok ? src[r * nbl] : T2{0, 0};
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int u = tid + q * NT;
+        if (nu % NT == 0 || u < nu) {
+          const int l = u / nbl, j = u % nbl;
+          Bfly<T, -1, R>::run(v[q]);
+#pragma unroll
+          for (int r = 0; r < R; ++r) lines[l * LP + gpad(j * R + r)] = v[q][r];
+        }
+      }
+      __syncthreads();
+    }
+    g2_fwd_rest<T, N, NLN, NT, 1, RH.r[0]>(lines, twl);
+
+    // forward radix-2 last stage, -Gamma/m, inverse radix-2 first stage
+    {
+      constexpr int nu = NL * H;
+      constexpr int NB = (nu + NT - 1) / NT;
+      T2 o[NB][6][2];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int u = tid + q * NT;
+        if (nu % NT == 0 || u < nu) {
+          const int sl = u / H, j = u % H;
+          const T2 w = twl[j];
+          // stream over the input component J: bins j and j + N/2 of
+          // component J, then its column of Gamma into both outputs
+          T2 ya[6], yb[6];
+#pragma unroll
+          for (int I = 0; I < 6; ++I) {
+            ya[I] = T2{0, 0};
+            yb[I] = T2{0, 0};
+          }
+#pragma unroll
+          for (int J = 0; J < 6; ++J) {
+            const T2* ln = lines + (sl * 6 + J) * LP;
+            const T2 x0 = ln[gpad(j)];
+            const T2 x1 = cmul(ln[gpad(j + H)], w);
+            const T2 aJ = cadd(x0, x1);  // bin j
+            const T2 bJ = csub(x0, x1);  // bin j + N/2
+#pragma unroll
+            for (int I = 0; I < 6; ++I) {
+              const int t = I <= J ? tri_idx(I, J) : tri_idx(J, I);
+              const T ga = Gl[t * N + j], gb = Gl[t * N + j + H];
+              ya[I].x += ga * aJ.x;
+              ya[I].y += ga * aJ.y;
+              yb[I].x += gb * bJ.x;
+              yb[I].y += gb * bJ.y;
+            }
+          }
+#pragma unroll
+          for (int I = 0; I < 6; ++I) {
+            o[q][I][0] = cadd(ya[I], yb[I]);
+            o[q][I][1] = csub(ya[I], yb[I]);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int u = tid + q * NT;
+        if (nu % NT == 0 || u < nu) {
+          const int sl = u / H, j = u % H;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            T2* ln = lines + (sl * 6 + c) * LP;
+            ln[gpad(2 * j)] = o[q][c][0];
+            ln[gpad(2 * j + 1)] = o[q][c][1];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    g2_inv_mid<T, N, NLN, NT, 0, 2>(lines, twl);
+
+    // last inverse stage: LDS -> registers -> global, residual against P_old
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    {
+      constexpr int R = RH.r[RH.n - 1];
+      constexpr int NS = 2 * radprod(RH, RH.n - 1);
+      constexpr int nbl = N / R;
+      static_assert(NS == nbl, "last stage spans the line");
+      constexpr int nu = NLN * nbl;
+      constexpr int NB = (nu + NT - 1) / NT;
+      T2 v[NB][R], po[NB][R];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int u = tid + q * NT;
+        const int l = u / nbl, j = u % nbl;
+        const int sl = l / 6, c = l % 6;
+        const bool ok = (nu % NT == 0 || u < nu) && (sl == 0 ? act0 : act1);
+        const T2* src = Pold + ((long long)((L0 + sl) * 6 + c)) * g.spec + row + j;
+#pragma unroll
+        for (int r = 0; r < R; ++r) po[q][r] = ok ? src[r * nbl] : T2{0, 0};
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int u = tid + q * NT;
+        if (nu % NT == 0 || u < nu) {
+          const int l = u / nbl, j = u % nbl;
+          const T2* ln = lines + l * LP;
+#pragma unroll
+          for (int r = 0; r < R; ++r) v[q][r] = ln[gpad(j + r * nbl)];
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            T2 w = twl[r * j];
+            w.y = -w.y;
+            v[q][r] = cmul(v[q][r], w);
+          }
+          Bfly<T, +1, R>::run(v[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int u = tid + q * NT;
+        const int l = u / nbl, j = u % nbl;
+        const int sl = l / 6, c = l % 6;
+        if ((nu % NT == 0 || u < nu) && (sl == 0 ? act0 : act1)) {
+          T2* dstp = Pnew + ((long long)((L0 + sl) * 6 + c)) * g.spec + row + j;
+          double dd = 0.0, nn = 0.0;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const T2 nv = v[q][r], ov = po[q][r];
+            dstp[r * nbl] = nv;
+            const double dx = (double)nv.x - (double)ov.x, dy = (double)nv.y - (double)ov.y;
+            dd += dx * dx + dy * dy;
+            nn += (double)nv.x * (double)nv.x + (double)nv.y * (double)nv.y;
+          }
+          if (sl == 0) {
+            acc[0] += wk1 * dd;
+            acc[1] += wk1 * nn;
+          } else {
+            acc[2] += wk1 * dd;
+            acc[3] += wk1 * nn;
+          }
+        }
+      }
+    }
+    double tot[4];
+    block_sum<4>(acc, tot);
+    if (tid == 0) {
+      if (act0) {
+        partial[((long long)L0 * npos + pos) * 2] = tot[0];
+        partial[((long long)L0 * npos + pos) * 2 + 1] = tot[1];
+      }
+      if (act1) {
+        partial[((long long)(L0 + 1) * npos + pos) * 2] = tot[2];
+        partial[((long long)(L0 + 1) * npos + pos) * 2 + 1] = tot[3];
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------ finalisers ---

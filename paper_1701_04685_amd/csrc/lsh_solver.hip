@@ -82,11 +82,12 @@ struct KernSet {
                       const int*, const int*, const double*, const double*, double*, double*);
   using A2 = void (*)(Geo, FftPlan, const C2<T>*, const C2<T>*, C2<T>*, const int*, const int*, T);
   using GR = void (*)(Geo, FftPlan, const C2<T>*, GreenParams, const C2<T>*, const C2<T>*, C2<T>*, const T*,
-                      const Inst*, const int*, const int*, const int*, int, int, double*, int, int);
+                      const Inst*, const int*, const int*, const int*, const int*, int, int, double*, int, int);
   A1 a1[3] = {nullptr, nullptr, nullptr};  // MODE_STRESS, MODE_FINAL, MODE_INIT
   A2 a2[2] = {nullptr, nullptr};           // forward, inverse
   GR gr = nullptr;
   int W1 = 0, NT1 = 0, W2 = 0, NT2 = 0, NTG = 0, lsG = 0;
+  int green2 = 0;  // 1: k_green2 (grid: positions x load chunks), 0: k_green
   size_t lds1 = 0, lds2 = 0, ldsG = 0;
 };
 
@@ -189,11 +190,29 @@ bool choose_axis2(const Geo& g, const FftPlan& pl, KernSet<T>& K) {
   return K.lds2 <= (size_t)lds_limit();
 }
 
+template <int N, int NL>
+constexpr int green2_nt() {
+  int nt = (NL * 6 * (N / 8) + 63) / 64 * 64;
+  return nt < 64 ? 64 : (nt > 512 ? 512 : nt);
+}
+
 template <typename T, int NC>
-void green_special(KernSet<T>& K) {
-  constexpr int NT = NC <= 64 ? 64 : (NC <= 128 ? 128 : 256);
-  K.gr = k_green<T, NC, NT>;
-  K.NTG = NT;
+void green_special(const Geo& g, KernSet<T>& K) {
+  if constexpr (NC % 2 == 0) {
+    constexpr int NL = NC <= 128 ? 2 : 1;
+    constexpr int NT = green2_nt<NC, NL>();
+    K.gr = k_green2<T, NC, NL, NT>;
+    K.NTG = NT;
+    K.green2 = 1;
+    K.lsG = 0;
+    K.ldsG = sizeof(C2<T>) * (size_t)NC + sizeof(T) * 21 * (size_t)NC +
+             sizeof(C2<T>) * (size_t)NL * 6 * GreenPlan<NC>::LP;
+  } else {
+    constexpr int NT = NC <= 64 ? 64 : (NC <= 128 ? 128 : 256);
+    K.gr = k_green<T, NC, NT>;
+    K.NTG = NT;
+  }
+  (void)g;
 }
 
 template <typename T>
@@ -201,7 +220,7 @@ bool choose_green(const Geo& g, const FftPlan& pl, bool table, KernSet<T>& K) {
   bool ok = false;
   switch (g.n3) {
 #define X(N) \
-  case N: green_special<T, N>(K); ok = true; break;
+  case N: green_special<T, N>(g, K); ok = true; break;
     LSH_SPECIAL_SIZES(X)
 #undef X
     default: break;
@@ -215,9 +234,11 @@ bool choose_green(const Geo& g, const FftPlan& pl, bool table, KernSet<T>& K) {
     else K.gr = k_green<T, 0, 256>;
     K.NTG = nt;
   }
-  K.lsG = g.n3 + ((g.n3 % 2 == 0) ? 1 : 0);
   (void)table;
-  K.ldsG = sizeof(C2<T>) * ((size_t)g.n3 + 6 * (size_t)K.lsG);
+  if (!K.green2) {
+    K.lsG = g.n3 + ((g.n3 % 2 == 0) ? 1 : 0);
+    K.ldsG = sizeof(C2<T>) * ((size_t)g.n3 + 6 * (size_t)K.lsG);
+  }
   return K.ldsG <= (size_t)lds_limit();
 }
 
@@ -406,6 +427,7 @@ struct GroupWS {
   int* nonfinite;
   int* itp;
   int* inst_of;
+  int* chunks;  // per Green chunk: first load, end load (one instance, <= GCH loads)
   Inst* insts;
   size_t total;
 };
@@ -432,6 +454,7 @@ GroupWS group_layout(const Geo& g, int nload, int ninst, const KernSet<T>& K, ch
   w.nonfinite = (int*)(base + off); off += lsh_align(sizeof(int) * nload);
   w.itp = (int*)(base + off); off += lsh_align(sizeof(int));
   w.inst_of = (int*)(base + off); off += lsh_align(sizeof(int) * nload);
+  w.chunks = (int*)(base + off); off += lsh_align(sizeof(int) * 2 * nload);
   w.insts = (Inst*)(base + off); off += lsh_align(sizeof(Inst) * ninst);
   w.total = off;
   return w;
@@ -529,6 +552,7 @@ struct GroupRun {
   int nload;
   dim3 gridS, gridB, gridG;
   int npos, nblkS;
+  std::vector<int> chunks;  // Green chunks: (first load, end load) pairs
   std::vector<int> stop;
   std::vector<double> ring;
 };
@@ -552,7 +576,15 @@ int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
   const int nt3b = (G.g.n3 + G.K.W2 - 1) / G.K.W2;
   G.gridB = dim3(G.g.h1 * nt3b, 6, G.nload);
   G.npos = G.g.h1 * G.g.n2;
-  G.gridG = dim3((G.npos + 7) / 8 * 8 * G.nload);
+  G.chunks.clear();
+  for (int L = 0; L < G.nload;) {
+    int e = L + 1;
+    while (e < G.nload && e - L < GCH && G.spec.inst_of[e] == G.spec.inst_of[L]) ++e;
+    G.chunks.push_back(L);
+    G.chunks.push_back(e);
+    L = e;
+  }
+  G.gridG = G.K.green2 ? dim3(G.npos, (unsigned)(G.chunks.size() / 2)) : dim3((G.npos + 7) / 8 * 8 * G.nload);
   G.nblkS = G.g.n2 * nt3a;
   return LSH_OK;
 }
@@ -583,6 +615,7 @@ int group_init(GroupRun<T>& G, int max_iter, const double* dev_E_init, hipStream
   HIPCHK(hipMemcpyAsync(G.w.nonfinite, zeros.data(), sizeof(int) * nload, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(G.w.itp, &zero, sizeof(int), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(G.w.inst_of, G.spec.inst_of.data(), sizeof(int) * nload, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(G.w.chunks, G.chunks.data(), sizeof(int) * G.chunks.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(G.w.insts, ins.data(), sizeof(Inst) * ins.size(), hipMemcpyHostToDevice, st));
   const size_t fb = sizeof(T2) * 6 * (size_t)nload * G.g.spec;
   const lsh_pattern* p = G.spec.rep;
@@ -633,8 +666,9 @@ int group_iterate(GroupRun<T>& G, int cur, double tol, bool fixed, hipStream_t s
     Timer tm(2, st);
     hipLaunchKernelGGL(G.K.gr, G.gridG, dim3(G.K.NTG), G.K.ldsG, st, G.g, p->plan[2], tw[2], G.gp,
                        (const T2*)G.w.TAU, (const T2*)G.w.P[cur], (T2*)G.w.P[1 - cur], table,
-                       (const Inst*)G.w.insts, (const int*)G.w.inst_of, (const int*)G.w.stop_iter,
-                       (const int*)G.w.itp, G.nload, G.npos, G.w.partial, G.K.lsG, G.gmode);
+                       (const Inst*)G.w.insts, (const int*)G.w.inst_of, (const int*)G.w.chunks,
+                       (const int*)G.w.stop_iter, (const int*)G.w.itp, G.nload, G.npos, G.w.partial, G.K.lsG,
+                       G.gmode);
   }
   {
     Timer tm(3, st);
