@@ -177,6 +177,32 @@ int lsh_solve(lsh_pattern *p, int nload, const double *eps0_voigt, double tol, i
               const double *dev_E_init, double *dev_E_out, double *sigma_out,
               lsh_stats *stats, double *history);
 
+/* ------------------------------------------------------------------ autotuner ---
+ * Each pass of an iteration has kernel variants (the axis-1 stress pass with or
+ * without its middle stages fused in registers, the axis-2 tile width, one or
+ * two load cases per Green-pass block).  lsh_autotune times every variant of
+ * every pass on this pattern's own data (nload load cases, precision prec,
+ * from a zero start; a warm-up launch, then the mean of three) with HIP events
+ * on `stream`, and keeps the fastest for later lsh_solve and lsh_solve_batch
+ * calls of this pattern (as a batch group's first pattern) at that precision.
+ * The choice is dropped by lsh_set_kernel and lsh_tune_reset.  Needs the solve
+ * workspace (lsh_solve_bytes); its contents are scratch.  Synchronises `stream`.
+ *   out (optional): the chosen variant per pass (0 = the default), the number
+ *                   of variants and each variant's mean time in ms.
+ * Errors: LSH_EINVAL, LSH_ESTATE, LSH_EWORKSPACE, LSH_EDEVICE.                      */
+typedef struct {
+  int choice[3];   /* stress pass, axis-2 passes, Green pass */
+  int ncand[3];
+  float ms[3][4];
+} lsh_tune_result;
+
+int lsh_autotune(lsh_pattern *p, int nload, lsh_precision prec, void *dev_workspace, size_t ws_bytes,
+                 void *stream, lsh_tune_result *out);
+int lsh_tune_reset(lsh_pattern *p);
+/* Force the variants (choice[3], as in lsh_tune_result; an index beyond a
+ * pass's variant count selects its last variant), e.g. to check each variant.   */
+int lsh_tune_set(lsh_pattern *p, lsh_precision prec, const int *choice);
+
 /* -------------------------------------------------------------------- batches ---
  * Many microstructures and load cases in one call (the Basic Scheme of Sec. 4 for
  * each task, all advanced together).  Tasks whose patterns share M, the SNF

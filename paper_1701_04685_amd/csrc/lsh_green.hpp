@@ -292,16 +292,21 @@ __device__ inline void iso_matrix(const IsoMoments& M, double mu0, double r, dou
 }
 
 // Isotropic version of gamma_sym_at for the analytic kernels (Dirichlet,
-// modified Dirichlet, dlVP): same alias sets and symmetrisation.
-__device__ inline void gamma_sym_iso(const GreenParams& gp, double mu0, double r, int64_t b0, int64_t b1, int64_t b2,
-                                     double G[21]) {
+// modified Dirichlet, dlVP): same alias sets and symmetrisation.  The weighted
+// moments of the alias directions go into one accumulator: each
+// representative's weights are normalised up front (its weight sum factors
+// over the axes), so no second moment set is held.  out(t, v) receives the 21
+// entries.
+template <typename Out>
+__device__ inline void gamma_iso_emit(const GreenParams& gp, double mu0, double r, int64_t b0, int64_t b1, int64_t b2,
+                                      Out&& out) {
   const int64_t b[3] = {b0, b1, b2};
   int64_t h[3];
   for (int i = 0; i < 3; ++i) h[i] = gp.VT[3 * i] * b[0] + gp.VT[3 * i + 1] * b[1] + gp.VT[3 * i + 2] * b[2];
   int64_t hr[3], xn[3];
   reduce_freq(gp, h, hr, xn);
   if (hr[0] == 0 && hr[1] == 0 && hr[2] == 0) {
-    for (int t = 0; t < 21; ++t) G[t] = 0.0;
+    for (int t = 0; t < 21; ++t) out(t, 0.0);
     return;
   }
   IsoMoments M = {};
@@ -314,53 +319,78 @@ __device__ inline void gamma_sym_iso(const GreenParams& gp, double mu0, double r
       const int64_t hm[3] = {-hr[0], -hr[1], -hr[2]};
       reduce_freq(gp, hm, hh, xx);
     }
-    const double x0[3] = {(double)xx[0] * invm, (double)xx[1] * invm, (double)xx[2] * invm};
     // per axis: the offsets z_i in {0, +-1} whose weight is non-zero (the
     // trapezoid of half-width (1+alpha)/2 reaches at most one neighbour)
-    int nz[3];
-    int zz[3][2];
-    double wz[3][2];
+    int nz[3], zs[3];
+    double w0[3], w1[3];
+    double W = 1.0;  // sum over aliases of prod_i g_i^2 = prod_i sum_z g_i(z)^2
     for (int i = 0; i < 3; ++i) {
       nz[i] = 1;
-      zz[i][0] = 0;
+      zs[i] = 0;
+      w1[i] = 0.0;
       if (gp.kind == 0) {
-        wz[i][0] = 1.0;
+        w0[i] = 1.0;
         continue;
       }
+      const double x0 = (double)xx[i] * invm;
       const double a = gp.kind == 1 ? 0.0 : gp.alpha[i];
-      const double g0 = trap_weight(x0[i], a);
-      wz[i][0] = g0;
-      const int s = x0[i] < 0.0 ? 1 : -1;
-      const double g1 = trap_weight(x0[i] + s, a);
+      w0[i] = trap_weight(x0, a);
+      const int sgn = x0 < 0.0 ? 1 : -1;
+      const double g1 = trap_weight(x0 + sgn, a);
       if (g1 > 0.0) {
-        zz[i][1] = s;
-        wz[i][1] = g1;
+        zs[i] = sgn;
+        w1[i] = g1;
         nz[i] = 2;
       }
+      W *= w0[i] * w0[i] + w1[i] * w1[i];
     }
-    IsoMoments Mr = {};
-    for (int i0 = 0; i0 < nz[0]; ++i0)
-      for (int i1 = 0; i1 < nz[1]; ++i1)
-        for (int i2 = 0; i2 < nz[2]; ++i2) {
-          const double g = wz[0][i0] * wz[1][i1] * wz[2][i2];
-          const double w = g * g;
-          if (w <= 0.0) continue;
-          const int z0 = zz[0][i0], z1 = zz[1][i1], z2 = zz[2][i2];
-          const int64_t kk[3] = {hh[0] + gp.MT[0] * z0 + gp.MT[1] * z1 + gp.MT[2] * z2,
-                                 hh[1] + gp.MT[3] * z0 + gp.MT[4] * z1 + gp.MT[5] * z2,
-                                 hh[2] + gp.MT[6] * z0 + gp.MT[7] * z1 + gp.MT[8] * z2};
-          if (kk[0] == 0 && kk[1] == 0 && kk[2] == 0) {
-            Mr.w += w;
-            continue;
-          }
-          const double kd[3] = {(double)kk[0], (double)kk[1], (double)kk[2]};
-          iso_add(Mr, kd, w);
-        }
-    // each representative's sum is normalised by its own weight, then averaged
-    const double f = 1.0 / (Mr.w * nrep);
-    for (int i = 0; i < 6; ++i) M.a[i] += Mr.a[i] * f;
-    for (int i = 0; i < 15; ++i) M.q[i] += Mr.q[i] * f;
+    const double f = 1.0 / (W * nrep);
+    // one alias at a time (kept rolled: unrolled, the aliases' moments would
+    // all be live at once)
+    const int nal = nz[0] * nz[1] * nz[2];
+#pragma unroll 1
+    for (int c = 0; c < nal; ++c) {
+      const int i0 = c / (nz[1] * nz[2]), i1 = (c / nz[2]) % nz[1], i2 = c % nz[2];
+      const double g = (i0 ? w1[0] : w0[0]) * (i1 ? w1[1] : w0[1]) * (i2 ? w1[2] : w0[2]);
+      const double w = g * g * f;
+      if (w <= 0.0) continue;
+      // k = h + M^T z in double: every term is an integer below 2^53, exact
+      const double z0 = i0 ? (double)zs[0] : 0.0, z1 = i1 ? (double)zs[1] : 0.0, z2 = i2 ? (double)zs[2] : 0.0;
+      double kd[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        kd[i] = (double)hh[i] + (double)gp.MT[3 * i] * z0 + (double)gp.MT[3 * i + 1] * z1 +
+                (double)gp.MT[3 * i + 2] * z2;
+      if (kd[0] == 0.0 && kd[1] == 0.0 && kd[2] == 0.0) continue;
+      iso_add(M, kd, w);
+    }
   }
-  M.w = 1.0;
-  iso_matrix(M, mu0, r, G);
+  // Gamma0 = S(n)/mu0 - r Q(n) is linear in the moments (already normalised)
+  const double SQ2 = 1.41421356237309504880168872420969808;
+  const double imu = 1.0 / mu0;
+#pragma unroll
+  for (int I = 0; I < 6; ++I) {
+    int ia, ib;
+    mandel_pair(I, ia, ib);
+    const double cI = I < 3 ? 1.0 : SQ2;
+#pragma unroll
+    for (int J = I; J < 6; ++J) {
+      int ic, id;
+      mandel_pair(J, ic, id);
+      const double cJ = J < 3 ? 1.0 : SQ2;
+      auto Am = [&](int u, int v) {
+        const int lo = u < v ? u : v, hi = u < v ? v : u;
+        return lo == hi ? M.a[lo] : M.a[6 - lo - hi];
+      };
+      const double S = 0.25 * ((ib == ic) * Am(ia, id) + (ib == id) * Am(ia, ic) + (ia == ic) * Am(ib, id) +
+                               (ia == id) * Am(ib, ic));
+      const double Q = M.q[q4_index(ia, ib, ic, id)];
+      out(tri_idx(I, J), cI * cJ * (imu * S - r * Q));
+    }
+  }
+}
+
+__device__ inline void gamma_sym_iso(const GreenParams& gp, double mu0, double r, int64_t b0, int64_t b1, int64_t b2,
+                                     double G[21]) {
+  gamma_iso_emit(gp, mu0, r, b0, b1, b2, [&](int t, double v) { G[t] = v; });
 }

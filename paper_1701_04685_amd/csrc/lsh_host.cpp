@@ -307,6 +307,7 @@ extern "C" int lsh_pattern_points(const lsh_pattern* p, int64_t* y) {
 
 extern "C" int lsh_set_kernel(lsh_pattern* p, lsh_kernel kind, const double* params, int nparams) {
   if (!p) return lsh_fail(LSH_EINVAL, "null pattern");
+  p->tuned[0] = p->tuned[1] = 0;
   if (nparams < 0 || (nparams > 0 && !params)) return lsh_fail(LSH_EINVAL, "bad parameter array");
   for (int i = 0; i < nparams; ++i)
     if (!std::isfinite(params[i])) return lsh_fail(LSH_EINVAL, "non-finite kernel parameter");

@@ -38,6 +38,10 @@ struct lsh_pattern {
   char* dev_persist = nullptr;
   size_t off_phase = 0, off_tw[3] = {0, 0, 0}, off_table = 0, off_dmat = 0, off_cmat = 0;
   bool has_table = false;
+
+  // ---- kernel variants chosen by lsh_autotune, per precision (0: FP64, 1: FP32)
+  int tuned[2] = {0, 0};
+  int tune_choice[2][3] = {{0, 0, 0}, {0, 0, 0}};  // stress, axis 2, Green pass
 };
 
 // ---- helpers implemented in lsh_host.cpp

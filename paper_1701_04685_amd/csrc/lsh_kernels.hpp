@@ -193,27 +193,38 @@ __global__ void __launch_bounds__(NT) k_axis1(Geo g, FftPlan pl, const C2<T>* __
   if (MODE == MODE_STRESS) {
     const double* e0 = eps0 + 6 * L;
     const T ep[6] = {(T)e0[0], (T)e0[1], (T)e0[2], (T)e0[3], (T)e0[4], (T)e0[5]};
-    auto stress = [&](int idx, int p) {
+    // D points at LDS (Dl) or global memory (dmat); the two callers below are
+    // separate code paths so that LDS reads stay ds_read instructions
+    auto stress = [&](int idx, const T* D) {
       const int w = idx % W, a1 = idx / W;
       T2* z = Z + a1 * W3 + w;
       const T2 z0 = z[0], z1 = z[W], z2 = z[2 * W];
       const T E[6] = {z0.x + ep[0], z0.y + ep[1], z1.x + ep[2], z1.y + ep[3], z2.x + ep[4], z2.y + ep[5]};
       T t[6];
-      if (p < NDL)
-        stress6<T>(Dl + 36 * p, E, t);
-      else
-        stress6<T>(dmat + 36 * p, E, t);
+      stress6<T>(D, E, t);
       z[0] = T2{t[0], t[1]};
       z[W] = T2{t[2], t[3]};
       z[2 * W] = T2{t[4], t[5]};
     };
     if constexpr (NC > 0) {
+      if (nphase <= NDL) {
 #pragma unroll
-      for (int i = 0; i < QT; ++i)
-        if (ph[i] >= 0) stress(tid + i * NT, ph[i]);
+        for (int i = 0; i < QT; ++i)
+          if (ph[i] >= 0) stress(tid + i * NT, Dl + 36 * ph[i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < QT; ++i)
+          if (ph[i] >= 0) stress(tid + i * NT, dmat + 36 * ph[i]);
+      }
     } else {
       for (int idx = tid; idx < n1 * W; idx += NT)
-        if (a30 + idx % W < g.n3) stress(idx, phase[(long long)(idx / W) * n23 + colbase + idx % W]);
+        if (a30 + idx % W < g.n3) {
+          const int p = phase[(long long)(idx / W) * n23 + colbase + idx % W];
+          if (nphase <= NDL)
+            stress(idx, Dl + 36 * p);
+          else
+            stress(idx, dmat + 36 * p);
+        }
     }
   } else if (MODE == MODE_INIT) {
     const double SQ2I = 0.70710678118654752440;
@@ -475,11 +486,20 @@ __host__ __device__ constexpr int gpad(int i) { return i + (i >> 3); }
 
 template <int N> struct GreenPlan {
   static constexpr RadList RH = make_radlist(N / 2);
-  static constexpr int LP = N + N / 8;
+  // line stride: the padded length plus one, odd, so that the same entry of
+  // neighbouring lines falls in different LDS banks
+  static constexpr int LP = N + N / 8 + 1;
 };
 
-// fixed-radix stage over NLN lines in LDS (in place)
-template <typename T, int DIR, int N, int R, int NS, int NLN, int NT>
+// element p of a line stored at (p >> 1) + (p & 1) N/2: the layout the
+// middle (Green) stage leaves behind, read by the next stage
+template <int N> __device__ __forceinline__ int g2_perm(int p) { return (p >> 1) + (p & 1) * (N / 2); }
+
+// fixed-radix stage over NLN lines in LDS (in place); PERM: the input is in
+// the g2_perm layout; LF: consecutive lanes take consecutive lines at the
+// same j (they read the same twiddles, an LDS broadcast), else consecutive j
+// of one line
+template <typename T, int DIR, int N, int R, int NS, int NLN, int NT, bool PERM = false, bool LF = false>
 __device__ __forceinline__ void g2_stage(C2<T>* lines, const C2<T>* __restrict__ twl) {
   using T2 = C2<T>;
   constexpr int LP = GreenPlan<N>::LP;
@@ -495,10 +515,10 @@ __device__ __forceinline__ void g2_stage(C2<T>* lines, const C2<T>* __restrict__
     const int u = tid + q * NT;
     dst[q] = -1;
     if (nu % NT == 0 || u < nu) {
-      const int l = u / nbl, j = u % nbl;
+      const int l = LF ? u % NLN : u / nbl, j = LF ? u / NLN : u % nbl;
       const T2* src = lines + l * LP;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = src[gpad(j + r * nbl)];
+      for (int r = 0; r < R; ++r) v[q][r] = src[gpad(PERM ? g2_perm<N>(j + r * nbl) : j + r * nbl)];
       const int k = j % NS;
       if (NS > 1 && k != 0) {
 #pragma unroll
@@ -537,8 +557,28 @@ template <typename T, int N, int NLN, int NT, int S, int NS>
 __device__ __forceinline__ void g2_inv_mid(C2<T>* lines, const C2<T>* twl) {
   constexpr RadList RH = GreenPlan<N>::RH;
   if constexpr (S + 1 < RH.n) {
-    g2_stage<T, +1, N, RH.r[S], NS, NLN, NT>(lines, twl);
+    g2_stage<T, +1, N, RH.r[S], NS, NLN, NT, S == 0>(lines, twl);
     g2_inv_mid<T, N, NLN, NT, S + 1, NS * RH.r[S]>(lines, twl);
+  }
+}
+// inverse stages S.. of the half-length radix list, starting at NS (the
+// final radix-2 stage is left to the caller)
+template <typename T, int N, int NLN, int NT, int S, int NS>
+__device__ __forceinline__ void g2_inv_all_but_last(C2<T>* lines, const C2<T>* twl) {
+  constexpr RadList RH = GreenPlan<N>::RH;
+  if constexpr (S < RH.n) {
+    g2_stage<T, +1, N, RH.r[S], NS, NLN, NT, false, true>(lines, twl);
+    g2_inv_all_but_last<T, N, NLN, NT, S + 1, NS * RH.r[S]>(lines, twl);
+  }
+}
+// forward stages S.. after a radix-2 first stage (NS from 2), the first one
+// reading the g2_perm layout
+template <typename T, int N, int NLN, int NT, int S, int NS>
+__device__ __forceinline__ void g2_fwd_after2(C2<T>* lines, const C2<T>* twl) {
+  constexpr RadList RH = GreenPlan<N>::RH;
+  if constexpr (S < RH.n) {
+    g2_stage<T, -1, N, RH.r[S], NS, NLN, NT, S == 0, true>(lines, twl);
+    g2_fwd_after2<T, N, NLN, NT, S + 1, NS * RH.r[S]>(lines, twl);
   }
 }
 __host__ __device__ constexpr int radprod(RadList L, int upto) {
@@ -547,7 +587,7 @@ __host__ __device__ constexpr int radprod(RadList L, int upto) {
   return p;
 }
 
-template <typename T, int N, int NL, int NT>
+template <typename T, int N, int NL, int NT, int GM>
 __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* __restrict__ tw, GreenParams gp,
                                                const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
                                                C2<T>* __restrict__ Pnew, const T* __restrict__ table,
@@ -560,6 +600,7 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
   (void)pl;
   (void)ls_unused;
   (void)nload;
+  (void)gmode;
   constexpr RadList RH = GreenPlan<N>::RH;
   constexpr int LP = GreenPlan<N>::LP;
   constexpr int H = N / 2;
@@ -568,6 +609,7 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
   T2* twl = reinterpret_cast<T2*>(smem_raw);
   T* Gl = reinterpret_cast<T*>(twl + N);           // [21][N]
   T2* lines = reinterpret_cast<T2*>(Gl + 21 * N);  // [NL][6][LP]
+  T2* twL = lines + NL * 6 * LP;                   // last inverse stage: [r-1][j] = tw[r j]
   const int pos = blockIdx.x;
   // a chunk holds up to GCH consecutive loads of one instance
   const int Lbeg = chunks[2 * blockIdx.y], Lend = chunks[2 * blockIdx.y + 1];
@@ -582,22 +624,52 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
     if (!any) return;
   }
   stage_twiddles<T>(twl, tw, N);
+  // forward stage 0 reads tau straight from global memory; the next pair's
+  // loads are issued while the current pair is transformed
+  constexpr int R0 = RH.r[0];
+  constexpr int nbl0 = N / R0;
+  constexpr int nu0 = NLN * nbl0;
+  constexpr int NB0 = (nu0 + NT - 1) / NT;
+  T2 pf[NB0][R0];
+  // last inverse stage geometry
+  constexpr int RL = RH.r[RH.n - 1];
+  constexpr int nblL = N / RL;
+  static_assert(2 * radprod(RH, RH.n - 1) == nblL, "last stage spans the line");
+  constexpr int nuL = NLN * nblL;
+  constexpr int NBL = (nuL + NT - 1) / NT;
+  auto load0 = [&](int Lb) {
+    const bool a0 = Lb < Lend && it < stop_iter[Lb];
+    const bool a1 = NL == 2 && Lb + 1 < Lend && it < stop_iter[Lb + 1];
+#pragma unroll
+    for (int q = 0; q < NB0; ++q) {
+      const int u = tid + q * NT;
+      const int l = u / nbl0, j = u % nbl0;
+      const int sl = l / 6, c = l % 6;
+      const bool ok = (nu0 % NT == 0 || u < nu0) && (sl == 0 ? a0 : a1);
+      const T2* src = tau + ((long long)((Lb + sl) * 6 + c)) * g.spec + row + j;
+#pragma unroll
+      for (int r = 0; r < R0; ++r) pf[q][r] = ok ? src[r * nbl0] : T2{0, 0};
+    }
+  };
+  load0(Lbeg);  // in flight while the Green operator is formed
+  for (int i = tid; i < (RL - 1) * nblL; i += NT) twL[i] = tw[(i / nblL + 1) * (i % nblL)];
+
   // the position's Green operator, scaled by -1/m, formed once for the chunk
+  // (GM: GREEN_ISO moment form, GREEN_GENERAL on the fly, GREEN_TABLE rows)
   {
     const double scale = -1.0 / (double)g.m;
-    const int inst = inst_of[Lbeg];
-    const double mu0 = insts[inst].mu0, riso = insts[inst].riso;
     for (int k3 = tid; k3 < N; k3 += NT) {
-      if (gmode == GREEN_TABLE) {
+      if constexpr (GM == GREEN_TABLE) {
         const T* tb = table + (long long)pos * 21 * N + k3;
 #pragma unroll
         for (int t = 0; t < 21; ++t) Gl[t * N + k3] = (T)(scale * (double)tb[(long long)t * N]);
+      } else if constexpr (GM == GREEN_ISO) {
+        const int inst = inst_of[Lbeg];
+        gamma_iso_emit(gp, insts[inst].mu0, insts[inst].riso, k1, k2, k3,
+                       [&](int t, double v) { Gl[t * N + k3] = (T)(scale * v); });
       } else {
         double Gd[21];
-        if (gmode == GREEN_ISO)
-          gamma_sym_iso(gp, mu0, riso, k1, k2, k3, Gd);
-        else
-          gamma_sym_at(gp, k1, k2, k3, Gd);
+        gamma_sym_at(gp, k1, k2, k3, Gd);
 #pragma unroll
         for (int t = 0; t < 21; ++t) Gl[t * N + k3] = (T)(scale * Gd[t]);
       }
@@ -607,93 +679,83 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
   for (int L0 = Lbeg; L0 < Lend; L0 += NL) {
     const bool act0 = it < stop_iter[L0];
     const bool act1 = NL == 2 && L0 + 1 < Lend && it < stop_iter[L0 + 1];
-    if (!act0 && !act1) continue;
+    if (!act0 && !act1) {
+      load0(L0 + NL);
+      continue;
+    }
 
-    // forward stage 0: global -> registers -> LDS
+    // forward stage 0 (Stockham, NS = 1) on the loaded lines -> LDS
     {
-      constexpr int R = RH.r[0];
-      constexpr int nbl = N / R;
-      constexpr int nu = NLN * nbl;
-      constexpr int NB = (nu + NT - 1) / NT;
-      T2 v[NB][R];
+      T2 v[NB0][R0];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
+      for (int q = 0; q < NB0; ++q)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[q][r] = pf[q][r];
+      if (L0 + NL < Lend) load0(L0 + NL);
+#pragma unroll
+      for (int q = 0; q < NB0; ++q) {
         const int u = tid + q * NT;
-        const int l = u / nbl, j = u % nbl;
-        const int sl = l / 6, c = l % 6;
-        const bool ok = (nu % NT == 0 || u < nu) && (sl == 0 ? act0 : act1);
-        const T2* src = tau + ((long long)((L0 + sl) * 6 + c)) * g.spec + row + j;
+        if (nu0 % NT == 0 || u < nu0) {
+          const int l = u / nbl0, j = u % nbl0;
+          Bfly<T, -1, R0>::run(v[q]);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q][r] = ok ? src[r * nbl] : T2{0, 0};
-      }
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int u = tid + q * NT;
-        if (nu % NT == 0 || u < nu) {
-          const int l = u / nbl, j = u % nbl;
-          Bfly<T, -1, R>::run(v[q]);
-#pragma unroll
-          for (int r = 0; r < R; ++r) lines[l * LP + gpad(j * R + r)] = v[q][r];
+          for (int r = 0; r < R0; ++r) lines[l * LP + gpad(j * R0 + r)] = v[q][r];
         }
       }
       __syncthreads();
     }
+    // the previous iterate for the residual: loads issued now, used at the end
+    T2 po[NBL][RL];
+#pragma unroll
+    for (int q = 0; q < NBL; ++q) {
+      const int u = tid + q * NT;
+      const int l = u / nblL, j = u % nblL;
+      const int sl = l / 6, c = l % 6;
+      const bool ok = (nuL % NT == 0 || u < nuL) && (sl == 0 ? act0 : act1);
+      const T2* src = Pold + ((long long)((L0 + sl) * 6 + c)) * g.spec + row + j;
+#pragma unroll
+      for (int r = 0; r < RL; ++r) po[q][r] = ok ? src[r * nblL] : T2{0, 0};
+    }
     g2_fwd_rest<T, N, NLN, NT, 1, RH.r[0]>(lines, twl);
 
-    // forward radix-2 last stage, -Gamma/m, inverse radix-2 first stage
+    // forward radix-2 last stage, -Gamma/m, inverse radix-2 first stage.
+    // Outputs go back to the entries j and j + N/2 that were read (the
+    // g2_perm layout): no thread's input is overwritten by another thread,
+    // so no barrier is needed before the writes.
     {
       constexpr int nu = NL * H;
       constexpr int NB = (nu + NT - 1) / NT;
-      T2 o[NB][6][2];
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const int u = tid + q * NT;
         if (nu % NT == 0 || u < nu) {
           const int sl = u / H, j = u % H;
           const T2 w = twl[j];
-          // stream over the input component J: bins j and j + N/2 of
-          // component J, then its column of Gamma into both outputs
-          T2 ya[6], yb[6];
-#pragma unroll
-          for (int I = 0; I < 6; ++I) {
-            ya[I] = T2{0, 0};
-            yb[I] = T2{0, 0};
-          }
-#pragma unroll
-          for (int J = 0; J < 6; ++J) {
-            const T2* ln = lines + (sl * 6 + J) * LP;
-            const T2 x0 = ln[gpad(j)];
-            const T2 x1 = cmul(ln[gpad(j + H)], w);
-            const T2 aJ = cadd(x0, x1);  // bin j
-            const T2 bJ = csub(x0, x1);  // bin j + N/2
-#pragma unroll
-            for (int I = 0; I < 6; ++I) {
-              const int t = I <= J ? tri_idx(I, J) : tri_idx(J, I);
-              const T ga = Gl[t * N + j], gb = Gl[t * N + j + H];
-              ya[I].x += ga * aJ.x;
-              ya[I].y += ga * aJ.y;
-              yb[I].x += gb * bJ.x;
-              yb[I].y += gb * bJ.y;
-            }
-          }
-#pragma unroll
-          for (int I = 0; I < 6; ++I) {
-            o[q][I][0] = cadd(ya[I], yb[I]);
-            o[q][I][1] = csub(ya[I], yb[I]);
-          }
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int u = tid + q * NT;
-        if (nu % NT == 0 || u < nu) {
-          const int sl = u / H, j = u % H;
+          T2 a[6], b[6];
 #pragma unroll
           for (int c = 0; c < 6; ++c) {
-            T2* ln = lines + (sl * 6 + c) * LP;
-            ln[gpad(2 * j)] = o[q][c][0];
-            ln[gpad(2 * j + 1)] = o[q][c][1];
+            const T2* ln = lines + (sl * 6 + c) * LP;
+            const T2 x0 = ln[gpad(j)];
+            const T2 x1 = cmul(ln[gpad(j + H)], w);
+            a[c] = cadd(x0, x1);  // bin j
+            b[c] = csub(x0, x1);  // bin j + N/2
+          }
+#pragma unroll
+          for (int I = 0; I < 6; ++I) {
+            T2 ya = T2{0, 0}, yb = T2{0, 0};
+#pragma unroll
+            for (int J = 0; J < 6; ++J) {
+              const int t = I <= J ? tri_idx(I, J) : tri_idx(J, I);
+              const T ga = Gl[t * N + j], gb = Gl[t * N + j + H];
+              ya.x += ga * a[J].x;
+              ya.y += ga * a[J].y;
+              yb.x += gb * b[J].x;
+              yb.y += gb * b[J].y;
+            }
+            T2* ln = lines + (sl * 6 + I) * LP;
+            ln[gpad(j)] = cadd(ya, yb);      // inverse radix-2 output 2j
+            ln[gpad(j + H)] = csub(ya, yb);  // inverse radix-2 output 2j + 1
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
@@ -704,23 +766,11 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
     // last inverse stage: LDS -> registers -> global, residual against P_old
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     {
-      constexpr int R = RH.r[RH.n - 1];
-      constexpr int NS = 2 * radprod(RH, RH.n - 1);
-      constexpr int nbl = N / R;
-      static_assert(NS == nbl, "last stage spans the line");
-      constexpr int nu = NLN * nbl;
-      constexpr int NB = (nu + NT - 1) / NT;
-      T2 v[NB][R], po[NB][R];
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int u = tid + q * NT;
-        const int l = u / nbl, j = u % nbl;
-        const int sl = l / 6, c = l % 6;
-        const bool ok = (nu % NT == 0 || u < nu) && (sl == 0 ? act0 : act1);
-        const T2* src = Pold + ((long long)((L0 + sl) * 6 + c)) * g.spec + row + j;
-#pragma unroll
-        for (int r = 0; r < R; ++r) po[q][r] = ok ? src[r * nbl] : T2{0, 0};
-      }
+      constexpr int R = RL;
+      constexpr int nbl = nblL;
+      constexpr int nu = nuL;
+      constexpr int NB = NBL;
+      T2 v[NB][R];
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const int u = tid + q * NT;
@@ -728,10 +778,10 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
           const int l = u / nbl, j = u % nbl;
           const T2* ln = lines + l * LP;
 #pragma unroll
-          for (int r = 0; r < R; ++r) v[q][r] = ln[gpad(j + r * nbl)];
+          for (int r = 0; r < R; ++r) v[q][r] = ln[gpad(RH.n == 1 ? g2_perm<N>(j + r * nbl) : j + r * nbl)];
 #pragma unroll
           for (int r = 1; r < R; ++r) {
-            T2 w = twl[r * j];
+            T2 w = twL[(r - 1) * nbl + j];
             w.y = -w.y;
             v[q][r] = cmul(v[q][r], w);
           }
@@ -774,6 +824,185 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
       if (act1) {
         partial[((long long)(L0 + 1) * npos + pos) * 2] = tot[2];
         partial[((long long)(L0 + 1) * npos + pos) * 2 + 1] = tot[3];
+      }
+    }
+  }
+}
+
+// ------------------------------------------- axis-1 stress pass, fused ---
+// The stress pass of k_axis1 (MODE_STRESS) with its middle in registers:
+// the C2R along axis 1 (component pairs share a complex line) runs all its
+// Stockham stages but the last in LDS; the last inverse radix-2 stage, the
+// stress tau = (C - C0):(E + eps0) at the two points a1 = j and j + n1/2, and
+// the first forward radix-2 stage of the R2C run on one thread that holds the
+// three pair lines of one column.  Its outputs go back to the entries it read
+// (g2_perm layout).  Lines are line-major in LDS with one pad slot per 8.
+template <typename T, int N, int W, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_axis1s(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
+                                               const C2<T>* __restrict__ X, C2<T>* __restrict__ Y,
+                                               const Inst* __restrict__ insts, const int* __restrict__ inst_of,
+                                               const double* __restrict__ eps0, const int* __restrict__ stop_iter,
+                                               const int* __restrict__ itp, const double* __restrict__ Einit,
+                                               const double* __restrict__ means, double* __restrict__ Eout,
+                                               double* __restrict__ partial) {
+  using T2 = C2<T>;
+  (void)pl;
+  (void)Einit;
+  (void)means;
+  (void)Eout;
+  (void)partial;
+  constexpr RadList RH = GreenPlan<N>::RH;
+  constexpr int LP = GreenPlan<N>::LP;
+  constexpr int H = N / 2;
+  constexpr int h1 = N / 2 + 1;
+  constexpr int NLN = 3 * W;
+  constexpr int NDL = 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* twl = reinterpret_cast<T2*>(smem_raw);
+  T* Dl = reinterpret_cast<T*>(twl + N);                 // 36 * NDL
+  T2* lines = reinterpret_cast<T2*>(Dl + 36 * NDL);      // [3][W][LP]
+  uint8_t* phl = reinterpret_cast<uint8_t*>(lines + 3 * W * LP);  // [a1][w]
+  const int L = blockIdx.y;
+  if (*itp >= stop_iter[L]) return;
+  const Inst& in = insts[inst_of[L]];
+  const uint8_t* __restrict__ phase = in.phase;
+  const T* __restrict__ dmat = reinterpret_cast<const T*>(in.dmat);
+  const int nphase = in.nphase;
+  const int ntile3 = (g.n3 + W - 1) / W;
+  const int a2 = blockIdx.x / ntile3;
+  const int a30 = (blockIdx.x % ntile3) * W;
+  const long long n23 = (long long)g.n2 * g.n3;
+  const long long colbase = (long long)a2 * g.n3 + a30;
+  const int tid = threadIdx.x;
+
+  // half spectra of the three pairs, w fastest (coalesced along i3)
+  constexpr int npairs = h1 * NLN;
+  constexpr int PT = (npairs + NT - 1) / NT;
+  T2 ra[PT], rb[PT];
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int idx = tid + i * NT;
+    const int w = idx % W, q = (idx / W) % 3, k = idx / NLN;
+    ra[i] = T2{0, 0};
+    rb[i] = T2{0, 0};
+    if ((npairs % NT == 0 || idx < npairs) && a30 + w < g.n3) {
+      const long long off = (long long)k * n23 + colbase + w;
+      ra[i] = X[((long long)(L * 6 + 2 * q)) * g.spec + off];
+      rb[i] = X[((long long)(L * 6 + 2 * q + 1)) * g.spec + off];
+    }
+  }
+  // phase indices of the tile, [a1][w], loaded coalesced along i3
+  constexpr int nuM = W * H;
+  constexpr int NBM = (nuM + NT - 1) / NT;
+  constexpr int NPH = N * W;
+  constexpr int QP = (NPH + NT - 1) / NT;
+  int phr[QP];
+#pragma unroll
+  for (int i = 0; i < QP; ++i) {
+    const int idx = tid + i * NT;
+    const int w = idx % W, a1 = idx / W;
+    phr[i] = ((NPH % NT == 0 || idx < NPH) && a30 + w < g.n3) ? phase[(long long)a1 * n23 + colbase + w] : 0;
+  }
+  stage_twiddles<T>(twl, tw, N);
+  {
+    const int nd = nphase < NDL ? nphase : NDL;
+    for (int i = tid; i < 36 * nd; i += NT) Dl[i] = dmat[i];
+  }
+#pragma unroll
+  for (int i = 0; i < QP; ++i) {
+    const int idx = tid + i * NT;
+    if (NPH % NT == 0 || idx < NPH) phl[idx] = (uint8_t)phr[i];
+  }
+  // Hermitian extension: Z_q[k] = X_{2q}[k] + i X_{2q+1}[k] on the full line
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int idx = tid + i * NT;
+    if (npairs % NT == 0 || idx < npairs) {
+      const int w = idx % W, q = (idx / W) % 3, k = idx / NLN;
+      const T2 a = ra[i], b = rb[i];
+      T2* ln = lines + (q * W + w) * LP;
+      if (k == 0 || k == H) {
+        ln[gpad(k)] = T2{a.x, b.x};
+      } else {
+        ln[gpad(k)] = T2{a.x - b.y, a.y + b.x};
+        ln[gpad(N - k)] = T2{a.x + b.y, b.x - a.y};
+      }
+    }
+  }
+  __syncthreads();
+  // inverse stages but the last (radix 2)
+  g2_inv_all_but_last<T, N, NLN, NT, 0, 1>(lines, twl);
+
+  // last inverse radix-2, stress at two points, first forward radix-2
+  {
+    const double* e0 = eps0 + 6 * L;
+    const T ep[6] = {(T)e0[0], (T)e0[1], (T)e0[2], (T)e0[3], (T)e0[4], (T)e0[5]};
+#pragma unroll
+    for (int qq = 0; qq < NBM; ++qq) {
+      const int u = tid + qq * NT;
+      if (nuM % NT == 0 || u < nuM) {
+        const int j = u % H, w = u / H;  // j fastest: lanes walk one line
+        const int p0 = phl[j * W + w], p1 = phl[(j + H) * W + w];
+        T2 wv = twl[j];
+        wv.y = -wv.y;
+        T2 z0[3], z1[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const T2* ln = lines + (q * W + w) * LP;
+          const T2 x0 = ln[gpad(j)];
+          const T2 x1 = cmul(ln[gpad(j + H)], wv);
+          z0[q] = cadd(x0, x1);  // a1 = j
+          z1[q] = csub(x0, x1);  // a1 = j + N/2
+        }
+        T2 t0[3], t1[3];
+        {
+          const T E[6] = {z0[0].x + ep[0], z0[0].y + ep[1], z0[1].x + ep[2],
+                          z0[1].y + ep[3], z0[2].x + ep[4], z0[2].y + ep[5]};
+          T t[6];
+          stress6<T>(nphase <= NDL ? Dl + 36 * p0 : Dl, E, t);
+          if (nphase > NDL) stress6<T>(dmat + 36 * p0, E, t);
+          t0[0] = T2{t[0], t[1]};
+          t0[1] = T2{t[2], t[3]};
+          t0[2] = T2{t[4], t[5]};
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        {
+          const T E[6] = {z1[0].x + ep[0], z1[0].y + ep[1], z1[1].x + ep[2],
+                          z1[1].y + ep[3], z1[2].x + ep[4], z1[2].y + ep[5]};
+          T t[6];
+          stress6<T>(nphase <= NDL ? Dl + 36 * p1 : Dl, E, t);
+          if (nphase > NDL) stress6<T>(dmat + 36 * p1, E, t);
+          t1[0] = T2{t[0], t[1]};
+          t1[1] = T2{t[2], t[3]};
+          t1[2] = T2{t[4], t[5]};
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          T2* ln = lines + (q * W + w) * LP;
+          ln[gpad(j)] = cadd(t0[q], t1[q]);      // forward radix-2 output 2j
+          ln[gpad(j + H)] = csub(t0[q], t1[q]);  // forward radix-2 output 2j + 1
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // remaining forward stages, the first reading the g2_perm layout
+  g2_fwd_after2<T, N, NLN, NT, 0, 2>(lines, twl);
+
+  // unpack the pairs and store the half spectrum k < h1
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int idx = tid + i * NT;
+    if (npairs % NT == 0 || idx < npairs) {
+      const int w = idx % W, q = (idx / W) % 3, k = idx / NLN;
+      if (a30 + w < g.n3) {
+        const T2* ln = lines + (q * W + w) * LP;
+        const T2 zk = ln[gpad(k)];
+        const T2 zn = ln[gpad((N - k) % N)];
+        const T hf = (T)0.5;
+        const long long off = (long long)k * n23 + colbase + w;
+        Y[((long long)(L * 6 + 2 * q)) * g.spec + off] = T2{hf * (zk.x + zn.x), hf * (zk.y - zn.y)};
+        Y[((long long)(L * 6 + 2 * q + 1)) * g.spec + off] = T2{hf * (zk.y + zn.y), hf * (zn.x - zk.x)};
       }
     }
   }

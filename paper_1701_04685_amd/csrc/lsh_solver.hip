@@ -86,7 +86,18 @@ struct KernSet {
   A1 a1[3] = {nullptr, nullptr, nullptr};  // MODE_STRESS, MODE_FINAL, MODE_INIT
   A2 a2[2] = {nullptr, nullptr};           // forward, inverse
   GR gr = nullptr;
+  GR gr2[3] = {nullptr, nullptr, nullptr};  // k_green2 per Green mode (ISO, GENERAL, TABLE)
   int W1 = 0, NT1 = 0, W2 = 0, NT2 = 0, NTG = 0, lsG = 0;
+  A1 a1s = nullptr;  // fused stress pass (k_axis1s) when the line length allows it
+  int NT1s = 0;
+  size_t lds1s = 0;
+  // autotuner candidates per pass; entry 0 is the default
+  struct CStress { A1 fused; int nt; size_t lds; };
+  struct CAxis2 { A2 fwd, inv; int W, nt; size_t lds; };
+  struct CGreen { GR fn[3]; int nt; size_t lds; };
+  std::vector<CStress> c1;
+  std::vector<CAxis2> c2;
+  std::vector<CGreen> cg;
   int green2 = 0;  // 1: k_green2 (grid: positions x load chunks), 0: k_green
   size_t lds1 = 0, lds2 = 0, ldsG = 0;
 };
@@ -109,6 +120,13 @@ void put_axis1(KernSet<T>& K) {
   K.NT1 = 256;
 }
 
+template <int N, int W>
+constexpr int axis1s_nt() {
+  int a = W * (N / 2), b = 3 * W * (N / 8);
+  int nt = ((a > b ? a : b) + 63) / 64 * 64;
+  return nt < 64 ? 64 : nt;
+}
+
 template <typename T, int NC>
 bool axis1_special(const Geo& g, KernSet<T>& K) {
   constexpr int W = pick_w(NC, 3 * (int)sizeof(C2<T>), 16, 60 * 1024);
@@ -122,12 +140,21 @@ bool axis1_special(const Geo& g, KernSet<T>& K) {
   } else {
     put_axis1<T, NC, W>(K);
   }
+  K.c1.clear();
+  K.c1.push_back({nullptr, 0, 0});  // k_axis1 (MODE_STRESS)
+  if constexpr (NC % 2 == 0 && axis1s_nt<NC, W>() <= 1024) {
+    constexpr int NT = axis1s_nt<NC, W>();
+    const size_t lds = sizeof(C2<T>) * (size_t)NC + sizeof(T) * 36 * 16 +
+                       sizeof(C2<T>) * 3 * (size_t)W * GreenPlan<NC>::LP + (size_t)NC * W;
+    if (lds <= (size_t)lds_limit()) K.c1.push_back({k_axis1s<T, NC, W, NT>, NT, lds});
+  }
   return true;
 }
 
 template <typename T>
 bool choose_axis1(const Geo& g, const FftPlan& pl, KernSet<T>& K) {
   bool ok = false;
+  K.c1.clear();
   switch (g.n1) {
 #define X(N) \
   case N: ok = axis1_special<T, N>(g, K); break;
@@ -147,6 +174,7 @@ bool choose_axis1(const Geo& g, const FftPlan& pl, KernSet<T>& K) {
       return false;
   }
   K.lds1 = sizeof(C2<T>) * ((size_t)g.n1 + (size_t)g.n1 * 3 * K.W1) + sizeof(T) * 36 * 16;
+  if (K.c1.empty()) K.c1.push_back({nullptr, 0, 0});
   return K.lds1 <= (size_t)lds_limit();
 }
 
@@ -163,12 +191,18 @@ bool axis2_special(const Geo& g, KernSet<T>& K) {
   constexpr int W = pick_w(NC, (int)sizeof(C2<T>), sizeof(T) == 8 ? 16 : 32, 32 * 1024);
   if (g.n3 < W) return false;
   put_axis2<T, NC, W>(K);
+  if constexpr (W >= 4) {
+    constexpr int Wh = W / 2;
+    K.c2.push_back({k_axis2<T, -1, NC, Wh, 256>, k_axis2<T, +1, NC, Wh, 256>, Wh, 256,
+                    sizeof(C2<T>) * ((size_t)NC + (size_t)NC * Wh)});
+  }
   return true;
 }
 
 template <typename T>
 bool choose_axis2(const Geo& g, const FftPlan& pl, KernSet<T>& K) {
   bool ok = false;
+  K.c2.clear();
   switch (g.n2) {
 #define X(N) \
   case N: ok = axis2_special<T, N>(g, K); break;
@@ -187,31 +221,53 @@ bool choose_axis2(const Geo& g, const FftPlan& pl, KernSet<T>& K) {
       return false;
   }
   K.lds2 = sizeof(C2<T>) * ((size_t)g.n2 + (size_t)g.n2 * K.W2);
+  K.c2.insert(K.c2.begin(), {K.a2[0], K.a2[1], K.W2, K.NT2, K.lds2});
   return K.lds2 <= (size_t)lds_limit();
 }
 
 template <int N, int NL>
 constexpr int green2_nt() {
+  // one thread per radix-8 butterfly over all lines of a pass
   int nt = (NL * 6 * (N / 8) + 63) / 64 * 64;
   return nt < 64 ? 64 : (nt > 512 ? 512 : nt);
 }
 
+template <typename T, int NC, int NL>
+typename KernSet<T>::CGreen green2_cand() {
+  constexpr int NT = green2_nt<NC, NL>();
+  constexpr RadList RH = GreenPlan<NC>::RH;
+  constexpr int RL = RH.r[RH.n - 1];
+  typename KernSet<T>::CGreen c;
+  c.fn[GREEN_ISO] = k_green2<T, NC, NL, NT, GREEN_ISO>;
+  c.fn[GREEN_GENERAL] = k_green2<T, NC, NL, NT, GREEN_GENERAL>;
+  c.fn[GREEN_TABLE] = k_green2<T, NC, NL, NT, GREEN_TABLE>;
+  c.nt = NT;
+  c.lds = sizeof(C2<T>) * (size_t)NC + sizeof(T) * 21 * (size_t)NC + sizeof(C2<T>) * (size_t)NL * 6 * GreenPlan<NC>::LP +
+          sizeof(C2<T>) * (size_t)(RL - 1) * (NC / RL);
+  return c;
+}
+
 template <typename T, int NC>
 void green_special(const Geo& g, KernSet<T>& K) {
+  K.cg.clear();
   if constexpr (NC % 2 == 0) {
-    constexpr int NL = NC <= 128 ? 2 : 1;
-    constexpr int NT = green2_nt<NC, NL>();
-    K.gr = k_green2<T, NC, NL, NT>;
-    K.NTG = NT;
-    K.green2 = 1;
-    K.lsG = 0;
-    K.ldsG = sizeof(C2<T>) * (size_t)NC + sizeof(T) * 21 * (size_t)NC +
-             sizeof(C2<T>) * (size_t)NL * 6 * GreenPlan<NC>::LP;
-  } else {
-    constexpr int NT = NC <= 64 ? 64 : (NC <= 128 ? 128 : 256);
-    K.gr = k_green<T, NC, NT>;
-    K.NTG = NT;
+    K.cg.push_back(green2_cand<T, NC, (NC <= 128 ? 2 : 1)>());
+    if constexpr (NC <= 128) K.cg.push_back(green2_cand<T, NC, 1>());
+    for (size_t i = K.cg.size(); i-- > 0;)
+      if (K.cg[i].lds > (size_t)lds_limit()) K.cg.erase(K.cg.begin() + i);
+    if (!K.cg.empty()) {
+      for (int m = 0; m < 3; ++m) K.gr2[m] = K.cg[0].fn[m];
+      K.gr = K.gr2[GREEN_ISO];
+      K.NTG = K.cg[0].nt;
+      K.ldsG = K.cg[0].lds;
+      K.green2 = 1;
+      K.lsG = 0;
+      return;
+    }
   }
+  constexpr int NT = NC <= 64 ? 64 : (NC <= 128 ? 128 : 256);
+  K.gr = k_green<T, NC, NT>;
+  K.NTG = NT;
   (void)g;
 }
 
@@ -557,16 +613,53 @@ struct GroupRun {
   std::vector<double> ring;
 };
 
+// Select candidate ch[pass] for each pass (stress, axis 2, Green pass).
+template <typename T>
+void apply_choice(KernSet<T>& K, int gmode, const int ch[3]) {
+  if (!K.c1.empty()) {
+    const auto& c = K.c1[std::min<size_t>((size_t)ch[0], K.c1.size() - 1)];
+    K.a1s = c.fused;
+    K.NT1s = c.nt;
+    K.lds1s = c.lds;
+  }
+  if (!K.c2.empty()) {
+    const auto& c = K.c2[std::min<size_t>((size_t)ch[1], K.c2.size() - 1)];
+    K.a2[0] = c.fwd;
+    K.a2[1] = c.inv;
+    K.W2 = c.W;
+    K.NT2 = c.nt;
+    K.lds2 = c.lds;
+  }
+  if (K.green2 && !K.cg.empty()) {
+    const auto& c = K.cg[std::min<size_t>((size_t)ch[2], K.cg.size() - 1)];
+    for (int m = 0; m < 3; ++m) K.gr2[m] = c.fn[m];
+    K.NTG = c.nt;
+    K.ldsG = c.lds;
+  }
+  if (K.green2) K.gr = K.gr2[gmode];
+}
+
+inline int prec_index(const lsh_pattern* p) { return p->bound_prec == LSH_FP32_MIXED ? 1 : 0; }
+
 template <typename T>
 int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
   const lsh_pattern* p = G.spec.rep;
   int rc = make_kernels<T>(p, p->has_table, &G.K);
   if (rc) return rc;
+  G.gmode = green_mode(p);
+  {
+    const int pi = prec_index(p);
+    const int zero[3] = {0, 0, 0};
+    apply_choice(G.K, G.gmode, p->tuned[pi] ? p->tune_choice[pi] : zero);
+  }
   rc = allow_lds(G.K.gr, G.K.ldsG);
   if (rc) return rc;
+  if (G.K.a1s) {
+    rc = allow_lds(G.K.a1s, G.K.lds1s);
+    if (rc) return rc;
+  }
   G.g = geo_of(p);
   lsh_green_params(p, &G.gp);
-  G.gmode = green_mode(p);
   G.nload = (int)G.spec.inst_of.size();
   G.w = group_layout<T>(G.g, G.nload, (int)G.spec.inst.size(), G.K, base);
   if (!base || avail < G.w.total) return lsh_fail(LSH_EWORKSPACE, "workspace too small");
@@ -641,34 +734,57 @@ int group_init(GroupRun<T>& G, int max_iter, const double* dev_E_init, hipStream
 
 // Enqueue one Basic Scheme iteration of the group; `cur` picks which P buffer
 // holds the previous iterate.
+// The passes of one iteration, launched one by one.
+template <typename T>
+void launch_stress(GroupRun<T>& G, hipStream_t st) {
+  using T2 = C2<T>;
+  const lsh_pattern* p = G.spec.rep;
+  const T2* tw0 = (const T2*)(p->dev_persist + p->off_tw[0]);
+  hipLaunchKernelGGL(G.K.a1s ? G.K.a1s : G.K.a1[MODE_STRESS], G.gridS, dim3(G.K.a1s ? G.K.NT1s : G.K.NT1),
+                     G.K.a1s ? G.K.lds1s : G.K.lds1, st, G.g, p->plan[0], tw0, (const T2*)G.w.X, (T2*)G.w.TAU,
+                     (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0, (const int*)G.w.stop_iter,
+                     (const int*)G.w.itp, (const double*)nullptr, (const double*)nullptr, (double*)nullptr,
+                     (double*)nullptr);
+}
+
+template <typename T>
+void launch_axis2(GroupRun<T>& G, int dir, const C2<T>* src, C2<T>* dst, hipStream_t st) {
+  using T2 = C2<T>;
+  const lsh_pattern* p = G.spec.rep;
+  const T2* tw1 = (const T2*)(p->dev_persist + p->off_tw[1]);
+  hipLaunchKernelGGL(G.K.a2[dir], G.gridB, dim3(G.K.NT2), G.K.lds2, st, G.g, p->plan[1], tw1, src, dst,
+                     (const int*)G.w.stop_iter, (const int*)G.w.itp, (T)1);
+}
+
+template <typename T>
+void launch_green(GroupRun<T>& G, int cur, hipStream_t st) {
+  using T2 = C2<T>;
+  const lsh_pattern* p = G.spec.rep;
+  const T2* tw2 = (const T2*)(p->dev_persist + p->off_tw[2]);
+  const T* table = p->has_table ? (const T*)(p->dev_persist + p->off_table) : nullptr;
+  hipLaunchKernelGGL(G.K.gr, G.gridG, dim3(G.K.NTG), G.K.ldsG, st, G.g, p->plan[2], tw2, G.gp, (const T2*)G.w.TAU,
+                     (const T2*)G.w.P[cur], (T2*)G.w.P[1 - cur], table, (const Inst*)G.w.insts,
+                     (const int*)G.w.inst_of, (const int*)G.w.chunks, (const int*)G.w.stop_iter,
+                     (const int*)G.w.itp, G.nload, G.npos, G.w.partial, G.K.lsG, G.gmode);
+}
+
+// One Basic Scheme iteration of a group: stress (axis 1), axis 2, Green pass
+// (axis 3), residual, inverse axis 2.
 template <typename T>
 int group_iterate(GroupRun<T>& G, int cur, double tol, bool fixed, hipStream_t st) {
   using T2 = C2<T>;
-  const lsh_pattern* p = G.spec.rep;
-  char* base = p->dev_persist;
-  const T2* tw[3] = {(const T2*)(base + p->off_tw[0]), (const T2*)(base + p->off_tw[1]),
-                     (const T2*)(base + p->off_tw[2])};
-  const T* table = p->has_table ? (const T*)(base + p->off_table) : nullptr;
   const double pscale = (double)G.g.n1 * (double)G.g.n2;
   {
     Timer tm(0, st);
-    hipLaunchKernelGGL(G.K.a1[MODE_STRESS], G.gridS, dim3(G.K.NT1), G.K.lds1, st, G.g, p->plan[0], tw[0],
-                       (const T2*)G.w.X, (T2*)G.w.TAU, (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0,
-                       (const int*)G.w.stop_iter, (const int*)G.w.itp, (const double*)nullptr,
-                       (const double*)nullptr, (double*)nullptr, (double*)nullptr);
+    launch_stress<T>(G, st);
   }
   {
     Timer tm(1, st);
-    hipLaunchKernelGGL(G.K.a2[0], G.gridB, dim3(G.K.NT2), G.K.lds2, st, G.g, p->plan[1], tw[1], (const T2*)G.w.TAU,
-                       (T2*)G.w.TAU, (const int*)G.w.stop_iter, (const int*)G.w.itp, (T)1);
+    launch_axis2<T>(G, 0, (const T2*)G.w.TAU, (T2*)G.w.TAU, st);
   }
   {
     Timer tm(2, st);
-    hipLaunchKernelGGL(G.K.gr, G.gridG, dim3(G.K.NTG), G.K.ldsG, st, G.g, p->plan[2], tw[2], G.gp,
-                       (const T2*)G.w.TAU, (const T2*)G.w.P[cur], (T2*)G.w.P[1 - cur], table,
-                       (const Inst*)G.w.insts, (const int*)G.w.inst_of, (const int*)G.w.chunks,
-                       (const int*)G.w.stop_iter, (const int*)G.w.itp, G.nload, G.npos, G.w.partial, G.K.lsG,
-                       G.gmode);
+    launch_green<T>(G, cur, st);
   }
   {
     Timer tm(3, st);
@@ -678,11 +794,70 @@ int group_iterate(GroupRun<T>& G, int cur, double tol, bool fixed, hipStream_t s
   }
   {
     Timer tm(4, st);
-    hipLaunchKernelGGL(G.K.a2[1], G.gridB, dim3(G.K.NT2), G.K.lds2, st, G.g, p->plan[1], tw[1],
-                       (const T2*)G.w.P[1 - cur], (T2*)G.w.X, (const int*)G.w.stop_iter, (const int*)G.w.itp, (T)1);
+    launch_axis2<T>(G, 1, (const T2*)G.w.P[1 - cur], (T2*)G.w.X, st);
   }
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, G.w.itp);
   HIPCHK(hipGetLastError());
+  return LSH_OK;
+}
+
+// Autotuner: time each candidate of each pass on the group's own data (after
+// a zero-start init) and keep the fastest; the caller re-initialises the state.
+template <typename T>
+int tune_group(GroupRun<T>& G, hipStream_t st, int choice[3], int ncand[3], float ms[3][4]) {
+  using T2 = C2<T>;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int ch[3] = {0, 0, 0};
+  const int nc[3] = {(int)G.K.c1.size(), (int)G.K.c2.size(), G.K.green2 ? (int)G.K.cg.size() : 1};
+  int rc = LSH_OK;
+  for (int pass = 0; pass < 3 && rc == LSH_OK; ++pass) {
+    ncand[pass] = nc[pass];
+    float best = 1e30f;
+    int bi = 0;
+    for (int c = 0; c < nc[pass] && c < 4 && rc == LSH_OK; ++c) {
+      ch[pass] = c;
+      apply_choice(G.K, G.gmode, ch);
+      const int nt3b = (G.g.n3 + G.K.W2 - 1) / G.K.W2;
+      G.gridB = dim3(G.g.h1 * nt3b, 6, G.nload);
+      if (pass == 0 && G.K.a1s) rc = allow_lds(G.K.a1s, G.K.lds1s);
+      if (pass == 2) rc = allow_lds(G.K.gr, G.K.ldsG);
+      if (rc) break;
+      auto run = [&]() {
+        if (pass == 0) launch_stress<T>(G, st);
+        if (pass == 1) {
+          launch_axis2<T>(G, 0, (const T2*)G.w.TAU, (T2*)G.w.TAU, st);
+          launch_axis2<T>(G, 1, (const T2*)G.w.P[1], (T2*)G.w.X, st);
+        }
+        if (pass == 2) launch_green<T>(G, 0, st);
+      };
+      run();
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < 3; ++r) run();
+      (void)hipEventRecord(e1, st);
+      if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = lsh_fail(LSH_EDEVICE, "autotuner launch failed");
+        break;
+      }
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      t /= 3.f;
+      ms[pass][c] = t;
+      if (t < best) {
+        best = t;
+        bi = c;
+      }
+    }
+    ch[pass] = bi;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  apply_choice(G.K, G.gmode, ch);
+  const int nt3b = (G.g.n3 + G.K.W2 - 1) / G.K.W2;
+  G.gridB = dim3(G.g.h1 * nt3b, 6, G.nload);
+  for (int i = 0; i < 3; ++i) choice[i] = ch[i];
   return LSH_OK;
 }
 
@@ -1028,6 +1203,73 @@ extern "C" int lsh_solve(lsh_pattern* p, int nload, const double* eps0_voigt, do
                            sigma_out, stats, history);
   return solve_t<float>(p, nload, eps0_voigt, tol, max_iter, dev_ws, ws_bytes, st, dev_E_init, dev_E_out, sigma_out,
                         stats, history);
+}
+
+template <typename T>
+int autotune_t(lsh_pattern* p, int nload, void* dev_ws, size_t ws_bytes, hipStream_t st, lsh_tune_result* out) {
+  std::vector<GroupRun<T>> groups(1);
+  GroupRun<T>& G = groups[0];
+  GroupSpec& S = G.spec;
+  S.rep = p;
+  S.inst = {p};
+  std::vector<double> sig(6 * (size_t)nload);
+  for (int L = 0; L < nload; ++L) {
+    S.inst_of.push_back(0);
+    for (int c = 0; c < 6; ++c) S.eps0_voigt.push_back(c == L % 6 ? 1.0 : 0.0);
+    S.sigma_out.push_back(sig.data() + 6 * L);
+    S.stats.push_back(nullptr);
+    S.history.push_back(nullptr);
+  }
+  const int pi = prec_index(p);
+  p->tuned[pi] = 0;  // time every candidate from the defaults
+  size_t used = 0;
+  int rc = group_prepare<T>(G, (char*)dev_ws, dev_ws ? ws_bytes : 0, &used);
+  if (rc) return rc;
+  rc = group_init<T>(G, 1, nullptr, st);
+  if (rc) return rc;
+  int choice[3] = {0, 0, 0}, ncand[3] = {1, 1, 1};
+  float ms[3][4] = {{0}};
+  rc = tune_group<T>(G, st, choice, ncand, ms);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  p->tuned[pi] = 1;
+  for (int i = 0; i < 3; ++i) p->tune_choice[pi][i] = choice[i];
+  if (out) {
+    for (int i = 0; i < 3; ++i) {
+      out->choice[i] = choice[i];
+      out->ncand[i] = ncand[i];
+      for (int c = 0; c < 4; ++c) out->ms[i][c] = c < ncand[i] ? ms[i][c] : 0.f;
+    }
+  }
+  return LSH_OK;
+}
+
+extern "C" int lsh_autotune(lsh_pattern* p, int nload, lsh_precision prec, void* dev_ws, size_t ws_bytes,
+                            void* stream, lsh_tune_result* out) {
+  if (!p) return lsh_fail(LSH_EINVAL, "null pattern");
+  if (nload < 1 || nload > 64) return lsh_fail(LSH_EINVAL, "nload must be in [1, 64]");
+  if (p->kind < 0 || p->nphase < 1) return lsh_fail(LSH_ESTATE, "kernel or stiffness not set");
+  if (p->bound_prec != (int)prec) return lsh_fail(LSH_ESTATE, "pattern not bound at this precision (lsh_bind)");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LSH_FP64) return autotune_t<double>(p, nload, dev_ws, ws_bytes, st, out);
+  return autotune_t<float>(p, nload, dev_ws, ws_bytes, st, out);
+}
+
+extern "C" int lsh_tune_set(lsh_pattern* p, lsh_precision prec, const int* choice) {
+  if (!p || !choice) return lsh_fail(LSH_EINVAL, "null argument");
+  if (prec != LSH_FP64 && prec != LSH_FP32_MIXED) return lsh_fail(LSH_EINVAL, "bad precision");
+  for (int i = 0; i < 3; ++i)
+    if (choice[i] < 0 || choice[i] > 3) return lsh_fail(LSH_EINVAL, "variant index out of range");
+  const int pi = prec == LSH_FP32_MIXED ? 1 : 0;
+  for (int i = 0; i < 3; ++i) p->tune_choice[pi][i] = choice[i];
+  p->tuned[pi] = 1;
+  return LSH_OK;
+}
+
+extern "C" int lsh_tune_reset(lsh_pattern* p) {
+  if (!p) return lsh_fail(LSH_EINVAL, "null pattern");
+  p->tuned[0] = p->tuned[1] = 0;
+  return LSH_OK;
 }
 
 extern "C" int lsh_profile_enable(int on) {

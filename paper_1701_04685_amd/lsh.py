@@ -27,7 +27,7 @@ STATUS = {0: "LSH_OK", -1: "LSH_EINVAL", -2: "LSH_ESINGULAR", -3: "LSH_ENOINTERP
 EXPORTS = ["lsh_create_pattern", "lsh_destroy", "lsh_pattern_info", "lsh_pattern_snf", "lsh_pattern_points",
            "lsh_set_kernel", "lsh_set_stiffness", "lsh_persistent_bytes", "lsh_bind", "lsh_gamma_probe",
            "lsh_solve_bytes", "lsh_solve", "lsh_batch_bytes", "lsh_solve_batch", "lsh_profile_enable",
-           "lsh_profile_read", "lsh_last_error", "lsh_unet_create", "lsh_unet_destroy", "lsh_unet_param_count",
+           "lsh_profile_read", "lsh_last_error", "lsh_autotune", "lsh_tune_reset", "lsh_tune_set", "lsh_unet_create", "lsh_unet_destroy", "lsh_unet_param_count",
            "lsh_unet_param_bytes", "lsh_unet_bind", "lsh_unet_get_params", "lsh_unet_act_bytes",
            "lsh_unet_train_step", "lsh_unet_zero_grad", "lsh_unet_get_grads", "lsh_unet_predict", "lsh_unet_head",
            "lsh_unet_layers", "lsh_unet_pack_target"]
@@ -77,6 +77,9 @@ _sig = {
     "lsh_profile_enable": ([ctypes.c_int], ctypes.c_int),
     "lsh_profile_read": ([_DP, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int], ctypes.c_int),
     "lsh_last_error": ([], ctypes.c_char_p),
+    "lsh_autotune": ([_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t, _P, _P], ctypes.c_int),
+    "lsh_tune_reset": ([_P], ctypes.c_int),
+    "lsh_tune_set": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "lsh_unet_create": ([ctypes.c_int, ctypes.POINTER(_P)], ctypes.c_int),
     "lsh_unet_destroy": ([_P], None),
     "lsh_unet_param_count": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -152,6 +155,10 @@ def _done_on(stream):
 def _device_bytes(n):
     torch = _torch()
     return torch.empty(max(int(n), 1), dtype=torch.uint8, device="cuda")
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("choice", ctypes.c_int * 3), ("ncand", ctypes.c_int * 3), ("ms", (ctypes.c_float * 4) * 3)]
 
 
 class Pattern:
@@ -237,6 +244,31 @@ class Pattern:
         n = ctypes.c_size_t()
         _check(_lib.lsh_solve_bytes(self._h, int(nload), p, ctypes.byref(n)))
         return n.value
+
+    def autotune(self, nload=6, workspace=None):
+        """Time each pass's kernel variants on this pattern (lsh_autotune); later
+        solves at the bound precision use the fastest.  Returns the choices."""
+        if self._prec is None:
+            raise RuntimeError("call bind() first")
+        need = self.workspace_bytes(nload)
+        ws = workspace if workspace is not None and workspace.numel() >= need else _device_bytes(need)
+        res = TuneResult()
+        S, sh = _solve_stream()
+        rc = _lib.lsh_autotune(self._h, int(nload), self._prec, ctypes.c_void_p(ws.data_ptr()), ws.numel(), sh,
+                               ctypes.byref(res))
+        _done_on(S)
+        _check(rc)
+        names = ["stress", "axis2", "green"]
+        return {n: {"choice": res.choice[i], "ms": [round(res.ms[i][c], 5) for c in range(res.ncand[i])]}
+                for i, n in enumerate(names)}
+
+    def tune_reset(self):
+        _check(_lib.lsh_tune_reset(self._h))
+
+    def tune_set(self, choice, precision=None):
+        p = self._prec if precision is None else (PRECISIONS[precision] if isinstance(precision, str) else precision)
+        arr = (ctypes.c_int * 3)(*[int(c) for c in choice])
+        _check(_lib.lsh_tune_set(self._h, int(p), arr))
 
     def solve(self, eps0_voigt, tol=1e-10, max_iter=1000, E_init=None, return_E=False, history=False,
               workspace=None, allow_notconverged=False):

@@ -1,0 +1,71 @@
+"""Every kernel variant the autotuner can pick gives the oracle's iterates.
+
+lsh_tune_set forces each combination of variants (stress pass plain or
+fused, axis-2 tile width, one or two load cases per Green-pass block) on a
+pattern whose SNF line lengths all have variants, and the lock-step run is
+compared with the FP64 oracle as in test_gpu_parity (7 iterations, FP64
+1e-10 / FP32 1e-5 relative).  lsh_autotune itself must report a valid choice
+and keep the answer.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import lsh_inputs as li
+from helpers import Problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+EPS0 = np.array([0.3, -0.2, 0.1, 0.4, -0.1, 0.25])
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300)
+
+
+def spheres(seed, frac=0.3):
+    def f(Y):
+        c, r = li.rsa_spheres(seed, li.lattice_unit(len(Y)), frac, rmin=1.5, rmax=3.0)
+        return li.spheres_phase(Y, c, r)
+    return f
+
+
+@pytest.fixture(scope="module", params=[("dlvp", {"alpha": [0.75] * 3}),
+                                        ("box", {"Xi": np.array([[1, 0, 0, 1], [0, 1, 0, 1], [0, 0, 1, 0]], float),
+                                                 "R": 2})])
+def problem(request):
+    kind, params = request.param
+    pr = Problem(np.diag([16, 32, 64]), kind, params, spheres(31))
+    ref = pr.oracle_solve(EPS0, n_iter=7)
+    return pr, ref
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_every_variant_matches_oracle(problem, prec):
+    pr, ref = problem
+    pr.bind(prec)
+    for choice in itertools.product(range(2), range(2), range(2)):
+        print(f"variant {choice} {prec}", flush=True)
+        pr.G.tune_set(choice)
+        res = pr.G.solve(EPS0[None], tol=-1.0, max_iter=7, return_E=True, history=True)
+        Eg = pr.gpu_E_to_oracle_mandel(res["E"].cpu().numpy()[0])
+        assert rel(res["sigma"][0], ref["sigma_voigt"]) < TOL[prec], choice
+        assert rel(Eg, ref["E"]) < TOL[prec], choice
+        np.testing.assert_allclose(res["history"][0], ref["history"], rtol=100 * TOL[prec], atol=1e-14)
+    pr.G.tune_reset()
+
+
+def test_autotune_choice_and_answer(problem):
+    pr, ref = problem
+    pr.bind("fp64")
+    info = pr.G.autotune(nload=1)
+    for name in ("stress", "axis2", "green"):
+        ms = info[name]["ms"]
+        assert len(ms) >= 1 and all(t > 0 for t in ms)
+        assert 0 <= info[name]["choice"] < len(ms)
+        assert ms[info[name]["choice"]] == min(ms)
+    res = pr.G.solve(EPS0[None], tol=-1.0, max_iter=7, return_E=True)
+    assert rel(res["sigma"][0], ref["sigma_voigt"]) < TOL["fp64"]
+    pr.G.tune_reset()
