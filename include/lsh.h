@@ -179,8 +179,8 @@ int lsh_solve(lsh_pattern *p, int nload, const double *eps0_voigt, double tol, i
 
 /* ------------------------------------------------------------------ autotuner ---
  * Each pass of an iteration has kernel variants (the axis-1 stress pass with or
- * without its middle stages fused in registers, the axis-2 tile width, one or
- * two load cases per Green-pass block).  lsh_autotune times every variant of
+ * without its middle stages fused in registers and its tile width along i3,
+ * the axis-2 tile width, one or two load cases per Green-pass block).  lsh_autotune times every variant of
  * every pass on this pattern's own data (nload load cases, precision prec,
  * from a zero start; a warm-up launch, then the mean of three) with HIP events
  * on `stream`, and keeps the fastest for later lsh_solve and lsh_solve_batch
@@ -190,10 +190,11 @@ int lsh_solve(lsh_pattern *p, int nload, const double *eps0_voigt, double tol, i
  *   out (optional): the chosen variant per pass (0 = the default), the number
  *                   of variants and each variant's mean time in ms.
  * Errors: LSH_EINVAL, LSH_ESTATE, LSH_EWORKSPACE, LSH_EDEVICE.                      */
+#define LSH_TUNE_MAX 8   /* variants timed per pass, at most */
 typedef struct {
   int choice[3];   /* stress pass, axis-2 passes, Green pass */
   int ncand[3];
-  float ms[3][4];
+  float ms[3][LSH_TUNE_MAX];
 } lsh_tune_result;
 
 int lsh_autotune(lsh_pattern *p, int nload, lsh_precision prec, void *dev_workspace, size_t ws_bytes,

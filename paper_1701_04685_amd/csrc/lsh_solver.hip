@@ -88,11 +88,11 @@ struct KernSet {
   GR gr = nullptr;
   GR gr2[3] = {nullptr, nullptr, nullptr};  // k_green2 per Green mode (ISO, GENERAL, TABLE)
   int W1 = 0, NT1 = 0, W2 = 0, NT2 = 0, NTG = 0, lsG = 0;
-  A1 a1s = nullptr;  // fused stress pass (k_axis1s) when the line length allows it
-  int NT1s = 0;
+  A1 a1s = nullptr;  // the stress-pass kernel in use (a candidate below)
+  int NT1s = 0, W1s = 0;
   size_t lds1s = 0;
   // autotuner candidates per pass; entry 0 is the default
-  struct CStress { A1 fused; int nt; size_t lds; };
+  struct CStress { A1 fn; int nt; size_t lds; int W; };
   struct CAxis2 { A2 fwd, inv; int W, nt; size_t lds; };
   struct CGreen { GR fn[3]; int nt; size_t lds; };
   std::vector<CStress> c1;
@@ -141,12 +141,30 @@ bool axis1_special(const Geo& g, KernSet<T>& K) {
     put_axis1<T, NC, W>(K);
   }
   K.c1.clear();
-  K.c1.push_back({nullptr, 0, 0});  // k_axis1 (MODE_STRESS)
+  K.c1.push_back({K.a1[0], K.NT1, 0, W});  // k_axis1 (MODE_STRESS); LDS filled in by choose_axis1
   if constexpr (NC % 2 == 0 && axis1s_nt<NC, W>() <= 1024) {
     constexpr int NT = axis1s_nt<NC, W>();
     const size_t lds = sizeof(C2<T>) * (size_t)NC + sizeof(T) * 36 * 16 +
                        sizeof(C2<T>) * 3 * (size_t)W * GreenPlan<NC>::LP + (size_t)NC * W;
-    if (lds <= (size_t)lds_limit()) K.c1.push_back({k_axis1s<T, NC, W, NT>, NT, lds});
+    if (lds <= (size_t)lds_limit()) K.c1.push_back({k_axis1s<T, NC, W, NT>, NT, lds, W});
+  }
+  if constexpr (W >= 4) {  // narrower tiles: more blocks per CU, shorter runs along i3
+    constexpr int Wh = W / 2;
+    const size_t lds = sizeof(C2<T>) * ((size_t)NC + (size_t)NC * 3 * Wh) + sizeof(T) * 36 * 16;
+    K.c1.push_back({k_axis1<T, MODE_STRESS, NC, Wh, 256>, 256, lds, Wh});
+  }
+  if constexpr (W <= 16 && NC <= 256) {  // wider tiles: longer runs along i3, one block per CU
+    constexpr int W2x = 2 * W;
+    if (g.n3 >= W2x) {
+      const size_t lds = sizeof(C2<T>) * ((size_t)NC + (size_t)NC * 3 * W2x) + sizeof(T) * 36 * 16;
+      if (lds <= (size_t)lds_limit()) K.c1.push_back({k_axis1<T, MODE_STRESS, NC, W2x, 1024>, 1024, lds, W2x});
+      if constexpr (NC % 2 == 0 && axis1s_nt<NC, W2x>() <= 1024) {
+        constexpr int NT = axis1s_nt<NC, W2x>();
+        const size_t lf = sizeof(C2<T>) * (size_t)NC + sizeof(T) * 36 * 16 +
+                          sizeof(C2<T>) * 3 * (size_t)W2x * GreenPlan<NC>::LP + (size_t)NC * W2x;
+        if (lf <= (size_t)lds_limit()) K.c1.push_back({k_axis1s<T, NC, W2x, NT>, NT, lf, W2x});
+      }
+    }
   }
   return true;
 }
@@ -174,7 +192,8 @@ bool choose_axis1(const Geo& g, const FftPlan& pl, KernSet<T>& K) {
       return false;
   }
   K.lds1 = sizeof(C2<T>) * ((size_t)g.n1 + (size_t)g.n1 * 3 * K.W1) + sizeof(T) * 36 * 16;
-  if (K.c1.empty()) K.c1.push_back({nullptr, 0, 0});
+  if (K.c1.empty()) K.c1.push_back({K.a1[0], K.NT1, K.lds1, K.W1});
+  K.c1[0].lds = K.lds1;
   return K.lds1 <= (size_t)lds_limit();
 }
 
@@ -195,6 +214,12 @@ bool axis2_special(const Geo& g, KernSet<T>& K) {
     constexpr int Wh = W / 2;
     K.c2.push_back({k_axis2<T, -1, NC, Wh, 256>, k_axis2<T, +1, NC, Wh, 256>, Wh, 256,
                     sizeof(C2<T>) * ((size_t)NC + (size_t)NC * Wh)});
+  }
+  if constexpr (W <= 32 && NC <= 256) {  // wider tiles: longer runs along i3, fewer blocks
+    constexpr int W2x = 2 * W;
+    const size_t lds = sizeof(C2<T>) * ((size_t)NC + (size_t)NC * W2x);
+    if (g.n3 >= W2x && lds <= (size_t)lds_limit())
+      K.c2.push_back({k_axis2<T, -1, NC, W2x, 512>, k_axis2<T, +1, NC, W2x, 512>, W2x, 512, lds});
   }
   return true;
 }
@@ -606,7 +631,7 @@ struct GroupRun {
   int gmode;
   GroupWS w;
   int nload;
-  dim3 gridS, gridB, gridG;
+  dim3 gridS, gridS1, gridB, gridG;  // gridS1: the stress pass (its own tile width)
   int npos, nblkS;
   std::vector<int> chunks;  // Green chunks: (first load, end load) pairs
   std::vector<int> stop;
@@ -618,9 +643,10 @@ template <typename T>
 void apply_choice(KernSet<T>& K, int gmode, const int ch[3]) {
   if (!K.c1.empty()) {
     const auto& c = K.c1[std::min<size_t>((size_t)ch[0], K.c1.size() - 1)];
-    K.a1s = c.fused;
+    K.a1s = c.fn;
     K.NT1s = c.nt;
     K.lds1s = c.lds;
+    K.W1s = c.W;
   }
   if (!K.c2.empty()) {
     const auto& c = K.c2[std::min<size_t>((size_t)ch[1], K.c2.size() - 1)];
@@ -654,10 +680,12 @@ int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
   }
   rc = allow_lds(G.K.gr, G.K.ldsG);
   if (rc) return rc;
-  if (G.K.a1s) {
-    rc = allow_lds(G.K.a1s, G.K.lds1s);
-    if (rc) return rc;
-  }
+  rc = allow_lds(G.K.a1s, G.K.lds1s);
+  if (rc) return rc;
+  rc = allow_lds(G.K.a2[0], G.K.lds2);
+  if (rc) return rc;
+  rc = allow_lds(G.K.a2[1], G.K.lds2);
+  if (rc) return rc;
   G.g = geo_of(p);
   lsh_green_params(p, &G.gp);
   G.nload = (int)G.spec.inst_of.size();
@@ -666,6 +694,7 @@ int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
   *used = G.w.total;
   const int nt3a = (G.g.n3 + G.K.W1 - 1) / G.K.W1;
   G.gridS = dim3(G.g.n2 * nt3a, G.nload);
+  G.gridS1 = dim3(G.g.n2 * ((G.g.n3 + G.K.W1s - 1) / G.K.W1s), G.nload);
   const int nt3b = (G.g.n3 + G.K.W2 - 1) / G.K.W2;
   G.gridB = dim3(G.g.h1 * nt3b, 6, G.nload);
   G.npos = G.g.h1 * G.g.n2;
@@ -740,8 +769,8 @@ void launch_stress(GroupRun<T>& G, hipStream_t st) {
   using T2 = C2<T>;
   const lsh_pattern* p = G.spec.rep;
   const T2* tw0 = (const T2*)(p->dev_persist + p->off_tw[0]);
-  hipLaunchKernelGGL(G.K.a1s ? G.K.a1s : G.K.a1[MODE_STRESS], G.gridS, dim3(G.K.a1s ? G.K.NT1s : G.K.NT1),
-                     G.K.a1s ? G.K.lds1s : G.K.lds1, st, G.g, p->plan[0], tw0, (const T2*)G.w.X, (T2*)G.w.TAU,
+  hipLaunchKernelGGL(G.K.a1s, G.gridS1, dim3(G.K.NT1s), G.K.lds1s, st, G.g, p->plan[0], tw0, (const T2*)G.w.X,
+                     (T2*)G.w.TAU,
                      (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0, (const int*)G.w.stop_iter,
                      (const int*)G.w.itp, (const double*)nullptr, (const double*)nullptr, (double*)nullptr,
                      (double*)nullptr);
@@ -804,7 +833,7 @@ int group_iterate(GroupRun<T>& G, int cur, double tol, bool fixed, hipStream_t s
 // Autotuner: time each candidate of each pass on the group's own data (after
 // a zero-start init) and keep the fastest; the caller re-initialises the state.
 template <typename T>
-int tune_group(GroupRun<T>& G, hipStream_t st, int choice[3], int ncand[3], float ms[3][4]) {
+int tune_group(GroupRun<T>& G, hipStream_t st, int choice[3], int ncand[3], float ms[3][LSH_TUNE_MAX]) {
   using T2 = C2<T>;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -816,12 +845,17 @@ int tune_group(GroupRun<T>& G, hipStream_t st, int choice[3], int ncand[3], floa
     ncand[pass] = nc[pass];
     float best = 1e30f;
     int bi = 0;
-    for (int c = 0; c < nc[pass] && c < 4 && rc == LSH_OK; ++c) {
+    for (int c = 0; c < nc[pass] && c < LSH_TUNE_MAX && rc == LSH_OK; ++c) {
       ch[pass] = c;
       apply_choice(G.K, G.gmode, ch);
       const int nt3b = (G.g.n3 + G.K.W2 - 1) / G.K.W2;
       G.gridB = dim3(G.g.h1 * nt3b, 6, G.nload);
-      if (pass == 0 && G.K.a1s) rc = allow_lds(G.K.a1s, G.K.lds1s);
+      G.gridS1 = dim3(G.g.n2 * ((G.g.n3 + G.K.W1s - 1) / G.K.W1s), G.nload);
+      if (pass == 0) rc = allow_lds(G.K.a1s, G.K.lds1s);
+      if (pass == 1) {
+        rc = allow_lds(G.K.a2[0], G.K.lds2);
+        if (!rc) rc = allow_lds(G.K.a2[1], G.K.lds2);
+      }
       if (pass == 2) rc = allow_lds(G.K.gr, G.K.ldsG);
       if (rc) break;
       auto run = [&]() {
@@ -857,6 +891,7 @@ int tune_group(GroupRun<T>& G, hipStream_t st, int choice[3], int ncand[3], floa
   apply_choice(G.K, G.gmode, ch);
   const int nt3b = (G.g.n3 + G.K.W2 - 1) / G.K.W2;
   G.gridB = dim3(G.g.h1 * nt3b, 6, G.nload);
+  G.gridS1 = dim3(G.g.n2 * ((G.g.n3 + G.K.W1s - 1) / G.K.W1s), G.nload);
   for (int i = 0; i < 3; ++i) choice[i] = ch[i];
   return LSH_OK;
 }
@@ -1228,7 +1263,7 @@ int autotune_t(lsh_pattern* p, int nload, void* dev_ws, size_t ws_bytes, hipStre
   rc = group_init<T>(G, 1, nullptr, st);
   if (rc) return rc;
   int choice[3] = {0, 0, 0}, ncand[3] = {1, 1, 1};
-  float ms[3][4] = {{0}};
+  float ms[3][LSH_TUNE_MAX] = {{0}};
   rc = tune_group<T>(G, st, choice, ncand, ms);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(st));
@@ -1238,7 +1273,7 @@ int autotune_t(lsh_pattern* p, int nload, void* dev_ws, size_t ws_bytes, hipStre
     for (int i = 0; i < 3; ++i) {
       out->choice[i] = choice[i];
       out->ncand[i] = ncand[i];
-      for (int c = 0; c < 4; ++c) out->ms[i][c] = c < ncand[i] ? ms[i][c] : 0.f;
+      for (int c = 0; c < LSH_TUNE_MAX; ++c) out->ms[i][c] = c < ncand[i] ? ms[i][c] : 0.f;
     }
   }
   return LSH_OK;
@@ -1259,7 +1294,7 @@ extern "C" int lsh_tune_set(lsh_pattern* p, lsh_precision prec, const int* choic
   if (!p || !choice) return lsh_fail(LSH_EINVAL, "null argument");
   if (prec != LSH_FP64 && prec != LSH_FP32_MIXED) return lsh_fail(LSH_EINVAL, "bad precision");
   for (int i = 0; i < 3; ++i)
-    if (choice[i] < 0 || choice[i] > 3) return lsh_fail(LSH_EINVAL, "variant index out of range");
+    if (choice[i] < 0 || choice[i] >= LSH_TUNE_MAX) return lsh_fail(LSH_EINVAL, "variant index out of range");
   const int pi = prec == LSH_FP32_MIXED ? 1 : 0;
   for (int i = 0; i < 3; ++i) p->tune_choice[pi][i] = choice[i];
   p->tuned[pi] = 1;

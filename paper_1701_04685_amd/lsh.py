@@ -158,7 +158,7 @@ def _device_bytes(n):
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("choice", ctypes.c_int * 3), ("ncand", ctypes.c_int * 3), ("ms", (ctypes.c_float * 4) * 3)]
+    _fields_ = [("choice", ctypes.c_int * 3), ("ncand", ctypes.c_int * 3), ("ms", (ctypes.c_float * 8) * 3)]
 
 
 class Pattern:

@@ -46,7 +46,7 @@ def problem(request):
 def test_every_variant_matches_oracle(problem, prec):
     pr, ref = problem
     pr.bind(prec)
-    for choice in itertools.product(range(2), range(2), range(2)):
+    for choice in itertools.product(range(5), range(3), range(2)):
         print(f"variant {choice} {prec}", flush=True)
         pr.G.tune_set(choice)
         res = pr.G.solve(EPS0[None], tol=-1.0, max_iter=7, return_E=True, history=True)
