@@ -292,24 +292,22 @@ __device__ inline void iso_matrix(const IsoMoments& M, double mu0, double r, dou
 }
 
 // Isotropic version of gamma_sym_at for the analytic kernels (Dirichlet,
-// modified Dirichlet, dlVP): same alias sets and symmetrisation.  The weighted
-// moments of the alias directions go into one accumulator: each
-// representative's weights are normalised up front (its weight sum factors
-// over the axes), so no second moment set is held.  out(t, v) receives the 21
-// entries.
-template <typename Out>
-__device__ inline void gamma_iso_emit(const GreenParams& gp, double mu0, double r, int64_t b0, int64_t b1, int64_t b2,
-                                      Out&& out) {
+// modified Dirichlet, dlVP): same alias sets and symmetrisation.  Gamma0 for
+// an isotropic C0 is S(n)/mu0 - r Q(n), linear in the second and fourth
+// moments of the direction n, so Gamma^p needs only the weighted moments of
+// the alias directions (6 + 15 numbers, independent of C0).
+//
+// iso_moments: the normalised moments at bin b; false (moments zero) at h = 0.
+// Each representative's weights are normalised up front (its weight sum
+// factors over the axes), so one accumulator suffices.
+__device__ inline bool iso_moments(const GreenParams& gp, int64_t b0, int64_t b1, int64_t b2, IsoMoments& M) {
+  M = IsoMoments{};
   const int64_t b[3] = {b0, b1, b2};
   int64_t h[3];
   for (int i = 0; i < 3; ++i) h[i] = gp.VT[3 * i] * b[0] + gp.VT[3 * i + 1] * b[1] + gp.VT[3 * i + 2] * b[2];
   int64_t hr[3], xn[3];
   reduce_freq(gp, h, hr, xn);
-  if (hr[0] == 0 && hr[1] == 0 && hr[2] == 0) {
-    for (int t = 0; t < 21; ++t) out(t, 0.0);
-    return;
-  }
-  IsoMoments M = {};
+  if (hr[0] == 0 && hr[1] == 0 && hr[2] == 0) return false;
   const double invm = 1.0 / (double)gp.m;
   const bool face = (2 * xn[0] == -gp.m) || (2 * xn[1] == -gp.m) || (2 * xn[2] == -gp.m);
   const int nrep = (face && gp.kind == 0) ? 2 : 1;
@@ -365,7 +363,13 @@ __device__ inline void gamma_iso_emit(const GreenParams& gp, double mu0, double 
       iso_add(M, kd, w);
     }
   }
-  // Gamma0 = S(n)/mu0 - r Q(n) is linear in the moments (already normalised)
+  return true;
+}
+
+// The 21 Mandel entries of S/mu0 - r Q from normalised moments a (6: the
+// pairs 00,11,22,12,02,01) and q (15, q4_index order); out(t, v).
+template <typename Out>
+__device__ inline void iso_emit(const double a[6], const double q[15], double mu0, double r, Out&& out) {
   const double SQ2 = 1.41421356237309504880168872420969808;
   const double imu = 1.0 / mu0;
 #pragma unroll
@@ -380,14 +384,24 @@ __device__ inline void gamma_iso_emit(const GreenParams& gp, double mu0, double 
       const double cJ = J < 3 ? 1.0 : SQ2;
       auto Am = [&](int u, int v) {
         const int lo = u < v ? u : v, hi = u < v ? v : u;
-        return lo == hi ? M.a[lo] : M.a[6 - lo - hi];
+        return lo == hi ? a[lo] : a[6 - lo - hi];
       };
       const double S = 0.25 * ((ib == ic) * Am(ia, id) + (ib == id) * Am(ia, ic) + (ia == ic) * Am(ib, id) +
                                (ia == id) * Am(ib, ic));
-      const double Q = M.q[q4_index(ia, ib, ic, id)];
-      out(tri_idx(I, J), cI * cJ * (imu * S - r * Q));
+      out(tri_idx(I, J), cI * cJ * (imu * S - r * q[q4_index(ia, ib, ic, id)]));
     }
   }
+}
+
+template <typename Out>
+__device__ inline void gamma_iso_emit(const GreenParams& gp, double mu0, double r, int64_t b0, int64_t b1, int64_t b2,
+                                      Out&& out) {
+  IsoMoments M;
+  if (!iso_moments(gp, b0, b1, b2, M)) {
+    for (int t = 0; t < 21; ++t) out(t, 0.0);
+    return;
+  }
+  iso_emit(M.a, M.q, mu0, r, out);
 }
 
 __device__ inline void gamma_sym_iso(const GreenParams& gp, double mu0, double r, int64_t b0, int64_t b1, int64_t b2,

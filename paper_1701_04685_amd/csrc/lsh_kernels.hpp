@@ -352,7 +352,22 @@ __global__ void __launch_bounds__(NT) k_axis2(Geo g, FftPlan pl, const C2<T>* __
 // and then hit that XCD's L2.  LDS: twiddles[n3], lines[6][ls].
 // gmode: 0 isotropic C0 (moment form, on the fly), 1 general C0 on the fly,
 // 2 table [pos][21][n3] built at bind time (double sums, stored at T).
-enum { GREEN_ISO = 0, GREEN_GENERAL = 1, GREEN_TABLE = 2 };
+// GREEN_MOMENTS: isotropic C0 with the normalised alias moments (21 per bin,
+// independent of C0) precomputed at bind time in the table slot.
+enum { GREEN_ISO = 0, GREEN_GENERAL = 1, GREEN_TABLE = 2, GREEN_MOMENTS = 3 };
+
+// Gamma^p entry row t at bin (pos, k3) from a moments row set [pos][21][n3].
+template <typename T, typename Out>
+__device__ __forceinline__ void moments_emit(const T* __restrict__ table, long long pos, int n3, int k3, double mu0,
+                                             double riso, Out&& out) {
+  const T* tb = table + pos * 21 * n3 + k3;
+  double a[6], q[15];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) a[t] = (double)tb[(long long)t * n3];
+#pragma unroll
+  for (int t = 0; t < 15; ++t) q[t] = (double)tb[(long long)(6 + t) * n3];
+  iso_emit(a, q, mu0, riso, out);
+}
 template <typename T, int NC, int NT>
 __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __restrict__ tw, GreenParams gp,
                                               const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
@@ -411,6 +426,8 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
       const T* tb = table + (long long)pos * 21 * n3 + k3;
 #pragma unroll
       for (int t = 0; t < 21; ++t) G[t] = (T)(scale * (double)tb[(long long)t * n3]);
+    } else if (gmode == GREEN_MOMENTS) {
+      moments_emit(table, pos, n3, k3, mu0, riso, [&](int t, double v) { G[t] = (T)(scale * v); });
     } else {
       double Gd[21];
       if (gmode == GREEN_ISO)
@@ -667,6 +684,10 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
         const int inst = inst_of[Lbeg];
         gamma_iso_emit(gp, insts[inst].mu0, insts[inst].riso, k1, k2, k3,
                        [&](int t, double v) { Gl[t * N + k3] = (T)(scale * v); });
+      } else if constexpr (GM == GREEN_MOMENTS) {
+        const int inst = inst_of[Lbeg];
+        moments_emit(table, pos, N, k3, insts[inst].mu0, insts[inst].riso,
+                     [&](int t, double v) { Gl[t * N + k3] = (T)(scale * v); });
       } else {
         double Gd[21];
         gamma_sym_at(gp, k1, k2, k3, Gd);
@@ -1088,6 +1109,35 @@ __global__ void k_gamma_table(Geo g, GreenParams gp, T* __restrict__ table, doub
     for (int w = 1; w < (int)((blockDim.x + 63) >> 6); ++w) r = fmin(r, red[w]);
     minden[blockIdx.x] = r;
   }
+}
+
+// One thread per half-spectrum bin: the normalised alias moments (isotropic C0
+// path), stored at T in the table layout [pos][21][n3] (6 second, 15 fourth).
+template <typename T>
+__global__ void k_moments_table(Geo g, GreenParams gp, T* __restrict__ table) {
+  const long long nb = g.spec;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (long long)gridDim.x * blockDim.x) {
+    const int k3 = (int)(i % g.n3);
+    const int k2 = (int)((i / g.n3) % g.n2);
+    const int k1 = (int)(i / ((long long)g.n2 * g.n3));
+    IsoMoments M;
+    iso_moments(gp, k1, k2, k3, M);
+    const long long pos = i / g.n3;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) table[(pos * 21 + t) * g.n3 + k3] = (T)M.a[t];
+#pragma unroll
+    for (int t = 0; t < 15; ++t) table[(pos * 21 + 6 + t) * g.n3 + k3] = (T)M.q[t];
+  }
+}
+
+// Gamma^p at probe bins from the moments table (the values the solver uses).
+template <typename T>
+__global__ void k_moments_probe(const T* __restrict__ table, double* __restrict__ out, const long long* __restrict__ bins,
+                                int n, Geo g, double mu0, double riso) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long long pos = bins[3 * i] * g.n2 + bins[3 * i + 1];
+  moments_emit(table, pos, g.n3, (int)bins[3 * i + 2], mu0, riso, [&](int t, double v) { out[21 * i + t] = v; });
 }
 
 __global__ void k_gamma_probe(GreenParams gp, const long long* __restrict__ bins, int n, double* __restrict__ out,

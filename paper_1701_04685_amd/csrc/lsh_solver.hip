@@ -86,7 +86,7 @@ struct KernSet {
   A1 a1[3] = {nullptr, nullptr, nullptr};  // MODE_STRESS, MODE_FINAL, MODE_INIT
   A2 a2[2] = {nullptr, nullptr};           // forward, inverse
   GR gr = nullptr;
-  GR gr2[3] = {nullptr, nullptr, nullptr};  // k_green2 per Green mode (ISO, GENERAL, TABLE)
+  GR gr2[4] = {nullptr, nullptr, nullptr, nullptr};  // k_green2 per Green mode (ISO, GENERAL, TABLE, MOMENTS)
   int W1 = 0, NT1 = 0, W2 = 0, NT2 = 0, NTG = 0, lsG = 0;
   A1 a1s = nullptr;  // the stress-pass kernel in use (a candidate below)
   int NT1s = 0, W1s = 0;
@@ -94,7 +94,7 @@ struct KernSet {
   // autotuner candidates per pass; entry 0 is the default
   struct CStress { A1 fn; int nt; size_t lds; int W; };
   struct CAxis2 { A2 fwd, inv; int W, nt; size_t lds; };
-  struct CGreen { GR fn[3]; int nt; size_t lds; };
+  struct CGreen { GR fn[4]; int nt; size_t lds; };
   std::vector<CStress> c1;
   std::vector<CAxis2> c2;
   std::vector<CGreen> cg;
@@ -266,6 +266,7 @@ typename KernSet<T>::CGreen green2_cand() {
   c.fn[GREEN_ISO] = k_green2<T, NC, NL, NT, GREEN_ISO>;
   c.fn[GREEN_GENERAL] = k_green2<T, NC, NL, NT, GREEN_GENERAL>;
   c.fn[GREEN_TABLE] = k_green2<T, NC, NL, NT, GREEN_TABLE>;
+  c.fn[GREEN_MOMENTS] = k_green2<T, NC, NL, NT, GREEN_MOMENTS>;
   c.nt = NT;
   c.lds = sizeof(C2<T>) * (size_t)NC + sizeof(T) * 21 * (size_t)NC + sizeof(C2<T>) * (size_t)NL * 6 * GreenPlan<NC>::LP +
           sizeof(C2<T>) * (size_t)(RL - 1) * (NC / RL);
@@ -281,7 +282,7 @@ void green_special(const Geo& g, KernSet<T>& K) {
     for (size_t i = K.cg.size(); i-- > 0;)
       if (K.cg[i].lds > (size_t)lds_limit()) K.cg.erase(K.cg.begin() + i);
     if (!K.cg.empty()) {
-      for (int m = 0; m < 3; ++m) K.gr2[m] = K.cg[0].fn[m];
+      for (int m = 0; m < 4; ++m) K.gr2[m] = K.cg[0].fn[m];
       K.gr = K.gr2[GREEN_ISO];
       K.NTG = K.cg[0].nt;
       K.ldsG = K.cg[0].lds;
@@ -387,15 +388,18 @@ bool c0_isotropic(const lsh_pattern* p, double* lam0, double* mu0) {
 int green_mode(const lsh_pattern* p) {
   double l, m;
   if (p->kind == LSH_BOXSPLINE) return GREEN_TABLE;
-  if (p->nphase >= 1 && c0_isotropic(p, &l, &m)) return GREEN_ISO;
+  if (p->nphase >= 1 && c0_isotropic(p, &l, &m))
+    return p->kind == LSH_DIRICHLET ? GREEN_ISO : GREEN_MOMENTS;  // Dirichlet: one alias, on the fly
   if (p->kind == LSH_DIRICHLET) return GREEN_GENERAL;
   return GREEN_TABLE;
 }
 
 bool kind_has_table(const lsh_pattern* p) {
-  // before the stiffness is known, size for the table
+  // the table slot holds Gamma^p rows (GREEN_TABLE) or alias moments
+  // (GREEN_MOMENTS); before the stiffness is known, size for it
   if (p->nphase < 1) return p->kind != LSH_DIRICHLET;
-  return green_mode(p) == GREEN_TABLE;
+  const int gm = green_mode(p);
+  return gm == GREEN_TABLE || gm == GREEN_MOMENTS;
 }
 
 template <typename T>
@@ -476,15 +480,22 @@ int bind_t(lsh_pattern* p, void* dev, size_t bytes, hipStream_t st) {
     const int nthr = 256;
     const int nblk = (int)std::min<long long>((g.spec + nthr - 1) / nthr, 4096);
     T* table = (T*)(base + p->off_table);
-    hipLaunchKernelGGL(k_gamma_table<T>, dim3(nblk), dim3(nthr), 0, st, g, gp, table, mins_dev);
-    HIPCHK(hipGetLastError());
-    std::vector<double> mins(nblk);
-    HIPCHK(hipMemcpyAsync(mins.data(), mins_dev, sizeof(double) * nblk, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    double mn = 1e300;
-    for (int i = 0; i < nblk; ++i) mn = std::min(mn, mins[i]);
-    if (!(mn > 0.0))
-      return lsh_fail(LSH_ENOINTERP, "a bracket sum of |c_k(f)|^2 vanishes: translates are not linearly independent");
+    if (green_mode(p) == GREEN_MOMENTS) {
+      // the trapezoid weights of the analytic kernels never all vanish
+      hipLaunchKernelGGL(k_moments_table<T>, dim3(nblk), dim3(nthr), 0, st, g, gp, table);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(st));
+    } else {
+      hipLaunchKernelGGL(k_gamma_table<T>, dim3(nblk), dim3(nthr), 0, st, g, gp, table, mins_dev);
+      HIPCHK(hipGetLastError());
+      std::vector<double> mins(nblk);
+      HIPCHK(hipMemcpyAsync(mins.data(), mins_dev, sizeof(double) * nblk, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      double mn = 1e300;
+      for (int i = 0; i < nblk; ++i) mn = std::min(mn, mins[i]);
+      if (!(mn > 0.0))
+        return lsh_fail(LSH_ENOINTERP, "a bracket sum of |c_k(f)|^2 vanishes: translates are not linearly independent");
+    }
     p->has_table = true;
   }
   p->dev_persist = base;
@@ -658,7 +669,7 @@ void apply_choice(KernSet<T>& K, int gmode, const int ch[3]) {
   }
   if (K.green2 && !K.cg.empty()) {
     const auto& c = K.cg[std::min<size_t>((size_t)ch[2], K.cg.size() - 1)];
-    for (int m = 0; m < 3; ++m) K.gr2[m] = c.fn[m];
+    for (int m = 0; m < 4; ++m) K.gr2[m] = c.fn[m];
     K.NTG = c.nt;
     K.ldsG = c.lds;
   }
@@ -1070,7 +1081,7 @@ bool same_group(const lsh_pattern* a, const lsh_pattern* b) {
     if (a->Xi[i] != b->Xi[i]) return false;
   const int ga = green_mode(a), gb = green_mode(b);
   if (ga != gb) return false;
-  if (ga != GREEN_ISO)  // the general form and the tables depend on C0
+  if (ga == GREEN_GENERAL || ga == GREEN_TABLE)  // these depend on C0 (ISO and moments do not)
     for (int i = 0; i < 36; ++i)
       if (a->C0_voigt[i] != b->C0_voigt[i]) return false;
   return true;
@@ -1155,13 +1166,20 @@ int probe_t(const lsh_pattern* p, const int64_t* bins, int n, double* out, void*
   HIPCHK(hipMemcpyAsync(dbins, bins, sizeof(long long) * 3 * n, hipMemcpyHostToDevice, st));
   GreenParams gp;
   lsh_green_params(p, &gp);
-  if (p->has_table) {
+  if (p->has_table && green_mode(p) == GREEN_MOMENTS) {
+    const T* table = (const T*)(p->dev_persist + p->off_table);
+    double lam0 = 0.0, mu0 = 1.0;
+    c0_isotropic(p, &lam0, &mu0);
+    hipLaunchKernelGGL((k_moments_probe<T>), dim3((n + 127) / 128), dim3(128), 0, st, table, dout, dbins, n, g, mu0,
+                       (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0)));
+  } else if (p->has_table) {
     const T* table = (const T*)(p->dev_persist + p->off_table);
     hipLaunchKernelGGL((k_cast_table<T>), dim3((n + 127) / 128), dim3(128), 0, st, table, dout, dbins, n, g);
   } else {
     double lam0 = 0.0, mu0 = 1.0;
     c0_isotropic(p, &lam0, &mu0);
-    hipLaunchKernelGGL(k_gamma_probe, dim3((n + 127) / 128), dim3(128), 0, st, gp, dbins, n, dout, green_mode(p), mu0,
+    hipLaunchKernelGGL(k_gamma_probe, dim3((n + 127) / 128), dim3(128), 0, st, gp, dbins, n, dout,
+                       green_mode(p), mu0,
                        (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0)));
   }
   HIPCHK(hipGetLastError());
