@@ -672,18 +672,16 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
   for (int i = tid; i < (RL - 1) * nblL; i += NT) twL[i] = tw[(i / nblL + 1) * (i % nblL)];
 
   // the position's Green operator, scaled by -1/m, formed once for the chunk
-  // (GM: GREEN_ISO moment form, GREEN_GENERAL on the fly, GREEN_TABLE rows)
+  // (GM: GREEN_MOMENTS isotropic C0 from the alias moments, GREEN_GENERAL on
+  // the fly, GREEN_TABLE stored rows)
   {
+    static_assert(GM != GREEN_ISO, "the isotropic path reads the moments table");
     const double scale = -1.0 / (double)g.m;
     for (int k3 = tid; k3 < N; k3 += NT) {
       if constexpr (GM == GREEN_TABLE) {
         const T* tb = table + (long long)pos * 21 * N + k3;
 #pragma unroll
         for (int t = 0; t < 21; ++t) Gl[t * N + k3] = (T)(scale * (double)tb[(long long)t * N]);
-      } else if constexpr (GM == GREEN_ISO) {
-        const int inst = inst_of[Lbeg];
-        gamma_iso_emit(gp, insts[inst].mu0, insts[inst].riso, k1, k2, k3,
-                       [&](int t, double v) { Gl[t * N + k3] = (T)(scale * v); });
       } else if constexpr (GM == GREEN_MOMENTS) {
         const int inst = inst_of[Lbeg];
         moments_emit(table, pos, N, k3, insts[inst].mu0, insts[inst].riso,

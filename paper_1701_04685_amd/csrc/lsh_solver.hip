@@ -263,7 +263,7 @@ typename KernSet<T>::CGreen green2_cand() {
   constexpr RadList RH = GreenPlan<NC>::RH;
   constexpr int RL = RH.r[RH.n - 1];
   typename KernSet<T>::CGreen c;
-  c.fn[GREEN_ISO] = k_green2<T, NC, NL, NT, GREEN_ISO>;
+  c.fn[GREEN_ISO] = nullptr;  // the isotropic path reads the moments table
   c.fn[GREEN_GENERAL] = k_green2<T, NC, NL, NT, GREEN_GENERAL>;
   c.fn[GREEN_TABLE] = k_green2<T, NC, NL, NT, GREEN_TABLE>;
   c.fn[GREEN_MOMENTS] = k_green2<T, NC, NL, NT, GREEN_MOMENTS>;
@@ -283,7 +283,7 @@ void green_special(const Geo& g, KernSet<T>& K) {
       if (K.cg[i].lds > (size_t)lds_limit()) K.cg.erase(K.cg.begin() + i);
     if (!K.cg.empty()) {
       for (int m = 0; m < 4; ++m) K.gr2[m] = K.cg[0].fn[m];
-      K.gr = K.gr2[GREEN_ISO];
+      K.gr = K.gr2[GREEN_MOMENTS];
       K.NTG = K.cg[0].nt;
       K.ldsG = K.cg[0].lds;
       K.green2 = 1;
@@ -388,8 +388,7 @@ bool c0_isotropic(const lsh_pattern* p, double* lam0, double* mu0) {
 int green_mode(const lsh_pattern* p) {
   double l, m;
   if (p->kind == LSH_BOXSPLINE) return GREEN_TABLE;
-  if (p->nphase >= 1 && c0_isotropic(p, &l, &m))
-    return p->kind == LSH_DIRICHLET ? GREEN_ISO : GREEN_MOMENTS;  // Dirichlet: one alias, on the fly
+  if (p->nphase >= 1 && c0_isotropic(p, &l, &m)) return GREEN_MOMENTS;
   if (p->kind == LSH_DIRICHLET) return GREEN_GENERAL;
   return GREEN_TABLE;
 }
@@ -397,7 +396,7 @@ int green_mode(const lsh_pattern* p) {
 bool kind_has_table(const lsh_pattern* p) {
   // the table slot holds Gamma^p rows (GREEN_TABLE) or alias moments
   // (GREEN_MOMENTS); before the stiffness is known, size for it
-  if (p->nphase < 1) return p->kind != LSH_DIRICHLET;
+  if (p->nphase < 1) return true;
   const int gm = green_mode(p);
   return gm == GREEN_TABLE || gm == GREEN_MOMENTS;
 }
