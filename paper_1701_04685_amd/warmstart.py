@@ -27,7 +27,7 @@ from . import lsh
 MATRIX = (1.0, 0.3)
 
 
-def grid_pattern(n, phase, contrast, kind="dlvp", kparams=None, precision="fp32"):
+def grid_pattern(n, phase, contrast, kind="dirichlet", kparams=None, precision="fp32"):
     """A bound pattern for M = diag(n, n, n) with the phase map in grid order."""
     P = lsh.Pattern(np.diag([n, n, n]))
     P.set_kernel(kind, kparams if kparams is not None else ({"alpha": [0.75] * 3} if kind == "dlvp" else None))
