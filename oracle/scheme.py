@@ -93,16 +93,10 @@ def effective_stiffness(P: Pattern, Gamma, C_phases_voigt, C0_voigt, phase, tol=
     return Ceff, its
 
 
-def dense_fixed_point(M, C0_voigt, kind, params, C_phases_voigt, phase_by_point, eps0_voigt):
-    """Solve eq. (pde_coefficients) directly as a dense linear system (tiny m).
-
-    Independent of the SNF path: the pattern DFT is the matrix of
-    eq. (Fouriermatrix) over brute-force enumerations of P(M) and G(M^T), and
-    Gamma^p_h is evaluated at those h.  Unknowns are E_y (6 per point):
-        (I + R) E = -R eps0,   R = Re F^H diag(Gamma_h) F (C - C0).
-    ``phase_by_point`` maps each brute-force point (tuple of Fractions) to its
-    phase.  Returns (Y, E) with Y the points and E (m, 6) Mandel.
-    """
+def _dense_pieces(M, C0_voigt, kind, params, C_phases_voigt, phase_by_point):
+    """Fourier matrix of eq. (Fouriermatrix) over brute-force enumerations of P(M)
+    and G(M^T), Gamma^p at those h (alias sum written out), and the per-point
+    Mandel stiffness.  Returns (F, Y, G (m,6,6), Cm_points (m,6,6), C0 Mandel)."""
     F, H, Y = dft.fourier_matrix(M)
     from .lattice import brute_force_points
     Yf = brute_force_points(M)
@@ -111,8 +105,6 @@ def dense_fixed_point(M, C0_voigt, kind, params, C_phases_voigt, phase_by_point,
     C0 = green.voigt_stiffness_to_mandel(C0_voigt)
     Cm = green.voigt_stiffness_to_mandel(np.asarray(C_phases_voigt, dtype=np.float64))
     ph = np.array([phase_by_point[y] for y in Yf], dtype=np.int64)
-    Delta = Cm[ph] - C0[None]
-    # Gamma^p at the brute-force rows h: sum over aliases of the weights
     MT = np.array(P.MT, dtype=np.int64)
     Minv_T = np.linalg.inv(np.array(P.M, dtype=np.float64)).T
     g = green.weight_fn(kind, params)
@@ -130,18 +122,101 @@ def dense_fixed_point(M, C0_voigt, kind, params, C_phases_voigt, phase_by_point,
                 num += w * green.gamma0(C0_voigt, (h + MT @ z)[None])[0]
                 den += w
         G[r] = num / den
-    # operator A: E (m*6) -> Re F^H Gamma F (Delta E), F unitary
+    return F, Y, G, Cm[ph], C0
+
+
+def _dense_operator(F, G, D):
+    """Matrix of E (m*6) -> Re F^H Gamma F (D E) for per-point 6x6 blocks D."""
+    m = F.shape[0]
     Fh = F.conj().T
     A = np.zeros((m * 6, m * 6))
     for p in range(m):
         for j in range(6):
             v = np.zeros((m, 6))
-            v[p] = Delta[p][:, j]          # column j of Delta at point p
+            v[p] = D[p][:, j]                # column j of D at point p
             vh = F @ v                       # (m, 6) spectrum
-            out = -(Fh @ np.einsum("hij,hj->hi", G, vh)).real
-            A[:, p * 6 + j] = out.reshape(-1)
+            A[:, p * 6 + j] = (Fh @ np.einsum("hij,hj->hi", G, vh)).real.reshape(-1)
+    return A
+
+
+def dense_fixed_point(M, C0_voigt, kind, params, C_phases_voigt, phase_by_point, eps0_voigt):
+    """Solve eq. (pde_coefficients) directly as a dense linear system (tiny m).
+
+    Independent of the SNF path: the pattern DFT is the matrix of
+    eq. (Fouriermatrix) over brute-force enumerations of P(M) and G(M^T), and
+    Gamma^p_h is evaluated at those h.  Unknowns are E_y (6 per point):
+        (I + R) E = -R eps0,   R = Re F^H diag(Gamma_h) F (C - C0).
+    ``phase_by_point`` maps each brute-force point (tuple of Fractions) to its
+    phase.  Returns (Y, E) with Y the points and E (m, 6) Mandel.
+    """
+    F, Y, G, Cp, C0 = _dense_pieces(M, C0_voigt, kind, params, C_phases_voigt, phase_by_point)
+    m = len(Y)
+    A = -_dense_operator(F, G, Cp - C0[None])
     eps0 = green.voigt_strain_to_mandel(eps0_voigt)
     rhs = (A @ np.tile(eps0, m))
     # E = A (E + eps0)  ->  (I - A) E = A eps0
     E = np.linalg.solve(np.eye(m * 6) - A, rhs).reshape(m, 6)
     return Y, E
+
+
+def dense_variational_point(M, C0_voigt, kind, params, C_phases_voigt, phase_by_point, eps0_voigt):
+    """Solve eq. (pde_coefficients_variational) directly (tiny m): with
+    R = Re F^H diag(Gamma_h) F (symmetric), find E in range(R) with
+    R C (E + eps0) = 0.  E = Q c over an orthonormal basis Q of range(R):
+        (Q^T R C Q) c = -Q^T R C eps0.
+    Returns (Y, E) as dense_fixed_point."""
+    F, Y, G, Cp, C0 = _dense_pieces(M, C0_voigt, kind, params, C_phases_voigt, phase_by_point)
+    m = len(Y)
+    R = _dense_operator(F, G, np.broadcast_to(np.eye(6), (m, 6, 6)))
+    R = 0.5 * (R + R.T)
+    w, V = np.linalg.eigh(R)
+    Q = V[:, np.abs(w) > 1e-10 * np.abs(w).max()]
+    Cb = np.zeros((m * 6, m * 6))
+    for p in range(m):
+        Cb[6 * p:6 * p + 6, 6 * p:6 * p + 6] = Cp[p]
+    eps0 = np.tile(green.voigt_strain_to_mandel(eps0_voigt), m)
+    K = Q.T @ R @ Cb
+    c = np.linalg.solve(K @ Q, -K @ eps0)
+    return Y, (Q @ c).reshape(m, 6)
+
+
+def variational_scheme(P: Pattern, Gamma, C_phases_voigt, C0_voigt, phase, eps0_voigt,
+                       tol=1e-10, max_iter=1000, E_init=None, n_iter=None):
+    """Fixed point for the variational discretisation, eq. (pde_coefficients_variational).
+
+    Thm. (ls_discretization): the sample values E_y satisfy
+        F^{-1}[ Gamma^p_h F[C:(E + eps0)]_h ] = 0      (C0 in front is invertible).
+    Iterated in the strain-update form
+        E^{k+1} = E^k - Re F^{-1}[ Gamma^p_h F[C:(E^k + eps0)]_h ],
+    whose fixed points are exactly the solutions in the range of Gamma^p.  For the
+    Dirichlet kernel Gamma^p C0 is a projection that fixes the iterates, and the
+    iterates coincide with the polarisation form (Remark (constants)); for the
+    other kernels they do not.  Residual, output and arguments as basic_scheme.
+    """
+    m = P.m
+    C = stiffness_field(C_phases_voigt, phase)
+    eps0 = green.voigt_strain_to_mandel(eps0_voigt)
+    if E_init is None:
+        E = np.zeros((m, 6))
+    else:
+        E = np.array(E_init, dtype=np.float64).reshape(m, 6)
+        E = E - E.mean(axis=0, keepdims=True)
+    history = []
+    it = 0
+    limit = n_iter if n_iter is not None else max_iter
+    while it < limit:
+        s = np.einsum("yij,yj->yi", C, E + eps0)                    # C:(E + eps0)
+        s_hat = dft.pattern_dft(P, s)
+        corr = dft.pattern_idft(P, np.einsum("bij,bj->bi", Gamma, s_hat)).real
+        E_new = E - corr
+        num = np.sqrt(np.sum((E_new - E) ** 2))
+        den = np.sqrt(np.sum((E_new + eps0) ** 2))
+        r = num / den
+        E = E_new
+        it += 1
+        history.append(r)
+        if n_iter is None and r <= tol:
+            break
+    sigma = np.einsum("yij,yj->i", C, E + eps0) / m
+    return dict(E=E, sigma_voigt=green.mandel_stress_to_voigt(sigma), iterations=it,
+                history=np.array(history))

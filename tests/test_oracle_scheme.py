@@ -154,3 +154,82 @@ def test_ls_and_variational_differ_for_dlvp_only():
         out[kind] = np.abs(eps - GCe - green.voigt_strain_to_mandel(eps0)).max()
     assert out["dirichlet"] < 1e-12
     assert out["dlvp"] > 1e-4
+
+
+# ----------------------------------------------------- variational (VE) ---
+def test_variational_iterates_equal_ls_for_dirichlet():
+    """Remark (constants): for the Dirichlet space Gamma^p C0 fixes compatible
+    fields, so the strain-update (variational) iterates equal the polarisation
+    (Lippmann-Schwinger) iterates one by one.  Odd axes: no real-part projection."""
+    P = Pattern(np.diag([5, 5, 7]))
+    rng = np.random.default_rng(11)
+    ph = rng.integers(0, 2, size=P.m).astype(np.uint8)
+    Cp, C0 = two_phase(1.0, 10.0, 0.3)
+    eps0 = np.array([0.3, -0.2, 0.1, 0.4, -0.1, 0.25])
+    G, _ = green.gamma_periodised(P, C0, "dirichlet")
+    a = scheme.basic_scheme(P, G, Cp, C0, ph, eps0, n_iter=12)
+    b = scheme.variational_scheme(P, G, Cp, C0, ph, eps0, n_iter=12)
+    np.testing.assert_allclose(b["history"], a["history"], rtol=1e-10)
+    np.testing.assert_allclose(b["E"], a["E"], atol=1e-12)
+
+
+@pytest.mark.parametrize("kind,params", [("dlvp", {"alpha": [0.75] * 3}), ("box", BOX4),
+                                         ("dirichlet_modified", {})])
+def test_variational_fixed_point_equals_dense_solve(kind, params):
+    """The strain-update limit solves eq. (pde_coefficients_variational): compare
+    with a dense solve in the range of the Green multiplier, assembled from the
+    Fourier matrix written out entry by entry.  The Box multiplier has small
+    eigenvalues on its range, where the strain update contracts slowly; there
+    the comparison allows the iteration error r / (1 - rho), rho estimated from
+    the last residuals."""
+    M = [[4, 1, 0], [0, 4, 0], [0, 0, 2]]
+    P = Pattern(M)
+    rng = np.random.default_rng(12)
+    ph = rng.integers(0, 2, size=P.m).astype(np.uint8)
+    Cp, C0 = two_phase(1.0, 5.0, 0.3)
+    eps0 = np.array([0.2, -0.1, 0.05, 0.3, 0.1, -0.2])
+    G, _ = green.gamma_periodised(P, C0, kind, params)
+    res = scheme.variational_scheme(P, G, Cp, C0, ph, eps0, tol=1e-15, max_iter=20000)
+    Ynum = P.point_numerators()
+    by_point = {tuple(Fraction(int(v), P.m) for v in row): int(p) for row, p in zip(Ynum, ph)}
+    Y, Ed = scheme.dense_variational_point(M, C0, kind, params, Cp, by_point, eps0)
+    key = {tuple(Fraction(int(v), P.m) for v in row): i for i, row in enumerate(Ynum)}
+    from oracle.lattice import brute_force_points
+    order = [key[y] for y in brute_force_points(M)]
+    h = res["history"]
+    rho = min(h[-1] / h[-2], 1 - 1e-12)
+    bound = max(1e-10, 10 * h[-1] / (1 - rho)) * max(1, np.abs(Ed).max())
+    assert bound < 1e-5
+    np.testing.assert_allclose(res["E"][order], Ed, atol=bound)
+
+
+@pytest.mark.parametrize("kind,params", KERNELS)
+def test_variational_laminate_closed_form(kind, params):
+    """The laminate's exact fields live on frequencies (h1, 0, 0), where every
+    kernel's Gamma^p equals Gamma0, so the variational fixed point is the same
+    closed form as the Lippmann-Schwinger one."""
+    C, _ = _laminate_closed_form()
+    P = Pattern(np.diag([16, 16, 16]))
+    ph = (P.points()[:, 0] >= 0).astype(np.uint8)
+    Cp, C0 = two_phase(1.0, 10.0, 0.3)
+    G, _ = green.gamma_periodised(P, C0, kind, params)
+    res = scheme.variational_scheme(P, G, Cp, C0, ph, np.array([1.0, 0, 0, 0, 0, 0]), tol=1e-12, max_iter=200)
+    np.testing.assert_allclose(res["sigma_voigt"], C[:, 0], rtol=1e-10, atol=1e-12)
+
+
+def test_variational_differs_from_ls_for_dlvp():
+    """The two discretisations coincide only on the Dirichlet space: their
+    effective stresses differ for dlVP and agree for Dirichlet (odd axes)."""
+    P = Pattern(np.diag([5, 5, 7]))
+    rng = np.random.default_rng(13)
+    ph = rng.integers(0, 2, size=P.m).astype(np.uint8)
+    Cp, C0 = two_phase(1.0, 10.0, 0.3)
+    eps0 = np.array([1.0, 0, 0, 0, 0, 0])
+    d = {}
+    for kind, params in [("dirichlet", {}), ("dlvp", {"alpha": [0.75] * 3})]:
+        G, _ = green.gamma_periodised(P, C0, kind, params)
+        a = scheme.basic_scheme(P, G, Cp, C0, ph, eps0, tol=1e-14, max_iter=5000)["sigma_voigt"]
+        b = scheme.variational_scheme(P, G, Cp, C0, ph, eps0, tol=1e-14, max_iter=5000)["sigma_voigt"]
+        d[kind] = np.abs(a - b).max() / np.abs(a).max()
+    assert d["dirichlet"] < 1e-11
+    assert d["dlvp"] > 1e-4
