@@ -123,6 +123,18 @@ int lsh_set_kernel(lsh_pattern *p, lsh_kernel kind, const double *params, int np
 int lsh_set_stiffness(lsh_pattern *p, int nphase, const double *C_voigt,
                       const double *C0_voigt, const uint8_t *phase);
 
+/* Discretisation solved by lsh_solve / lsh_solve_batch:
+ *   LSH_SCHEME_LS (default): the Lippmann-Schwinger form, eq. (pde_coefficients),
+ *     Thm. (pde_discretization), iterated in the polarisation form
+ *       E <- -Gamma^p[(C - C0):(E + eps0)];
+ *   LSH_SCHEME_VE: the variational form, eq. (pde_coefficients_variational),
+ *     Thm. (ls_discretization), iterated in the strain-update form
+ *       E <- E - Gamma^p[C:(E + eps0)].
+ * The two coincide for the Dirichlet kernel (Remark (constants)).  Changing the
+ * scheme drops the device binding (call lsh_bind again).  Errors: LSH_EINVAL.    */
+typedef enum { LSH_SCHEME_LS = 0, LSH_SCHEME_VE = 1 } lsh_scheme;
+int lsh_set_scheme(lsh_pattern *p, lsh_scheme scheme);
+
 /* ------------------------------------------------------------- device binding ---
  * Bytes of persistent device memory for this pattern at precision prec: the
  * phase map, FFT twiddles and, for LSH_BOXSPLINE, the Gamma^p table (21

@@ -355,6 +355,16 @@ extern "C" int lsh_set_kernel(lsh_pattern* p, lsh_kernel kind, const double* par
   return LSH_OK;
 }
 
+extern "C" int lsh_set_scheme(lsh_pattern* p, lsh_scheme scheme) {
+  if (!p) return lsh_fail(LSH_EINVAL, "null pattern");
+  if (scheme != LSH_SCHEME_LS && scheme != LSH_SCHEME_VE) return lsh_fail(LSH_EINVAL, "unknown scheme");
+  if (p->scheme != (int)scheme) {
+    p->scheme = (int)scheme;
+    p->bound_prec = -1;  // the stress matrices on the device depend on the scheme
+  }
+  return LSH_OK;
+}
+
 extern "C" int lsh_set_stiffness(lsh_pattern* p, int nphase, const double* C_voigt, const double* C0_voigt,
                                  const uint8_t* phase) {
   if (!p || !C_voigt || !C0_voigt || !phase) return lsh_fail(LSH_EINVAL, "null argument");

@@ -32,6 +32,7 @@ struct lsh_pattern {
   std::vector<double> C_voigt;   // nphase * 36
   double C0_voigt[36];
   std::vector<uint8_t> phase;    // m, storage order
+  int scheme = 0;                // lsh_scheme: 0 Lippmann-Schwinger, 1 variational
 
   // ---- device binding (one precision at a time)
   int bound_prec = -1;

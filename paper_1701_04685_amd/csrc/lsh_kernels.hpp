@@ -375,7 +375,8 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
                                               const Inst* __restrict__ insts, const int* __restrict__ inst_of,
                                               const int* __restrict__ chunks_unused,
                                               const int* __restrict__ stop_iter, const int* __restrict__ itp,
-                                              int nload, int npos, double* __restrict__ partial, int ls, int gmode) {
+                                              int nload, int npos, double* __restrict__ partial, int ls, int gmode,
+                                              int ve) {
   using T2 = C2<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n3 = NC > 0 ? NC : g.n3;
@@ -467,7 +468,8 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
   auto finish = [&](int idx, T2 ov) {
     const int c = idx / n3, k3 = idx - c * n3;
     const long long gi = ((long long)(L * 6 + c)) * g.spec + row + k3;
-    const T2 nv = lines[c * ls + k3];
+    // variational scheme: the pass computes the correction, added to P_old
+    const T2 nv = ve ? cadd(lines[c * ls + k3], ov) : lines[c * ls + k3];
     Pnew[gi] = nv;
     const double dx = (double)nv.x - (double)ov.x, dy = (double)nv.y - (double)ov.y;
     acc[0] += wk1 * (dx * dx + dy * dy);
@@ -611,7 +613,7 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
                                                const Inst* __restrict__ insts, const int* __restrict__ inst_of,
                                                const int* __restrict__ chunks, const int* __restrict__ stop_iter,
                                                const int* __restrict__ itp, int nload, int npos,
-                                               double* __restrict__ partial, int ls_unused, int gmode) {
+                                               double* __restrict__ partial, int ls_unused, int gmode, int ve) {
   using T2 = C2<T>;
   static_assert(NL == 1 || NL == 2, "one or two loads at a time");
   (void)pl;
@@ -817,7 +819,8 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
           double dd = 0.0, nn = 0.0;
 #pragma unroll
           for (int r = 0; r < R; ++r) {
-            const T2 nv = v[q][r], ov = po[q][r];
+            // variational scheme: the pass computes the correction, added to P_old
+            const T2 ov = po[q][r], nv = ve ? cadd(v[q][r], ov) : v[q][r];
             dstp[r * nbl] = nv;
             const double dx = (double)nv.x - (double)ov.x, dy = (double)nv.y - (double)ov.y;
             dd += dx * dx + dy * dy;

@@ -82,7 +82,7 @@ struct KernSet {
                       const int*, const int*, const double*, const double*, double*, double*);
   using A2 = void (*)(Geo, FftPlan, const C2<T>*, const C2<T>*, C2<T>*, const int*, const int*, T);
   using GR = void (*)(Geo, FftPlan, const C2<T>*, GreenParams, const C2<T>*, const C2<T>*, C2<T>*, const T*,
-                      const Inst*, const int*, const int*, const int*, const int*, int, int, double*, int, int);
+                      const Inst*, const int*, const int*, const int*, const int*, int, int, double*, int, int, int);
   A1 a1[3] = {nullptr, nullptr, nullptr};  // MODE_STRESS, MODE_FINAL, MODE_INIT
   A2 a2[2] = {nullptr, nullptr};           // forward, inverse
   GR gr = nullptr;
@@ -456,7 +456,8 @@ int bind_t(lsh_pattern* p, void* dev, size_t bytes, hipStream_t st) {
     double Cm[36];
     lsh_voigt_to_mandel(p->C_voigt.data() + 36 * q, Cm);
     for (int i = 0; i < 36; ++i) {
-      dm[36 * q + i] = (T)(Cm[i] - C0m[i]);
+      // stress-pass matrix: C_p - C0 (Lippmann-Schwinger), C_p (variational)
+      dm[36 * q + i] = (T)(p->scheme == LSH_SCHEME_VE ? Cm[i] : Cm[i] - C0m[i]);
       cm[36 * q + i] = Cm[i];
     }
   }
@@ -804,7 +805,8 @@ void launch_green(GroupRun<T>& G, int cur, hipStream_t st) {
   hipLaunchKernelGGL(G.K.gr, G.gridG, dim3(G.K.NTG), G.K.ldsG, st, G.g, p->plan[2], tw2, G.gp, (const T2*)G.w.TAU,
                      (const T2*)G.w.P[cur], (T2*)G.w.P[1 - cur], table, (const Inst*)G.w.insts,
                      (const int*)G.w.inst_of, (const int*)G.w.chunks, (const int*)G.w.stop_iter,
-                     (const int*)G.w.itp, G.nload, G.npos, G.w.partial, G.K.lsG, G.gmode);
+                     (const int*)G.w.itp, G.nload, G.npos, G.w.partial, G.K.lsG, G.gmode,
+                     G.spec.rep->scheme == LSH_SCHEME_VE ? 1 : 0);
 }
 
 // One Basic Scheme iteration of a group: stress (axis 1), axis 2, Green pass
@@ -1073,7 +1075,7 @@ int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int
 bool same_group(const lsh_pattern* a, const lsh_pattern* b) {
   for (int i = 0; i < 9; ++i)
     if (a->M[i] != b->M[i]) return false;
-  if (a->kind != b->kind || a->R != b->R || a->nxi != b->nxi) return false;
+  if (a->kind != b->kind || a->R != b->R || a->nxi != b->nxi || a->scheme != b->scheme) return false;
   for (int i = 0; i < 3; ++i)
     if (a->alpha[i] != b->alpha[i]) return false;
   for (int i = 0; i < 3 * LSH_MAX_XI; ++i)

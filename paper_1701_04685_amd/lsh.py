@@ -27,7 +27,7 @@ STATUS = {0: "LSH_OK", -1: "LSH_EINVAL", -2: "LSH_ESINGULAR", -3: "LSH_ENOINTERP
 EXPORTS = ["lsh_create_pattern", "lsh_destroy", "lsh_pattern_info", "lsh_pattern_snf", "lsh_pattern_points",
            "lsh_set_kernel", "lsh_set_stiffness", "lsh_persistent_bytes", "lsh_bind", "lsh_gamma_probe",
            "lsh_solve_bytes", "lsh_solve", "lsh_batch_bytes", "lsh_solve_batch", "lsh_profile_enable",
-           "lsh_profile_read", "lsh_last_error", "lsh_autotune", "lsh_tune_reset", "lsh_tune_set", "lsh_unet_create", "lsh_unet_destroy", "lsh_unet_param_count",
+           "lsh_profile_read", "lsh_last_error", "lsh_autotune", "lsh_tune_reset", "lsh_tune_set", "lsh_set_scheme", "lsh_unet_create", "lsh_unet_destroy", "lsh_unet_param_count",
            "lsh_unet_param_bytes", "lsh_unet_bind", "lsh_unet_get_params", "lsh_unet_act_bytes",
            "lsh_unet_train_step", "lsh_unet_zero_grad", "lsh_unet_get_grads", "lsh_unet_predict", "lsh_unet_head",
            "lsh_unet_layers", "lsh_unet_pack_target"]
@@ -79,6 +79,7 @@ _sig = {
     "lsh_last_error": ([], ctypes.c_char_p),
     "lsh_autotune": ([_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t, _P, _P], ctypes.c_int),
     "lsh_tune_reset": ([_P], ctypes.c_int),
+    "lsh_set_scheme": ([_P, ctypes.c_int], ctypes.c_int),
     "lsh_tune_set": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "lsh_unet_create": ([ctypes.c_int, ctypes.POINTER(_P)], ctypes.c_int),
     "lsh_unet_destroy": ([_P], None),
@@ -218,6 +219,11 @@ class Pattern:
             raise ValueError("phase map must have m entries")
         _check(_lib.lsh_set_stiffness(self._h, C.shape[0], _dptr(C), _dptr(C0),
                                       ph.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        self._prec = None
+
+    def set_scheme(self, scheme):
+        """'ls' (Lippmann-Schwinger, default) or 've' (variational); rebind afterwards."""
+        _check(_lib.lsh_set_scheme(self._h, {"ls": 0, "ve": 1}[scheme]))
         self._prec = None
 
     def bind(self, precision="fp64"):

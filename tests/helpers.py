@@ -67,6 +67,10 @@ class Problem:
         return scheme.basic_scheme(self.O, self.gamma_oracle(), self.Cp, self.C0, self.phase_o, eps0,
                                    tol=tol, max_iter=max_iter, n_iter=n_iter)
 
+    def oracle_solve_ve(self, eps0, tol=1e-10, max_iter=1000, n_iter=None):
+        return scheme.variational_scheme(self.O, self.gamma_oracle(), self.Cp, self.C0, self.phase_o, eps0,
+                                         tol=tol, max_iter=max_iter, n_iter=n_iter)
+
     def gpu_E_to_oracle_mandel(self, E):
         """GPU field [6][m] (Voigt, engineering shear) -> oracle order (m, 6) Mandel."""
         E = np.asarray(E).reshape(6, -1)[:, self.q].T
