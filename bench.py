@@ -211,7 +211,9 @@ def bench_cfg5(args):
     f = 0.3, radii 6-12 grid steps, contrast 100, Dirichlet kernel, FP32 path),
     evaluated on unseen 128^3 packings: time to the Cauchy residual 1e-6 from
     the learned start (inference and the judged fallback included) vs the
-    zero start."""
+    zero start.  The evaluation solves run the FP64 path: the FP32 path's
+    residual floor at this contrast lies near 1e-6, so some FP32 solves
+    stall just above the tolerance whatever their start."""
     import torch
     from paper_1701_04685_amd import lsh, warmstart as wst
     import lsh_inputs as li
@@ -236,27 +238,31 @@ def bench_cfg5(args):
     rows = []
     for k in range(args.eval_packings):
         ph = wst.packing(60000 + k, n_eval)
-        P = wst.grid_pattern(n_eval, ph, 100.0)
+        P = wst.grid_pattern(n_eval, ph, 100.0, precision="fp64")
         if k == 0:
             wst.check_grid_order(P, n_eval)
             ws = torch.empty(P.workspace_bytes(2), dtype=torch.uint8, device="cuda")
         phd = torch.from_numpy(ph).cuda()
         eps = li.random_unit_load(rng)
         if k == 0:  # untimed warm-up of both paths
-            wst.solve_plain(P, eps, workspace=ws)
-            wst.solve_learned(P, net, phd, n_eval, eps, workspace=ws)
-        a = wst.solve_plain(P, eps, workspace=ws)
-        b = wst.solve_learned(P, net, phd, n_eval, eps, workspace=ws)
+            wst.solve_plain(P, eps, workspace=ws, max_iter=20000)
+            wst.solve_learned(P, net, phd, n_eval, eps, workspace=ws, max_iter=20000)
+        a = wst.solve_plain(P, eps, workspace=ws, max_iter=20000)
+        b = wst.solve_learned(P, net, phd, n_eval, eps, workspace=ws, max_iter=20000)
         row = dict(plain_s=a["seconds"], learned_s=b["seconds"], plain_it=a["iterations"],
                    learned_it=b["iterations"], fell_back=b["fell_back"],
                    dsig=float(np.abs(a["sigma"] - b["sigma"]).max() / np.abs(a["sigma"]).max()),
                    converged=a["converged"] and b["converged"])
         if k < args.ablation_packings:
-            c = wst.solve_learned(P, untrained, phd, n_eval, eps, workspace=ws)
+            c = wst.solve_learned(P, untrained, phd, n_eval, eps, workspace=ws, max_iter=20000)
             row["untrained_s"], row["untrained_it"] = c["seconds"], c["iterations"]
         rows.append(row)
+        if not row["converged"]:
+            log(f"eval packing {60000 + k}: not converged (plain {a['iterations']}, learned {b['iterations']})")
         if (k + 1) % 20 == 0:
             log(f"eval {k + 1}/{args.eval_packings}")
+    nconv = sum(not r["converged"] for r in rows)
+    rows = [r for r in rows if r["converged"]]   # the ratio is taken over solves that reached tol
     ratio = np.array([r["plain_s"] / r["learned_s"] for r in rows])
     pit = np.array([r["plain_it"] for r in rows])
     lit = np.array([r["learned_it"] for r in rows])
@@ -274,16 +280,15 @@ def bench_cfg5(args):
     # how the iteration count reacts to the start's error: exact field (FP64,
     # tol 1e-9) scaled, or plus white noise of a given RMS, on the first packing
     ph = wst.packing(60000, n_eval)
-    P = wst.grid_pattern(n_eval, ph, 100.0)
-    P64 = wst.grid_pattern(n_eval, ph, 100.0, precision="fp64")
+    P = wst.grid_pattern(n_eval, ph, 100.0, precision="fp64")
     eps = np.eye(6)[0].reshape(1, 6)
-    Es = P64.solve(eps, tol=1e-9, max_iter=6000, return_E=True)["E"]
-    del P64
+    Es = P.solve(eps, tol=1e-9, max_iter=6000, return_E=True)["E"]
     rms = Es.norm().item() / np.sqrt(Es.numel())
     nrng = np.random.Generator(np.random.PCG64(8))
 
     def iters_from(E0):
-        return int(P.solve(eps, tol=1e-6, max_iter=6000, E_init=E0, workspace=ws)["iterations"][0])
+        o = P.solve(eps, tol=1e-6, max_iter=20000, E_init=E0, workspace=ws, allow_notconverged=True)
+        return int(o["iterations"][0]) if o["converged"][0] else None
 
     sens = {"zero": iters_from(None), "0.9*exact": iters_from((0.9 * Es).contiguous())}
     for sg in (1e-1, 1e-2, 1e-3):
@@ -295,10 +300,10 @@ def bench_cfg5(args):
     out = {"metric": METRIC, "value": float(np.median(ratio)), "unit": "x (t_plain / t_learned, median)",
            "n_gpus": 1, "steps": len(rows), "warmup": 1,
            "ms_per_step": float(np.median([r["learned_s"] for r in rows]) * 1e3), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (U-Net) / f32 (solver)", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (U-Net) / f64 (solver)", "data": "synthetic",
            "config": {"workload": f"learned warm start: U-Net trained on {len(its) * 6} fields "
                                   f"({len(its)} RSA packings 64^3, 6 unit loads), evaluated on {len(rows)} unseen "
-                                  f"128^3 packings, f=0.3, radii 6-12, contrast 100, Dirichlet, FP32, tol 1e-6",
+                                  f"128^3 packings, f=0.3, radii 6-12, contrast 100, Dirichlet, FP64 solver, tol 1e-6",
                       "epochs": args.epochs, "train_steps": args.epochs * len(its)},
            "roofline": None, "cpu_baseline": None,
            "warm_start": {
@@ -308,7 +313,8 @@ def bench_cfg5(args):
                "learned_ms_median": float(np.median([r["learned_s"] for r in rows]) * 1e3),
                "plain_iterations_median": float(np.median(pit)), "learned_iterations_median": float(np.median(lit)),
                "fallback_fraction": float(np.mean([r["fell_back"] for r in rows])),
-               "all_converged": bool(all(r["converged"] for r in rows)),
+               "not_converged_packings": int(nconv),
+               "plain_iterations_min_max": [int(pit.min()), int(pit.max())],
                "sigma_rel_diff_max": float(max(r["dsig"] for r in rows)),
                "inference_ms_128": round(t_inf * 1e3, 3),
                "untrained_ratio_median": (float(np.median([r["plain_s"] / r["untrained_s"] for r in abl]))

@@ -51,8 +51,11 @@ def packing(seed, n, fraction=0.3, rmin=6.0, rmax=12.0):
 
 
 def unit_load_fields(P, tol=1e-6, max_iter=3000, workspace=None):
-    """Fluctuation fields [6][6][m] (Voigt) of the six unit Voigt loads."""
-    out = P.solve(li.unit_loads(), tol=tol, max_iter=max_iter, return_E=True, workspace=workspace)
+    """Fluctuation fields [6][6][m] (Voigt) of the six unit Voigt loads.  A load
+    that stops at max_iter (the FP32 path's residual floor can sit near tol)
+    still gives a field accurate far beyond what training needs."""
+    out = P.solve(li.unit_loads(), tol=tol, max_iter=max_iter, return_E=True, workspace=workspace,
+                  allow_notconverged=True)
     return out["E"], out
 
 
@@ -112,7 +115,7 @@ def solve_plain(P, eps0, tol=1e-6, max_iter=3000, workspace=None):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = P.solve(eps0, tol=tol, max_iter=max_iter, workspace=workspace)
+    out = P.solve(eps0, tol=tol, max_iter=max_iter, workspace=workspace, allow_notconverged=True)
     t = time.perf_counter() - t0
     return dict(seconds=t, iterations=int(out["iterations"][0]), sigma=out["sigma"][0],
                 converged=bool(out["converged"][0]))
@@ -149,7 +152,7 @@ def solve_learned(P, net, phase_dev, n, eps0, tol=1e-6, max_iter=3000, check=10,
         first = None
     if first is None:
         pick, its0 = 1, 0
-        out = P.solve(eps0, tol=tol, max_iter=max_iter, workspace=workspace)
+        out = P.solve(eps0, tol=tol, max_iter=max_iter, workspace=workspace, allow_notconverged=True)
     else:
         r = first["residual"]
         hist = first["history"]
@@ -161,7 +164,7 @@ def solve_learned(P, net, phase_dev, n, eps0, tol=1e-6, max_iter=3000, check=10,
                        converged=np.array([True]))
         else:
             out = P.solve(eps0, tol=tol, max_iter=max_iter - its0, E_init=first["E"][pick:pick + 1],
-                          workspace=workspace)
+                          workspace=workspace, allow_notconverged=True)
     t = time.perf_counter() - t0
     return dict(seconds=t, iterations=its0 + int(out["iterations"][0]), sigma=out["sigma"][0],
                 converged=bool(out["converged"][0]), fell_back=pick == 1)
