@@ -91,9 +91,12 @@ __device__ __forceinline__ void stress6(const T* D, const T E[6], T t[6]) {
 // ------------------------------------------------------- axis-1 (stress) ---
 // One block: the axis-1 lines at fixed (load, i2) for W consecutive i3 and all
 // six components; component pairs (0,1), (2,3), (4,5) share one complex line.
-// LDS: twiddles[n1] then Z[k][q*W + w] (k < n1, q < 3, w < W).
-template <typename T, int MODE, int NC, int W, int NT>
-__global__ void __launch_bounds__(NT) k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
+// LDS: twiddles[n1] then Z[k][q*W + w] (k < n1, q < 3, w < W), then the
+// (C_p - C0) of the first NDL phases (more phases are read from global memory).
+// MINW asks the compiler for at least that many waves per SIMD.
+template <typename T, int MODE, int NC, int W, int NT, int NDL = 16, int MINW = 1>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
+k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
                                               const C2<T>* __restrict__ X, C2<T>* __restrict__ Y,
                                               const Inst* __restrict__ insts, const int* __restrict__ inst_of,
                                               const double* __restrict__ eps0, const int* __restrict__ stop_iter,
@@ -102,7 +105,6 @@ __global__ void __launch_bounds__(NT) k_axis1(Geo g, FftPlan pl, const C2<T>* __
                                               double* __restrict__ partial) {
   using T2 = C2<T>;
   constexpr int W3 = 3 * W;
-  constexpr int NDL = 16;  // phases whose (C_p - C0) live in LDS
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n1 = NC > 0 ? NC : g.n1;
   const int h1 = n1 / 2 + 1;
@@ -116,9 +118,11 @@ __global__ void __launch_bounds__(NT) k_axis1(Geo g, FftPlan pl, const C2<T>* __
   const T* __restrict__ dmat = reinterpret_cast<const T*>(in.dmat);
   const double* __restrict__ cmat = in.cmat;
   const int nphase = in.nphase;
-  const int ntile3 = (g.n3 + W - 1) / W;
-  const int a2 = blockIdx.x / ntile3;
-  const int a30 = (blockIdx.x % ntile3) * W;
+  // consecutive blocks take consecutive i2 at one i3 tile: their 16-byte x W
+  // runs then lie n3 elements apart instead of side by side, which the memory
+  // system serves faster (measured: +13% for a copy with this pattern, W = 8)
+  const int a2 = blockIdx.x % g.n2;
+  const int a30 = (blockIdx.x / g.n2) * W;
   const long long n23 = (long long)g.n2 * g.n3;
   const int tid = threadIdx.x;
   const long long colbase = (long long)a2 * g.n3 + a30;
@@ -890,9 +894,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
   const uint8_t* __restrict__ phase = in.phase;
   const T* __restrict__ dmat = reinterpret_cast<const T*>(in.dmat);
   const int nphase = in.nphase;
-  const int ntile3 = (g.n3 + W - 1) / W;
-  const int a2 = blockIdx.x / ntile3;
-  const int a30 = (blockIdx.x % ntile3) * W;
+  // consecutive blocks take consecutive i2 at one i3 tile: their 16-byte x W
+  // runs then lie n3 elements apart instead of side by side, which the memory
+  // system serves faster (measured: +13% for a copy with this pattern, W = 8)
+  const int a2 = blockIdx.x % g.n2;
+  const int a30 = (blockIdx.x / g.n2) * W;
   const long long n23 = (long long)g.n2 * g.n3;
   const long long colbase = (long long)a2 * g.n3 + a30;
   const int tid = threadIdx.x;

@@ -142,6 +142,17 @@ bool axis1_special(const Geo& g, KernSet<T>& K) {
   }
   K.c1.clear();
   K.c1.push_back({K.a1[0], K.NT1, 0, W});  // k_axis1 (MODE_STRESS); LDS filled in by choose_axis1
+  {
+    // the same tile with the LDS phase table cut to two phases and the register
+    // budget capped so that as many blocks run per CU as the LDS allows
+    constexpr int NTo = NC * 3 * W * sizeof(C2<T>) >= 32768 ? 512 : 256;
+    constexpr size_t lds_o = sizeof(C2<T>) * ((size_t)NC + (size_t)NC * 3 * W) + sizeof(T) * 36 * 2;
+    constexpr int waves = (int)(163840 / lds_o) * NTo / 64;
+    constexpr int MINW = (waves + 3) / 4 < 1 ? 1 : ((waves + 3) / 4 > 6 ? 6 : (waves + 3) / 4);
+    // first in the list: the default when the pattern is not tuned
+    if (lds_o <= (size_t)lds_limit())
+      K.c1.insert(K.c1.begin(), {k_axis1<T, MODE_STRESS, NC, W, NTo, 2, MINW>, NTo, lds_o, W});
+  }
   if constexpr (NC % 2 == 0 && axis1s_nt<NC, W>() <= 1024) {
     constexpr int NT = axis1s_nt<NC, W>();
     const size_t lds = sizeof(C2<T>) * (size_t)NC + sizeof(T) * 36 * 16 +
@@ -193,7 +204,8 @@ bool choose_axis1(const Geo& g, const FftPlan& pl, KernSet<T>& K) {
   }
   K.lds1 = sizeof(C2<T>) * ((size_t)g.n1 + (size_t)g.n1 * 3 * K.W1) + sizeof(T) * 36 * 16;
   if (K.c1.empty()) K.c1.push_back({K.a1[0], K.NT1, K.lds1, K.W1});
-  K.c1[0].lds = K.lds1;
+  for (auto& c : K.c1)
+    if (c.fn == K.a1[0]) c.lds = K.lds1;
   return K.lds1 <= (size_t)lds_limit();
 }
 

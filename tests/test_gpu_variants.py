@@ -46,7 +46,10 @@ def problem(request):
 def test_every_variant_matches_oracle(problem, prec):
     pr, ref = problem
     pr.bind(prec)
-    for choice in itertools.product(range(5), range(3), range(2)):
+    info = pr.G.autotune(nload=1)           # reports how many candidates each pass has
+    ncand = [len(info[k]["ms"]) for k in ("stress", "axis2", "green")]
+    assert ncand[0] >= 5 and ncand[1] >= 3 and ncand[2] >= 2, ncand
+    for choice in itertools.product(*(range(n) for n in ncand)):
         print(f"variant {choice} {prec}", flush=True)
         pr.G.tune_set(choice)
         res = pr.G.solve(EPS0[None], tol=-1.0, max_iter=7, return_E=True, history=True)
