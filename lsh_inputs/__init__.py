@@ -31,6 +31,27 @@ def isotropic_voigt(E, nu):
     return C
 
 
+def isotropic_voigt_plane(E, nu):
+    """3x3 Voigt stiffness (order 11, 22, 12; tensor components) of an isotropic
+    material in plane strain: the in-plane block of the three-dimensional one."""
+    return isotropic_voigt(E, nu)[np.ix_([0, 1, 5], [0, 1, 5])]
+
+
+def confocal_ellipses_phase(points, c=(0.05, 0.35), rho=0.09, angle_deg=60.0):
+    """Two confocal ellipses x1^2/(c1^2 + r) + x2^2/(c2^2 + r) = 1, r = 0 (core)
+    and r = rho (coating), rotated by angle_deg about the cell centre, in the
+    periodic cell [-1/2, 1/2)^2: phase 0 core, 1 coating, 2 matrix."""
+    y = np.asarray(points, dtype=np.float64)
+    y = y - np.round(y)
+    t = np.deg2rad(angle_deg)
+    # coordinates in the frame of the unrotated ellipses
+    u = np.cos(t) * y[:, 0] + np.sin(t) * y[:, 1]
+    v = -np.sin(t) * y[:, 0] + np.cos(t) * y[:, 1]
+    inner = u ** 2 / c[0] ** 2 + v ** 2 / c[1] ** 2 <= 1.0
+    outer = u ** 2 / (c[0] ** 2 + rho) + v ** 2 / (c[1] ** 2 + rho) <= 1.0
+    return np.where(inner, 0, np.where(outer, 1, 2)).astype(np.uint8)
+
+
 def mean_reference(C_phases):
     """Reference stiffness C0 = arithmetic mean of the phase stiffnesses."""
     return np.mean(np.asarray(C_phases, dtype=np.float64), axis=0)

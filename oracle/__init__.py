@@ -16,6 +16,8 @@ green     stiffness tensors, the Green operator of Def. (projection), the
           operator of Def. (gamma_tilde_fourier).
 scheme    the Basic Scheme fixed point for eq. (pde_coefficients) (Sec. 4),
           the effective stress and a dense direct solve of the same system.
+plane     the same chain in two dimensions (2x2 patterns, plane strain,
+          3-component Mandel fields), the setting of the numerics of Sec. 4.
 
 Every function cites the passage it follows.  All floating point is float64.
 The Box-spline alias sum truncation is the one fixed in Sec. 4.2 (a box of
