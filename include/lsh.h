@@ -25,6 +25,12 @@
  *  - Real-space device fields are laid out [load][component][a1][a2][a3] with
  *    a = (a1, a2, a3) the SNF grid index of the point (lsh_pattern_points),
  *    a3 fastest.
+ *  - Two-dimensional patterns (d = 2, the setting of the numerics of Sec. 4):
+ *    strains, stresses and stiffness matrices are 2-D Voigt, order (11, 22, 12)
+ *    (3 entries per strain or stress, 3x3 per stiffness), in plane strain.  The
+ *    library holds such a pattern as the three-dimensional blockdiag(M, 1), whose
+ *    frequencies all have k3 = 0; every 3-entry array below takes the place of
+ *    the 6-entry one, and device fields carry 3 components.
  */
 #ifndef LSH_H
 #define LSH_H
@@ -80,22 +86,24 @@ typedef struct {
  * by a in Z_e1 x Z_e2 x Z_e3 (y = M^{-1} U a mod 1) and G(M^T) by b
  * (h = V^T b mod M^T); the pattern DFT of eq. (Fouriermatrix) is then the
  * plain 3-D DFT over that grid.
- *   d      : must be 3 (the GPU path is three-dimensional).
+ *   d      : 3, or 2 for a pattern of the plane (held as blockdiag(M, 1): its
+ *            SNF has e1 = 1 and its points have y3 = 0).
  *   M      : d*d integers, row-major.
  *   out    : receives a new pattern; release with lsh_destroy.
- * Errors: LSH_EINVAL (d != 3, null), LSH_ESINGULAR (det M == 0),
+ * Errors: LSH_EINVAL (d not 2 or 3, null), LSH_ESINGULAR (det M == 0),
  *         LSH_EUNSUPPORTED (|det M| beyond int32 grid limits).                     */
 int lsh_create_pattern(int d, const int64_t *M, lsh_pattern **out);
 void lsh_destroy(lsh_pattern *p);
 
-/* m = |det M| and the SNF diagonal e (e1 | e2 | e3).                               */
+/* m = |det M| and the SNF diagonal e (e1 | e2 | e3) of the three-dimensional
+ * pattern the library holds (for d = 2 that of blockdiag(M, 1)).                 */
 int lsh_pattern_info(const lsh_pattern *p, int64_t *m, int64_t e[3]);
 
 /* The unimodular SNF factors, M = U diag(e) V, each 3x3 row-major.                */
 int lsh_pattern_snf(const lsh_pattern *p, int64_t U[9], int64_t V[9]);
 
-/* The points of P(M) in storage order: y = y_num / m, y in [-1/2,1/2)^3 exactly.
- *   y_num : host int64 array of m*3 entries, caller-allocated.                    */
+/* The points of P(M) in storage order: y = y_num / m, y in [-1/2,1/2)^d exactly.
+ *   y_num : host int64 array of m*d entries, caller-allocated.                    */
 int lsh_pattern_points(const lsh_pattern *p, int64_t *y_num);
 
 /* -------------------------------------------------------- generating function ---
@@ -104,11 +112,12 @@ int lsh_pattern_points(const lsh_pattern *p, int64_t *y_num);
  * orthonormalised translates (Lemma (FI:Props) c):
  *   Gamma^p_h = sum_z g(x+z)^2 Gamma0_{h+M^T z} / sum_z g(x+z)^2,  x = M^{-T} h.
  *   LSH_DIRICHLET, LSH_DIRICHLET_MODIFIED : nparams = 0.
- *   LSH_DLVP      : params = alpha[3], each in (0, 1], the trapezoid of Sec. 2.2
+ *   LSH_DLVP      : params = alpha[d], each in [0, 1], the trapezoid of Sec. 2.2
  *                   (g_alpha = B_Xi, Xi = (diag alpha, I); alpha = 1 is Fejer).
- *   LSH_BOXSPLINE : params = {s, Xi[3*s] (columns, pattern coordinates, row-major
- *                   3 x s), R}; the alias sum runs over z in [-R,R]^3
- *                   (Sec. 4.2 truncates the bracket sums to a box of terms).
+ *   LSH_BOXSPLINE : params = {s, Xi[d*s] (columns, pattern coordinates, row-major
+ *                   d x s, spanning R^d), R}; the alias sum runs over z in
+ *                   [-R,R]^d (Sec. 4.2 truncates the bracket sums to a box of
+ *                   terms).  s <= 16 (d = 3), <= 15 (d = 2).
  * Host only.  Errors: LSH_EINVAL (kind, parameter count or range).               */
 int lsh_set_kernel(lsh_pattern *p, lsh_kernel kind, const double *params, int nparams);
 
@@ -116,9 +125,14 @@ int lsh_set_kernel(lsh_pattern *p, lsh_kernel kind, const double *params, int np
  * The piecewise-constant stiffness C(y) (Def. (weak_pde)) and the reference C0
  * of the Green operator (Def. (projection)).
  *   nphase   : 1..256 phases.
- *   C_voigt  : nphase*36 doubles, Voigt 6x6 per phase (row-major).
- *   C0_voigt : 36 doubles.
+ *   C_voigt  : nphase*36 doubles, Voigt 6x6 per phase (row-major); d = 2:
+ *              nphase*9, Voigt 3x3 (11, 22, 12).
+ *   C0_voigt : 36 doubles (d = 2: 9).
  *   phase    : m bytes, phase index of each point in storage order.
+ * d = 2: the 3x3 matrices are the in-plane blocks of plane-strain tensors; the
+ * library completes them with out-of-plane entries shared by C0 and every
+ * phase (those of the isotropic tensor with C0's Lame constants when C0 is
+ * isotropic), so C - C0 acts in the plane only.
  * Host only (copied).  Errors: LSH_EINVAL, LSH_ENOTELLIPTIC (a matrix not SPD).  */
 int lsh_set_stiffness(lsh_pattern *p, int nphase, const double *C_voigt,
                       const double *C0_voigt, const uint8_t *phase);
@@ -153,7 +167,9 @@ int lsh_bind(lsh_pattern *p, lsh_precision prec, void *dev_persistent, size_t by
 /* Evaluates the (Hermitian-symmetrised) Gamma^p at n frequency bins b
  * (3 ints each, 0 <= b1 <= e1/2, 0 <= b2 < e2, 0 <= b3 < e3) with the same
  * device code the solver uses; writes 21 doubles per bin (upper triangle of
- * the 6x6 Mandel matrix, row by row).  dev_scratch: >= n*(24+21*8) bytes.
+ * the 6x6 Mandel matrix, row by row).  For d = 2 the bins and the matrix are
+ * those of the three-dimensional pattern held (its in-plane block is the 2-D
+ * operator).  dev_scratch: >= n*(24+21*8) bytes.
  * Synchronises `stream`.  For tests and diagnostics.                            */
 int lsh_gamma_probe(const lsh_pattern *p, lsh_precision prec, const int64_t *bins, int n,
                     double *out, void *dev_scratch, size_t scratch_bytes, void *stream);
@@ -169,14 +185,16 @@ int lsh_solve_bytes(const lsh_pattern *p, int nload, lsh_precision prec, size_t 
  *   all points; relative Cauchy criterion of Sec. 4).
  * Load cases run side by side and stop independently.
  *   nload        : 1..64 load cases.
- *   eps0_voigt   : host nload*6 macroscopic strains (Voigt, engineering shear).
+ *   eps0_voigt   : host nload*6 macroscopic strains (Voigt, engineering shear);
+ *                  nload*3 for d = 2 (as every per-load 6 below).
  *   tol          : Cauchy tolerance; tol < 0 runs exactly max_iter iterations
  *                  (fixed-count mode, returns LSH_OK).
  *   max_iter     : iteration limit, >= 1.
  *   dev_workspace: >= lsh_solve_bytes(...) bytes.
  *   dev_E_init   : optional device double [nload][6][m] start fluctuation (Voigt,
- *                  engineering shear) or NULL for zero.
- *   dev_E_out    : optional device double [nload][6][m] receiving the final E.
+ *                  engineering shear) or NULL for zero; [nload][3][m] for d = 2.
+ *   dev_E_out    : optional device double [nload][6][m] receiving the final E
+ *                  ([nload][3][m] for d = 2).
  *   sigma_out    : host nload*6: sigma_bar = (1/m) sum_y C(y):(E_y + eps0)
  *                  (Voigt stress) at the final iterate (Sec. 3.1, C^eff : eps0).
  *   stats        : optional host nload entries.
@@ -227,7 +245,8 @@ int lsh_tune_set(lsh_pattern *p, lsh_precision prec, const int *choice);
  *                isotropic (the Green operator is evaluated per instance) or all
  *                share the same C0.
  *   nload      : load cases of this task (>= 1).
- *   eps0_voigt : host nload*6 macroscopic strains; sigma_out host nload*6.
+ *   eps0_voigt : host nload*6 macroscopic strains; sigma_out host nload*6
+ *                (nload*3 each for d = 2; tasks of 2-D and 3-D patterns may mix).
  *   stats      : optional host nload entries.
  * No start field and no field output in batch mode.                               */
 typedef struct {

@@ -22,7 +22,7 @@ struct GreenParams {
   int kind;          // lsh_kernel
   int nxi;           // Box spline: number of directions
   int R;             // Box spline: alias box [-R, R]^3
-  int pad_;
+  int flat3;         // two-dimensional pattern: the third axis carries no aliases
   int64_t m;         // |det M|
   int64_t e[3];      // SNF diagonal
   int64_t VT[9];     // h = V^T b
@@ -141,7 +141,8 @@ __device__ inline double kernel_weight(const GreenParams& gp, const double x[3])
 
 // Weighted alias sum for the representative h_rep (x_num its M^{-T} numerator):
 // acc = sum_z w Gamma0, returns sum_z w.  z over {-1,0,1}^3 (modified
-// Dirichlet, dlVP), {0} (Dirichlet) or [-R,R]^3 (Box).
+// Dirichlet, dlVP), {0} (Dirichlet) or [-R,R]^3 (Box); z3 = 0 only for a
+// two-dimensional pattern (its third weight factor vanishes at every z3 != 0).
 __device__ inline double alias_sum(const GreenParams& gp, const int64_t hr[3], const int64_t xn[3], double acc[21]) {
   for (int t = 0; t < 21; ++t) acc[t] = 0.0;
   const double invm = 1.0 / (double)gp.m;
@@ -149,10 +150,11 @@ __device__ inline double alias_sum(const GreenParams& gp, const int64_t hr[3], c
   int r = 0;
   if (gp.kind == 1 || gp.kind == 2) r = 1;
   if (gp.kind == 3) r = gp.R;
+  const int r2 = gp.flat3 ? 0 : r;
   double den = 0.0;
   for (int z0 = -r; z0 <= r; ++z0)
     for (int z1 = -r; z1 <= r; ++z1)
-      for (int z2 = -r; z2 <= r; ++z2) {
+      for (int z2 = -r2; z2 <= r2; ++z2) {
         const double x[3] = {x0[0] + z0, x0[1] + z1, x0[2] + z2};
         const double w = kernel_weight(gp, x);
         if (w <= 0.0) continue;

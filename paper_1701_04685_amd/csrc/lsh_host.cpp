@@ -213,6 +213,7 @@ static int check_stiffness(const double* Cv, const char* what) {
 void lsh_green_params(const lsh_pattern* p, GreenParams* gp) {
   memset(gp, 0, sizeof(*gp));
   gp->kind = p->kind;
+  gp->flat3 = p->d == 2 ? 1 : 0;
   gp->nxi = p->nxi;
   gp->R = p->R;
   gp->m = p->m;
@@ -230,16 +231,25 @@ void lsh_green_params(const lsh_pattern* p, GreenParams* gp) {
 }
 
 // ------------------------------------------------------------------ the ABI
-extern "C" int lsh_create_pattern(int d, const int64_t* M, lsh_pattern** out) {
-  if (!out || !M) return lsh_fail(LSH_EINVAL, "null argument");
+extern "C" int lsh_create_pattern(int d, const int64_t* Md, lsh_pattern** out) {
+  if (!out || !Md) return lsh_fail(LSH_EINVAL, "null argument");
   *out = nullptr;
-  if (d != 3) return lsh_fail(LSH_EINVAL, "only d = 3 is supported");
+  if (d != 2 && d != 3) return lsh_fail(LSH_EINVAL, "d must be 2 or 3");
+  // d = 2: M = blockdiag(M2, 1) (a single point along the third axis)
+  int64_t M[9];
+  if (d == 3) {
+    memcpy(M, Md, sizeof(M));
+  } else {
+    const int64_t E[9] = {Md[0], Md[1], 0, Md[2], Md[3], 0, 0, 0, 1};
+    memcpy(M, E, sizeof(M));
+  }
   for (int i = 0; i < 9; ++i)
     if (std::llabs(M[i]) > (1 << 20)) return lsh_fail(LSH_EUNSUPPORTED, "entries of M beyond 2^20");
   const int64_t det = det3(M);
   if (det == 0) return lsh_fail(LSH_ESINGULAR, "det M == 0: the pattern needs a regular matrix");
   if (std::llabs(det) > ((int64_t)1 << 31)) return lsh_fail(LSH_EUNSUPPORTED, "|det M| beyond 2^31 points");
   lsh_pattern* p = new lsh_pattern();
+  p->d = d;
   memcpy(p->M, M, sizeof(p->M));
   p->det = det;
   p->m = std::llabs(det);
@@ -300,7 +310,8 @@ extern "C" int lsh_pattern_points(const lsh_pattern* p, int64_t* y) {
           __int128 v = (__int128)T[3 * i] * a0 + (__int128)T[3 * i + 1] * a1 + (__int128)T[3 * i + 2] * a2;
           int64_t r = (int64_t)((v + h) % m);
           if (r < 0) r += m;
-          y[3 * idx + i] = r - h;
+          // d = 2: the third coordinate is 0 for every point and is not returned
+          if (i < p->d) y[p->d * idx + i] = r - h;
         }
   return LSH_OK;
 }
@@ -317,31 +328,35 @@ extern "C" int lsh_set_kernel(lsh_pattern* p, lsh_kernel kind, const double* par
       if (nparams != 0) return lsh_fail(LSH_EINVAL, "Dirichlet kernels take no parameters");
       break;
     case LSH_DLVP:
-      if (nparams != 3) return lsh_fail(LSH_EINVAL, "dlVP needs alpha[3]");
-      for (int i = 0; i < 3; ++i)
+      if (nparams != p->d) return lsh_fail(LSH_EINVAL, "dlVP needs alpha[d]");
+      for (int i = 0; i < nparams; ++i)
         if (!(params[i] >= 0.0 && params[i] <= 1.0)) return lsh_fail(LSH_EINVAL, "dlVP alpha must lie in [0, 1]");
-      for (int i = 0; i < 3; ++i) p->alpha[i] = params[i];
+      for (int i = 0; i < 3; ++i) p->alpha[i] = i < nparams ? params[i] : 0.5;  // d = 2: the third factor is 1 at x3 = 0
       break;
     case LSH_BOXSPLINE: {
-      if (nparams < 1) return lsh_fail(LSH_EINVAL, "Box spline needs {s, Xi[3 s], R}");
+      const int d = p->d;
+      if (nparams < 1) return lsh_fail(LSH_EINVAL, "Box spline needs {s, Xi[d s], R}");
       const int s = (int)params[0];
-      if (s < 3 || s > LSH_MAX_XI || (double)s != params[0])
-        return lsh_fail(LSH_EINVAL, "Box spline: s must be an integer in [3, 16]");
-      if (nparams != 1 + 3 * s && nparams != 2 + 3 * s) return lsh_fail(LSH_EINVAL, "Box spline: expected 1 + 3 s (+1) parameters");
+      // d = 2 appends the direction e3 (its factor vanishes at every alias z3 != 0)
+      if (s < d || s + (3 - d) > LSH_MAX_XI || (double)s != params[0])
+        return lsh_fail(LSH_EINVAL, "Box spline: s must be an integer in [d, 16 - (3 - d)]");
+      if (nparams != 1 + d * s && nparams != 2 + d * s) return lsh_fail(LSH_EINVAL, "Box spline: expected 1 + d s (+1) parameters");
       double XiXt[9] = {0};
       memset(p->Xi, 0, sizeof(p->Xi));
       for (int c = 0; c < s; ++c)
-        for (int i = 0; i < 3; ++i) p->Xi[3 * c + i] = params[1 + i * s + c];
+        for (int i = 0; i < d; ++i) p->Xi[3 * c + i] = params[1 + i * s + c];
+      if (d == 2) p->Xi[3 * s + 2] = 1.0;
+      const int sx = s + (3 - d);
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
-          for (int c = 0; c < s; ++c) XiXt[3 * i + j] += p->Xi[3 * c + i] * p->Xi[3 * c + j];
+          for (int c = 0; c < sx; ++c) XiXt[3 * i + j] += p->Xi[3 * c + i] * p->Xi[3 * c + j];
       const double dd = XiXt[0] * (XiXt[4] * XiXt[8] - XiXt[5] * XiXt[7]) - XiXt[1] * (XiXt[3] * XiXt[8] - XiXt[5] * XiXt[6]) +
                         XiXt[2] * (XiXt[3] * XiXt[7] - XiXt[4] * XiXt[6]);
-      if (!(dd > 1e-12)) return lsh_fail(LSH_EINVAL, "Box spline directions must span R^3 (Sec. 2.2)");
-      p->nxi = s;
+      if (!(dd > 1e-12)) return lsh_fail(LSH_EINVAL, "Box spline directions must span R^d (Sec. 2.2)");
+      p->nxi = sx;
       p->R = 16;
-      if (nparams == 2 + 3 * s) {
-        const double r = params[1 + 3 * s];
+      if (nparams == 2 + d * s) {
+        const double r = params[1 + d * s];
         if (!(r >= 0 && r <= 64) || (double)(int)r != r) return lsh_fail(LSH_EINVAL, "Box spline: R must be an integer in [0, 64]");
         p->R = (int)r;
       }
@@ -365,10 +380,85 @@ extern "C" int lsh_set_scheme(lsh_pattern* p, lsh_scheme scheme) {
   return LSH_OK;
 }
 
+// d = 2: 3x3 Voigt matrices (11, 22, 12), symmetric positive definite in Mandel form.
+static int check_stiffness_plane(const double* Cv, const char* what) {
+  double mx = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    if (!std::isfinite(Cv[i])) return lsh_fail(LSH_EINVAL, std::string(what) + " has a non-finite entry");
+    mx = std::max(mx, fabs(Cv[i]));
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < i; ++j)
+      if (fabs(Cv[3 * i + j] - Cv[3 * j + i]) > 1e-12 * mx)
+        return lsh_fail(LSH_ENOTELLIPTIC, std::string(what) + " is not symmetric (major symmetry)");
+  const double w[3] = {1.0, 1.0, M_SQRT2};
+  double A[9];
+  for (int i = 0; i < 9; ++i) A[i] = Cv[i] * w[i / 3] * w[i % 3];
+  // leading principal minors of the Mandel matrix
+  const double d1 = A[0], d2 = A[0] * A[4] - A[1] * A[3];
+  const double d3 = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                    A[2] * (A[3] * A[7] - A[4] * A[6]);
+  if (!(d1 > 0.0 && d2 > 0.0 && d3 > 0.0))
+    return lsh_fail(LSH_ENOTELLIPTIC, std::string(what) + " is not positive definite");
+  return LSH_OK;
+}
+
+// d = 2 (plane strain): a 3x3 Voigt matrix becomes the 6x6 one whose in-plane
+// block (Voigt rows and columns 11, 22, 12) it is and whose other entries are
+// those of a template T shared by C0 and every phase, so that C - C0 vanishes
+// outside the in-plane block and the 33 and anti-plane strains stay zero.  For
+// an isotropic C0 the template is the three-dimensional isotropic tensor with
+// C0's Lame constants (the solver then uses its isotropic Green operator);
+// otherwise it has no couplings and diagonal (C11 + C22)/2, C66, C66.
+static void plane_template(const double* C02, double* T) {
+  for (int i = 0; i < 36; ++i) T[i] = 0.0;
+  double mx = 0.0;
+  for (int i = 0; i < 9; ++i) mx = std::max(mx, fabs(C02[i]));
+  const double c11 = C02[0], c12 = C02[1], c16 = C02[2], c22 = C02[4], c26 = C02[5], c66 = C02[8];
+  const double tol = 1e-13 * mx;
+  const bool iso = fabs(c11 - c22) <= tol && fabs(c16) <= tol && fabs(c26) <= tol &&
+                   fabs(c66 - 0.5 * (c11 - c12)) <= tol;
+  if (iso) {
+    const double lam = c12, mu = c66;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) T[6 * i + j] = lam + (i == j ? 2.0 * mu : 0.0);
+    T[21] = T[28] = T[35] = mu;
+  } else {
+    T[14] = 0.5 * (c11 + c22);
+    T[21] = T[28] = c66;
+  }
+}
+
+static void embed_plane(const double* C2, const double* T, double* C6) {
+  static const int map[3] = {0, 1, 5};
+  for (int i = 0; i < 36; ++i) C6[i] = T[i];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C6[6 * map[i] + map[j]] = C2[3 * i + j];
+}
+
 extern "C" int lsh_set_stiffness(lsh_pattern* p, int nphase, const double* C_voigt, const double* C0_voigt,
                                  const uint8_t* phase) {
   if (!p || !C_voigt || !C0_voigt || !phase) return lsh_fail(LSH_EINVAL, "null argument");
   if (nphase < 1 || nphase > 256) return lsh_fail(LSH_EINVAL, "nphase must be in [1, 256]");
+  if (p->d == 2) {
+    for (int q = 0; q < nphase; ++q) {
+      int st = check_stiffness_plane(C_voigt + 9 * q, "phase stiffness");
+      if (st) return st;
+    }
+    int st = check_stiffness_plane(C0_voigt, "reference stiffness C0");
+    if (st) return st;
+    for (int64_t i = 0; i < p->m; ++i)
+      if (phase[i] >= nphase) return lsh_fail(LSH_EINVAL, "phase index out of range");
+    double T[36];
+    plane_template(C0_voigt, T);
+    p->nphase = nphase;
+    p->C_voigt.assign(36 * (size_t)nphase, 0.0);
+    for (int q = 0; q < nphase; ++q) embed_plane(C_voigt + 9 * q, T, p->C_voigt.data() + 36 * q);
+    embed_plane(C0_voigt, T, p->C0_voigt);
+    p->phase.assign(phase, phase + p->m);
+    p->bound_prec = -1;
+    return LSH_OK;
+  }
   for (int q = 0; q < nphase; ++q) {
     int st = check_stiffness(C_voigt + 36 * q, "phase stiffness");
     if (st) return st;

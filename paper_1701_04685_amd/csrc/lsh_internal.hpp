@@ -11,7 +11,10 @@
 #include "lsh_green.hpp"
 
 struct lsh_pattern {
-  // ---- Sec. 2.1: M, m, SNF M = U diag(e) V
+  // ---- Sec. 2.1: M, m, SNF M = U diag(e) V.  A two-dimensional pattern
+  // (d = 2) is held as M = blockdiag(M2, 1): its frequencies all have k3 = 0,
+  // so the three-dimensional operators act on it as their plane-strain forms.
+  int d = 3;
   int64_t M[9];
   int64_t det;
   int64_t m;

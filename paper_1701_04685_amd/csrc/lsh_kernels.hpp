@@ -28,7 +28,17 @@ struct Geo {
   int n1, n2, n3, h1;
   long long m;
   long long spec;  // h1 * n2 * n3 complex values per component and load
+  int ncf;         // components of the caller's real-space fields: 6, or 3 for d = 2
+  int pad_;
 };
+
+// Where component c (internal order 11, 22, 33, 23, 13, 12) sits in a
+// caller's field of ncf components: c itself for six, 11, 22, 12 -> 0, 1, 2
+// for the three of a two-dimensional pattern, -1 for a component that such a
+// field does not carry (it is zero there).
+__host__ __device__ inline int boundary_comp(int c, int ncf) {
+  return ncf == 6 ? c : (c < 2 ? c : (c == 5 ? 2 : -1));
+}
 
 template <typename T> using C2 = typename cpx<T>::t;
 
@@ -238,7 +248,8 @@ k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
       if (a30 + w < g.n3) {
         const long long pt = (long long)a1 * n23 + colbase + w;
         for (int c = 0; c < 6; ++c) {
-          const double v = Einit[((long long)(L * 6 + c)) * g.m + pt] * (c < 3 ? 1.0 : SQ2I);
+          const int bc = boundary_comp(c, g.ncf);
+          const double v = bc < 0 ? 0.0 : Einit[((long long)(L * g.ncf + bc)) * g.m + pt] * (c < 3 ? 1.0 : SQ2I);
           // the solver keeps X = D1[E] / n1 (D1: unnormalised DFT along axis 1)
           E[c] = (v - means[6 * L + c]) / (double)n1;
         }
@@ -266,7 +277,10 @@ k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
         acc[I] += s;
       }
       if (Eout)
-        for (int c = 0; c < 6; ++c) Eout[((long long)(L * 6 + c)) * g.m + pt] = E[c] * (c < 3 ? 1.0 : SQ2);
+        for (int c = 0; c < 6; ++c) {
+          const int bc = boundary_comp(c, g.ncf);
+          if (bc >= 0) Eout[((long long)(L * g.ncf + bc)) * g.m + pt] = E[c] * (c < 3 ? 1.0 : SQ2);
+        }
     }
     block_sum<6>(acc, partial + ((long long)L * gridDim.x + blockIdx.x) * 6);
     return;
@@ -1080,12 +1094,15 @@ __global__ void k_finalize_sum(const double* __restrict__ partial, int nblk, int
   if (threadIdx.x == 0) out[L * nv + i] = scale * o[0];
 }
 
-// mean of the Mandel components of a start field, per (load, comp) block
-__global__ void k_mean(const double* __restrict__ E, long long m, double* __restrict__ means) {
+// mean of the Mandel components of a start field (ncf components per load),
+// per (load, comp) block; components the field does not carry have mean 0
+__global__ void k_mean(const double* __restrict__ E, long long m, int ncf, double* __restrict__ means) {
   const int L = blockIdx.x, c = blockIdx.y;
   const double f = c < 3 ? 1.0 : 0.70710678118654752440;
+  const int bc = boundary_comp(c, ncf);
   double s[1] = {0.0};
-  for (long long i = threadIdx.x; i < m; i += blockDim.x) s[0] += E[((long long)(L * 6 + c)) * m + i];
+  if (bc >= 0)
+    for (long long i = threadIdx.x; i < m; i += blockDim.x) s[0] += E[((long long)(L * ncf + bc)) * m + i];
   double o[1];
   block_sum<1>(s, o);
   if (threadIdx.x == 0) means[6 * L + c] = f * o[0] / (double)m;

@@ -49,6 +49,8 @@ Geo geo_of(const lsh_pattern* p) {
   g.h1 = g.n1 / 2 + 1;
   g.m = p->m;
   g.spec = (long long)g.h1 * g.n2 * g.n3;
+  g.ncf = p->d == 2 ? 3 : 6;
+  g.pad_ = 0;
   return g;
 }
 
@@ -322,10 +324,14 @@ bool choose_green(const Geo& g, const FftPlan& pl, bool table, KernSet<T>& K) {
   if (!ok) {
     int nt = 64;
     while (nt < 256 && (nt < g.n3 || !plan_fits(pl, 6, nt))) nt *= 2;
+    // long lines (e.g. 1024, 2048) need more threads for their butterflies
+    while (nt < 1024 && !plan_fits(pl, 6, nt)) nt *= 2;
     if (!plan_fits(pl, 6, nt)) return false;
     if (nt == 64) K.gr = k_green<T, 0, 64>;
     else if (nt == 128) K.gr = k_green<T, 0, 128>;
-    else K.gr = k_green<T, 0, 256>;
+    else if (nt == 256) K.gr = k_green<T, 0, 256>;
+    else if (nt == 512) K.gr = k_green<T, 0, 512>;
+    else K.gr = k_green<T, 0, 1024>;
     K.NTG = nt;
   }
   (void)table;
@@ -768,7 +774,7 @@ int group_init(GroupRun<T>& G, int max_iter, const double* dev_E_init, hipStream
   const T2* tw0 = (const T2*)(base + p->off_tw[0]);
   const T2* tw1 = (const T2*)(base + p->off_tw[1]);
   if (dev_E_init) {
-    hipLaunchKernelGGL(k_mean, dim3(nload, 6), dim3(1024), 0, st, dev_E_init, (long long)G.g.m, G.w.means);
+    hipLaunchKernelGGL(k_mean, dim3(nload, 6), dim3(1024), 0, st, dev_E_init, (long long)G.g.m, G.g.ncf, G.w.means);
     hipLaunchKernelGGL(G.K.a1[MODE_INIT], G.gridS, dim3(G.K.NT1), G.K.lds1, st, G.g, p->plan[0], tw0,
                        (const T2*)nullptr, (T2*)G.w.X, (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0,
                        (const int*)G.w.stop_iter, (const int*)G.w.itp, dev_E_init, (const double*)G.w.means,
@@ -964,7 +970,10 @@ int group_finish(GroupRun<T>& G, int done, double tol, bool fixed, double secs, 
   if (g_prof.on) g_ev.flush();
   int status = LSH_OK;
   for (int L = 0; L < G.nload; ++L) {
-    for (int c = 0; c < 6; ++c) G.spec.sigma_out[L][c] = sig[6 * L + c] * (c < 3 ? 1.0 : M_SQRT1_2);
+    for (int c = 0; c < 6; ++c) {
+      const int bc = boundary_comp(c, G.g.ncf);
+      if (bc >= 0) G.spec.sigma_out[L][bc] = sig[6 * L + c] * (c < 3 ? 1.0 : M_SQRT1_2);
+    }
     const int its = std::min(G.stop[L], done);
     double last = NAN;
     if (its > 0) last = G.ring[((its - 1) % LSH_HIST) * G.nload + L];
@@ -1062,6 +1071,16 @@ int run_groups(std::vector<GroupRun<T>>& groups, double tol, int max_iter, const
   return status;
 }
 
+// The caller's macroscopic strain of load L (6 Voigt entries, or 3 for d = 2)
+// as the internal six-entry Voigt vector.
+void push_eps0(const lsh_pattern* p, const double* eps0_voigt, int L, std::vector<double>* out) {
+  const int nc = p->d == 2 ? 3 : 6;
+  for (int c = 0; c < 6; ++c) {
+    const int bc = boundary_comp(c, nc);
+    out->push_back(bc < 0 ? 0.0 : eps0_voigt[nc * L + bc]);
+  }
+}
+
 template <typename T>
 int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int max_iter, void* dev_ws,
             size_t ws_bytes, hipStream_t st, const double* dev_E_init, double* dev_E_out, double* sigma_out,
@@ -1072,8 +1091,8 @@ int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int
   S.inst = {p};
   for (int L = 0; L < nload; ++L) {
     S.inst_of.push_back(0);
-    for (int c = 0; c < 6; ++c) S.eps0_voigt.push_back(eps0_voigt[6 * L + c]);
-    S.sigma_out.push_back(sigma_out + 6 * L);
+    push_eps0(p, eps0_voigt, L, &S.eps0_voigt);
+    S.sigma_out.push_back(sigma_out + (p->d == 2 ? 3 : 6) * L);
     S.stats.push_back(stats ? stats + L : nullptr);
     S.history.push_back(history ? history + (long long)L * max_iter : nullptr);
   }
@@ -1085,6 +1104,7 @@ int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int
 
 // Batched solve: tasks grouped by SNF grid, M and generating function.
 bool same_group(const lsh_pattern* a, const lsh_pattern* b) {
+  if (a->d != b->d) return false;
   for (int i = 0; i < 9; ++i)
     if (a->M[i] != b->M[i]) return false;
   if (a->kind != b->kind || a->R != b->R || a->nxi != b->nxi || a->scheme != b->scheme) return false;
@@ -1106,7 +1126,7 @@ int build_groups(const lsh_task* tasks, int ntask, int max_iter, std::vector<Gro
   for (int t = 0; t < ntask; ++t) {
     const lsh_task& tk = tasks[t];
     if (!tk.p || !tk.eps0_voigt || !tk.sigma_out || tk.nload < 1) return lsh_fail(LSH_EINVAL, "bad task " + std::to_string(t));
-    for (int i = 0; i < 6 * tk.nload; ++i)
+    for (int i = 0; i < (tk.p->d == 2 ? 3 : 6) * tk.nload; ++i)
       if (!std::isfinite(tk.eps0_voigt[i])) return lsh_fail(LSH_EINVAL, "non-finite macroscopic strain");
     size_t gi = 0;
     for (; gi < groups.size(); ++gi)
@@ -1120,8 +1140,8 @@ int build_groups(const lsh_task* tasks, int ntask, int max_iter, std::vector<Gro
     S.inst.push_back(tk.p);
     for (int L = 0; L < tk.nload; ++L) {
       S.inst_of.push_back(ii);
-      for (int c = 0; c < 6; ++c) S.eps0_voigt.push_back(tk.eps0_voigt[6 * L + c]);
-      S.sigma_out.push_back(tk.sigma_out + 6 * L);
+      push_eps0(tk.p, tk.eps0_voigt, L, &S.eps0_voigt);
+      S.sigma_out.push_back(tk.sigma_out + (tk.p->d == 2 ? 3 : 6) * L);
       S.stats.push_back(tk.stats ? tk.stats + L : nullptr);
       S.history.push_back(nullptr);
     }
@@ -1259,7 +1279,7 @@ extern "C" int lsh_solve(lsh_pattern* p, int nload, const double* eps0_voigt, do
   if (nload < 1 || nload > 64) return lsh_fail(LSH_EINVAL, "nload must be in [1, 64]");
   if (max_iter < 1) return lsh_fail(LSH_EINVAL, "max_iter must be >= 1");
   if (!(tol == tol)) return lsh_fail(LSH_EINVAL, "tol is NaN");
-  for (int i = 0; i < 6 * nload; ++i)
+  for (int i = 0; i < (p->d == 2 ? 3 : 6) * nload; ++i)
     if (!std::isfinite(eps0_voigt[i])) return lsh_fail(LSH_EINVAL, "non-finite macroscopic strain");
   if (p->kind < 0 || p->nphase < 1) return lsh_fail(LSH_ESTATE, "kernel or stiffness not set");
   if (p->bound_prec != (int)prec) return lsh_fail(LSH_ESTATE, "pattern not bound at this precision (lsh_bind)");

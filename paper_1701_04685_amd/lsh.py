@@ -166,9 +166,13 @@ class Pattern:
     """A pattern P(M) with its generating function, stiffness and device data."""
 
     def __init__(self, M):
-        M = np.ascontiguousarray(np.asarray(M, dtype=np.int64).reshape(3, 3))
+        M = np.asarray(M, dtype=np.int64)
+        d = int(M.shape[0]) if M.ndim == 2 else 3
+        M = np.ascontiguousarray(M.reshape(d, d))
         h = _P()
-        _check(_lib.lsh_create_pattern(3, M.ctypes.data_as(_I64P), ctypes.byref(h)))
+        _check(_lib.lsh_create_pattern(d, M.ctypes.data_as(_I64P), ctypes.byref(h)))
+        self.d = d
+        self.nc = 3 if d == 2 else 6   # strain / stress components (Voigt)
         self._h = h
         m = ctypes.c_int64()
         e = np.zeros(3, dtype=np.int64)
@@ -191,7 +195,7 @@ class Pattern:
         return U.reshape(3, 3), V.reshape(3, 3)
 
     def point_numerators(self):
-        y = np.zeros((self.m, 3), dtype=np.int64)
+        y = np.zeros((self.m, self.d), dtype=np.int64)
         _check(_lib.lsh_pattern_points(self._h, y.ctypes.data_as(_I64P)))
         return y
 
@@ -212,8 +216,9 @@ class Pattern:
         self._prec = None
 
     def set_stiffness(self, C_phases_voigt, C0_voigt, phase):
-        C = np.ascontiguousarray(np.asarray(C_phases_voigt, dtype=np.float64).reshape(-1, 6, 6))
-        C0 = np.ascontiguousarray(np.asarray(C0_voigt, dtype=np.float64).reshape(6, 6))
+        nc = self.nc
+        C = np.ascontiguousarray(np.asarray(C_phases_voigt, dtype=np.float64).reshape(-1, nc, nc))
+        C0 = np.ascontiguousarray(np.asarray(C0_voigt, dtype=np.float64).reshape(nc, nc))
         ph = np.ascontiguousarray(np.asarray(phase, dtype=np.uint8).reshape(-1))
         if ph.size != self.m:
             raise ValueError("phase map must have m entries")
@@ -280,18 +285,19 @@ class Pattern:
               workspace=None, allow_notconverged=False):
         """Basic Scheme for all load cases (rows of eps0_voigt)."""
         torch = _torch()
-        eps = np.ascontiguousarray(np.asarray(eps0_voigt, dtype=np.float64).reshape(-1, 6))
+        nc = self.nc
+        eps = np.ascontiguousarray(np.asarray(eps0_voigt, dtype=np.float64).reshape(-1, nc))
         nload = eps.shape[0]
         if self._prec is None:
             raise RuntimeError("call bind() first")
         need = self.workspace_bytes(nload)
         ws = workspace if workspace is not None and workspace.numel() >= need else _device_bytes(need)
-        Eout = torch.empty((nload, 6, self.m), dtype=torch.float64, device="cuda") if return_E else None
+        Eout = torch.empty((nload, nc, self.m), dtype=torch.float64, device="cuda") if return_E else None
         if E_init is not None:
-            if E_init.dtype != torch.float64 or not E_init.is_cuda or E_init.numel() != nload * 6 * self.m:
-                raise ValueError("E_init must be a cuda float64 tensor with nload*6*m entries")
+            if E_init.dtype != torch.float64 or not E_init.is_cuda or E_init.numel() != nload * nc * self.m:
+                raise ValueError(f"E_init must be a cuda float64 tensor with nload*{nc}*m entries")
             E_init = E_init.contiguous()
-        sig = np.zeros((nload, 6), dtype=np.float64)
+        sig = np.zeros((nload, nc), dtype=np.float64)
         stats = (Stats * nload)()
         hist = np.full((nload, max_iter), np.nan) if history else None
         S, sh = _solve_stream()
@@ -319,8 +325,9 @@ def solve_batch(patterns, eps0_list, tol=1e-6, max_iter=1000, precision="fp32", 
     """Solve many bound patterns at once (lsh_solve_batch).
 
     patterns: list of Pattern (bound at `precision`); eps0_list: per pattern an
-    (nload, 6) array of Voigt strains.  Returns per pattern a dict with sigma
-    (nload, 6), iterations, converged, residual, and the call's status.
+    (nload, nc) array of Voigt strains (nc = 6, or 3 for a 2-D pattern).
+    Returns per pattern a dict with sigma (nload, nc), iterations, converged,
+    residual, and the call's status.
     """
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     n = len(patterns)
@@ -328,7 +335,7 @@ def solve_batch(patterns, eps0_list, tol=1e-6, max_iter=1000, precision="fp32", 
     keep = []
     outs = []
     for i, (P, e) in enumerate(zip(patterns, eps0_list)):
-        e = np.ascontiguousarray(np.asarray(e, dtype=np.float64).reshape(-1, 6))
+        e = np.ascontiguousarray(np.asarray(e, dtype=np.float64).reshape(-1, P.nc))
         sig = np.zeros_like(e)
         st = (Stats * e.shape[0])()
         keep += [e, sig, st]

@@ -144,3 +144,51 @@ def test_unet_host_side(lib):
         assert so.lsh_unet_get_params(h, (ctypes.c_float * 1)(), None) == -10
     finally:
         so.lsh_unet_destroy(h)
+
+
+@pytest.mark.parametrize("M", [[[128, 0], [0, 128]], [[64, 64], [-64, 64]], [[128, 272], [0, 128]],
+                               [[5, 2], [1, 4]], [[-3, 1], [2, 6]]])
+def test_plane_pattern_matches_oracle(lib, M):
+    """d = 2 (Sec. 4's M1, M2, M3 and ragged ones): the library holds
+    blockdiag(M, 1) (SNF e1 = 1, U diag(e) V of that), and its 2-D point set is
+    the oracle's exactly."""
+    P = lib.Pattern(M)
+    O = OPattern(M)
+    assert P.d == 2 and P.nc == 3 and P.m == O.m
+    assert P.e[0] == 1 and list(P.e[1:]) == list(O.e)
+    U, V = P.snf()
+    M3 = np.zeros((3, 3), dtype=np.int64)
+    M3[:2, :2] = M
+    M3[2, 2] = 1
+    np.testing.assert_array_equal(U @ np.diag(P.e) @ V, M3)
+    y = P.point_numerators()
+    assert y.shape == (P.m, 2)
+    assert sorted(map(tuple, y.tolist())) == sorted(map(tuple, O.point_numerators().tolist()))
+
+
+def test_plane_errors_host_side(lib):
+    P = lib.Pattern([[8, 8], [-8, 8]])
+    with pytest.raises(lib.LshError) as e:
+        P.set_kernel("dlvp", {"alpha": [0.5, 0.5, 0.5]})     # alpha[d], d = 2
+    assert e.value.status == -1
+    with pytest.raises(lib.LshError) as e:
+        P.set_kernel("box", {"Xi": np.array([[1.0, 2.0, -1.0], [2.0, 4.0, -2.0]]), "R": 2})
+    assert e.value.status == -1                              # directions do not span R^2
+    P.set_kernel("box", {"Xi": np.array([[1, 0, 1, 0, 1, 0, 1, 0], [0, 1, 0, 1, 0, 1, 0, 1]], float), "R": 16})
+    P.set_kernel("dlvp", {"alpha": [0.9, 0.0]})
+    C = np.stack([li.isotropic_voigt_plane(1.0, 0.3), li.isotropic_voigt_plane(10.0, 0.3)])
+    C0 = li.mean_reference(C)
+    P.set_stiffness(C, C0, np.zeros(P.m, np.uint8))
+    bad = C.copy()
+    bad[1, 2, 2] = -0.5                                      # negative shear modulus
+    with pytest.raises(lib.LshError) as e:
+        P.set_stiffness(bad, C0, np.zeros(P.m, np.uint8))
+    assert e.value.status == -4
+    asym = C.copy()
+    asym[0, 0, 1] += 0.1
+    with pytest.raises(lib.LshError) as e:
+        P.set_stiffness(asym, C0, np.zeros(P.m, np.uint8))
+    assert e.value.status == -4
+    with pytest.raises(lib.LshError) as e:
+        lib.Pattern(np.diag([4, 4, 4, 4]))                   # d = 4
+    assert e.value.status == -1
