@@ -220,3 +220,84 @@ def variational_scheme(P: Pattern, Gamma, C_phases_voigt, C0_voigt, phase, eps0_
     sigma = np.einsum("yij,yj->i", C, E + eps0) / m
     return dict(E=E, sigma_voigt=green.mandel_stress_to_voigt(sigma), iterations=it,
                 history=np.array(history))
+
+
+def conjugate_gradient(P: Pattern, Gamma, C_phases_voigt, C0_voigt, phase, eps0_voigt,
+                       tol=1e-10, max_iter=1000, E_init=None, n_iter=None, trace=False):
+    """Conjugate gradients for the Dirichlet kernel's system (Sec. 1 names Krylov
+    solvers as the alternative to the fixed-point iteration).
+
+    For the Dirichlet kernel on a pattern without Nyquist faces (m odd: no bin
+    with x_i = -1/2) the operator G: v -> Re F^{-1}[Gamma^p_h F[v]_h] satisfies
+    G C0 G = G: G C0 projects onto the compatible fields (Def. (projection)),
+    and eq. (pde_coefficients) is equivalent to its variational form
+    (Remark (constants)): E compatible with G C (E + eps0) = 0.  On the
+    compatible fields v -> G C v is symmetric positive definite in the C0
+    inner product <a, C0 b>, so CG applies.  With the stress R = C(E + eps0)
+    the residual is z = -G R (a compatible strain, the step one fixed-point
+    iteration would take), and
+        rho = <z, C0 z>,  alpha = rho / <p, C p>,  E += alpha p,  R += alpha C p,
+        z = -G R,  beta = rho_new / rho,  p = z + beta p,
+    starting from p = z.  rho is taken as <z, C0 z> (a sum of non-negative
+    terms); the equal <R, G R> cancels: R is large and mostly in G's null space,
+    and its rounding stalls the iteration near the square root of the unit
+    roundoff.
+
+    Stopping rule: r_k = ||z_k|| / ||E_k + z_k + eps0|| <= tol, the Basic
+    Scheme's Cauchy residual one fixed-point step from E_k would show.
+    history[k] = r_k; `iterations` counts applications of G (the start's one
+    included), the unit of the fixed-point schemes.  n_iter runs exactly that
+    many.  trace=True also returns the directions p_k, stresses R_k and
+    residuals z_k (for the conjugacy pins).
+    """
+    m = P.m
+    C = stiffness_field(C_phases_voigt, phase)
+    C0 = green.voigt_stiffness_to_mandel(C0_voigt)
+    eps0 = green.voigt_strain_to_mandel(eps0_voigt)
+
+    def apply_G(v):
+        return -dft.pattern_idft(P, np.einsum("bij,bj->bi", Gamma, dft.pattern_dft(P, v))).real
+
+    def c0_norm2(v):
+        return float(np.sum(v * (v @ C0)))
+
+    if E_init is None:
+        E = np.zeros((m, 6))
+    else:
+        E = np.array(E_init, dtype=np.float64).reshape(m, 6)
+        E = E - E.mean(axis=0, keepdims=True)
+    R = np.einsum("yij,yj->yi", C, E + eps0)
+    z = apply_G(R)
+    rho = c0_norm2(z)
+    p = z.copy()
+    history = []
+    tr = {"p": [], "R": [], "z": []}
+    limit = n_iter if n_iter is not None else max_iter
+    it = 0
+    while it < limit:
+        r = np.sqrt(np.sum(z ** 2)) / np.sqrt(np.sum((E + z + eps0) ** 2))
+        history.append(r)
+        it += 1
+        if n_iter is None and r <= tol:
+            break
+        if it == limit:
+            break
+        q = np.einsum("yij,yj->yi", C, p)
+        pq = np.sum(p * q)
+        alpha = rho / pq if pq > 0 else 0.0
+        if trace:
+            tr["p"].append(p.copy())
+            tr["R"].append(R.copy())
+            tr["z"].append(z.copy())
+        E = E + alpha * p
+        R = R + alpha * q
+        z = apply_G(R)
+        rho_new = c0_norm2(z)
+        beta = rho_new / rho if rho > 0 else 0.0
+        rho = rho_new
+        p = z + beta * p
+    sigma = np.einsum("yij,yj->i", C, E + eps0) / m
+    out = dict(E=E, sigma_voigt=green.mandel_stress_to_voigt(sigma), iterations=it, history=np.array(history))
+    if trace:
+        out["trace"] = tr
+    return out

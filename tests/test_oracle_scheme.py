@@ -233,3 +233,85 @@ def test_variational_differs_from_ls_for_dlvp():
         d[kind] = np.abs(a - b).max() / np.abs(a).max()
     assert d["dirichlet"] < 1e-11
     assert d["dlvp"] > 1e-4
+
+
+# ---------------------------------------------------------------------------
+# conjugate gradients for the Dirichlet kernel (scheme.conjugate_gradient)
+# ---------------------------------------------------------------------------
+def _cg_problem(M, kind, params, contrast=20.0, seed=11):
+    P = Pattern(M)
+    rng = np.random.default_rng(seed)
+    ph = rng.integers(0, 2, size=P.m).astype(np.uint8)
+    Cp, C0 = two_phase(1.0, contrast, 0.3)
+    G, _ = green.gamma_periodised(P, C0, kind, params)
+    return P, ph, Cp, C0, G
+
+
+@pytest.mark.parametrize("M", [[[5, 1, 0], [0, 3, 0], [0, 0, 1]], [[3, 1, 0], [-1, 2, 1], [0, 1, 4]]])
+def test_cg_limit_equals_dense_solve(M):
+    """CG converges to the solution of eq. (pde_coefficients) assembled densely
+    from the Fourier matrix written out entry by entry (Dirichlet, m odd)."""
+    kind, params = "dirichlet", {}
+    P, ph, Cp, C0, G = _cg_problem(M, kind, params, 20.0, 4)
+    assert P.m % 2 == 1
+    eps0 = np.array([0.2, -0.1, 0.05, 0.3, 0.1, -0.2])
+    res = scheme.conjugate_gradient(P, G, Cp, C0, ph, eps0, tol=1e-14, max_iter=500)
+    Ynum = P.point_numerators()
+    by_point = {tuple(Fraction(int(v), P.m) for v in row): int(p) for row, p in zip(Ynum, ph)}
+    _, Ed = scheme.dense_fixed_point(M, C0, kind, params, Cp, by_point, eps0)
+    key = {tuple(Fraction(int(v), P.m) for v in row): i for i, row in enumerate(Ynum)}
+    from oracle.lattice import brute_force_points
+    order = [key[y] for y in brute_force_points(M)]
+    np.testing.assert_allclose(res["E"][order], Ed, atol=1e-11 * max(1, np.abs(Ed).max()))
+
+
+@pytest.mark.parametrize("M", [np.diag([5, 5, 7]), [[3, 1, 0], [-1, 2, 1], [0, 1, 4]]])
+def test_cg_limit_equals_basic_scheme_for_dirichlet(M):
+    """Without Nyquist faces (odd m) the Dirichlet operator G C0 is a projection
+    and the variational and Lippmann-Schwinger solutions coincide
+    (Remark (constants)); CG gets there with far fewer applications."""
+    P, ph, Cp, C0, G = _cg_problem(M, "dirichlet", {}, 100.0)
+    assert P.m % 2 == 1
+    eps0 = np.array([1.0, 0.0, 0.0, 0.0, 0.5, 0.0])
+    a = scheme.basic_scheme(P, G, Cp, C0, ph, eps0, tol=1e-13, max_iter=20000)
+    b = scheme.conjugate_gradient(P, G, Cp, C0, ph, eps0, tol=1e-13, max_iter=2000)
+    np.testing.assert_allclose(b["sigma_voigt"], a["sigma_voigt"], rtol=1e-10)
+    np.testing.assert_allclose(b["E"], a["E"], atol=1e-9)
+    assert b["iterations"] * 3 < a["iterations"]
+
+
+def test_cg_directions_conjugate_and_residuals_orthogonal():
+    """The defining properties of CG: directions conjugate in C, <p_i, C p_j> = 0,
+    and residuals C0-orthogonal, <z_i, C0 z_j> = 0 (equivalently <R_i, z_j> = 0),
+    for i != j (a wrong alpha or beta breaks both)."""
+    P, ph, Cp, C0, G = _cg_problem(np.diag([5, 5, 7]), "dirichlet", {}, 10.0)
+    res = scheme.conjugate_gradient(P, G, Cp, C0, ph, np.array([1.0, 0, 0, 0, 0, 0]), n_iter=7, trace=True)
+    C = scheme.stiffness_field(Cp, ph)
+    ps, Rs, zs = res["trace"]["p"], res["trace"]["R"], res["trace"]["z"]
+    assert len(ps) == 6
+    Cps = [np.einsum("yij,yj->yi", C, p) for p in ps]
+    for i in range(6):
+        for j in range(i):
+            pij = abs(np.sum(ps[i] * Cps[j])) / np.sqrt(np.sum(ps[i] * Cps[i]) * np.sum(ps[j] * Cps[j]))
+            rij = abs(np.sum(Rs[i] * zs[j])) / np.sqrt(abs(np.sum(Rs[i] * zs[i]) * np.sum(Rs[j] * zs[j])))
+            assert pij < 1e-8 and rij < 1e-8, (i, j, pij, rij)
+
+
+def test_cg_energy_error_decreases_and_finite_termination():
+    """CG minimises the C-energy of the error over growing Krylov spaces: the
+    energy error never grows, and on a tiny pattern (18 unknowns) the solution
+    is reached to rounding within 19 applications."""
+    P, ph, Cp, C0, G = _cg_problem(np.diag([5, 5, 5]), "dirichlet", {}, 10.0)
+    eps0 = np.array([0.3, 0.1, -0.2, 0.0, 0.4, 0.1])
+    ref = scheme.conjugate_gradient(P, G, Cp, C0, ph, eps0, tol=1e-15, max_iter=3000)
+    C = scheme.stiffness_field(Cp, ph)
+    errs = []
+    for n in range(1, 25):
+        Ek = scheme.conjugate_gradient(P, G, Cp, C0, ph, eps0, n_iter=n)["E"]
+        d = Ek - ref["E"]
+        errs.append(np.sum(d * np.einsum("yij,yj->yi", C, d)))
+    assert all(b <= a * (1 + 1e-9) + 1e-28 for a, b in zip(errs, errs[1:]))
+    Pt, pht, Cpt, C0t, Gt = _cg_problem([[3, 1, 0], [0, 1, 0], [0, 0, 1]], "dirichlet", {}, 50.0)
+    assert Pt.m == 3
+    r = scheme.conjugate_gradient(Pt, Gt, Cpt, C0t, pht, eps0, tol=1e-13, max_iter=100)
+    assert r["iterations"] <= 19 and r["history"][-1] <= 1e-13
