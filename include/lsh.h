@@ -144,9 +144,20 @@ int lsh_set_stiffness(lsh_pattern *p, int nphase, const double *C_voigt,
  *   LSH_SCHEME_VE: the variational form, eq. (pde_coefficients_variational),
  *     Thm. (ls_discretization), iterated in the strain-update form
  *       E <- E - Gamma^p[C:(E + eps0)].
- * The two coincide for the Dirichlet kernel (Remark (constants)).  Changing the
- * scheme drops the device binding (call lsh_bind again).  Errors: LSH_EINVAL.    */
-typedef enum { LSH_SCHEME_LS = 0, LSH_SCHEME_VE = 1 } lsh_scheme;
+ *   LSH_SCHEME_CG: conjugate gradients (the Krylov alternative named in Sec. 1)
+ *     for the Dirichlet kernel on a pattern of odd m (no Nyquist faces).  There
+ *     Gamma^p C0 projects onto the compatible strains, eq. (pde_coefficients) is
+ *     equivalent to the variational system, and that system is symmetric
+ *     positive definite in the C0 inner product.  Each iteration applies the
+ *     operator once (the fixed-point schemes' unit of work; the count includes
+ *     the start's application).  It stops on the Basic Scheme's Cauchy
+ *     residual one fixed-point step from the current iterate,
+ *     ||z|| / ||E + z + eps0|| with z = -Gamma^p C (E + eps0).  Same solution
+ *     as LSH_SCHEME_LS; lsh_solve only (lsh_solve_batch refuses it).
+ *     lsh_solve returns LSH_EUNSUPPORTED for other kernels or even m.
+ * LS and VE coincide for the Dirichlet kernel (Remark (constants)).  Changing
+ * the scheme drops the device binding (call lsh_bind again).  Errors: LSH_EINVAL. */
+typedef enum { LSH_SCHEME_LS = 0, LSH_SCHEME_VE = 1, LSH_SCHEME_CG = 2 } lsh_scheme;
 int lsh_set_scheme(lsh_pattern *p, lsh_scheme scheme);
 
 /* ------------------------------------------------------------- device binding ---

@@ -372,7 +372,8 @@ extern "C" int lsh_set_kernel(lsh_pattern* p, lsh_kernel kind, const double* par
 
 extern "C" int lsh_set_scheme(lsh_pattern* p, lsh_scheme scheme) {
   if (!p) return lsh_fail(LSH_EINVAL, "null pattern");
-  if (scheme != LSH_SCHEME_LS && scheme != LSH_SCHEME_VE) return lsh_fail(LSH_EINVAL, "unknown scheme");
+  if (scheme != LSH_SCHEME_LS && scheme != LSH_SCHEME_VE && scheme != LSH_SCHEME_CG)
+    return lsh_fail(LSH_EINVAL, "unknown scheme");
   if (p->scheme != (int)scheme) {
     p->scheme = (int)scheme;
     p->bound_prec = -1;  // the stress matrices on the device depend on the scheme

@@ -1108,6 +1108,198 @@ __global__ void k_mean(const double* __restrict__ E, long long m, int ncf, doubl
   if (threadIdx.x == 0) means[6 * L + c] = f * o[0] / (double)m;
 }
 
+// ------------------------------------------------- conjugate gradients ---
+// CG for the Dirichlet kernel's system (see lsh_set_scheme): the iterate x,
+// the residual z = -G C (x + eps0) (G C0 projects onto compatible strains),
+// the direction p and W = -G C p all live in the solver's axis-1 half
+// spectrum layout, where sums over the points follow from Parseval:
+// sum_y a(y) b(y) = n1 sum_{k1 <= n1/2} w(k1) Re(a_k conj(b_k)), w = 1 at
+// k1 = 0 and n1/2, else 2.  Per load the device keeps {rho, alpha, beta, -}.
+
+// x += alpha p, z += alpha W, and the partial sums of ||z||^2, ||x + z||^2 and
+// <z, C0 z> (Mandel C0, 36 doubles) over this block's spectrum slots.  One
+// thread per slot (k1, i2, i3) holds all six components.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_update(Geo g, const C2<T>* __restrict__ p, const C2<T>* __restrict__ Wv,
+                                                   C2<T>* __restrict__ x, C2<T>* __restrict__ z,
+                                                   const double* __restrict__ cg, const double* __restrict__ C0m,
+                                                   const int* __restrict__ stop_iter, const int* __restrict__ itp,
+                                                   double* __restrict__ partial) {
+  using T2 = C2<T>;
+  const int L = blockIdx.y;
+  if (*itp >= stop_iter[L]) return;  // uniform over the block
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const T a = (T)cg[4 * L + 1];
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (i < g.spec) {
+    const int k1 = (int)(i / ((long long)g.n2 * g.n3));
+    const double w = (k1 == 0 || 2 * k1 == g.n1) ? 1.0 : 2.0;
+    double zr[6], zi[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const long long o = ((long long)(L * 6 + c)) * g.spec + i;
+      const T2 pv = p[o], wv = Wv[o];
+      T2 xv = x[o], zv = z[o];
+      xv.x += a * pv.x;
+      xv.y += a * pv.y;
+      zv.x += a * wv.x;
+      zv.y += a * wv.y;
+      x[o] = xv;
+      z[o] = zv;
+      zr[c] = (double)zv.x;
+      zi[c] = (double)zv.y;
+      const double sx = (double)xv.x + zr[c], sy = (double)xv.y + zi[c];
+      acc[0] += w * (zr[c] * zr[c] + zi[c] * zi[c]);
+      acc[1] += w * (sx * sx + sy * sy);
+    }
+    double q = 0.0;
+#pragma unroll
+    for (int I = 0; I < 6; ++I)
+#pragma unroll
+      for (int J = 0; J < 6; ++J) q += C0m[6 * I + J] * (zr[I] * zr[J] + zi[I] * zi[J]);
+    acc[2] += w * q;
+  }
+  block_sum<3>(acc, partial + ((long long)L * gridDim.x + blockIdx.x) * 3);
+}
+
+// Residual of the current iterate (the Basic Scheme's Cauchy residual one
+// fixed-point step from x would show, ||z|| / ||x + z + eps0||), the stop test
+// and beta = rho_new / rho_old (0 at the first iteration).
+__global__ void k_cg_scalars(const double* __restrict__ partial, int nblk, int nload, const double* __restrict__ e0sq,
+                             double pscale, double tol, int fixed, const int* __restrict__ itp,
+                             int* __restrict__ stop_iter, double* __restrict__ hist, int* __restrict__ nonfinite,
+                             double* __restrict__ cg) {
+  const int L = blockIdx.x;
+  const int it = *itp;
+  if (it >= stop_iter[L]) return;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < nblk; j += blockDim.x)
+#pragma unroll
+    for (int v = 0; v < 3; ++v) s[v] += partial[((long long)L * nblk + j) * 3 + v];
+  double o[3];
+  block_sum<3>(s, o);
+  if (threadIdx.x == 0) {
+    const double zz = o[0] * pscale, xz = o[1] * pscale, rho = o[2] * pscale;
+    const double r = sqrt(zz / (xz + e0sq[L]));
+    hist[(it % LSH_HIST) * nload + L] = r;
+    if (!isfinite(r) || !isfinite(rho)) {
+      nonfinite[L] = 1;
+      stop_iter[L] = it + 1;
+    } else if (!fixed && r <= tol) {
+      stop_iter[L] = it + 1;
+    }
+    const double rho_old = cg[4 * L];
+    cg[4 * L + 2] = (it == 0 || !(rho_old > 0.0)) ? 0.0 : rho / rho_old;
+    cg[4 * L] = rho;
+  }
+}
+
+// alpha = rho / <p, C p> from the direction pass's partial sums.
+__global__ void k_cg_alpha(const double* __restrict__ partial, int nblk, const int* __restrict__ itp,
+                           const int* __restrict__ stop_iter, double* __restrict__ cg) {
+  const int L = blockIdx.x;
+  if (*itp >= stop_iter[L]) return;
+  double s[1] = {0.0};
+  for (int j = threadIdx.x; j < nblk; j += blockDim.x) s[0] += partial[(long long)L * nblk + j];
+  double o[1];
+  block_sum<1>(s, o);
+  if (threadIdx.x == 0) cg[4 * L + 1] = o[0] > 0.0 ? cg[4 * L] / o[0] : 0.0;
+}
+
+// The direction pass: p <- z + beta p in the half spectrum (written back), then
+// tau = C p at the points (no eps0: the operator's linear part) through the
+// axis-1 transforms of k_axis1 (runtime plan), stored as the axis-2 input, and
+// the partial sums of <p, C p> = sum_y p(y) . tau(y).  Block layout and LDS as
+// k_axis1 (twiddles, lines, the first 16 phases' C in LDS).
+template <typename T, int W, int NT>
+__global__ void __launch_bounds__(NT) k_cg_stress(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
+                                                  const C2<T>* __restrict__ z, C2<T>* __restrict__ p,
+                                                  C2<T>* __restrict__ tau, const Inst* __restrict__ insts,
+                                                  const int* __restrict__ inst_of, const double* __restrict__ cg,
+                                                  const int* __restrict__ stop_iter, const int* __restrict__ itp,
+                                                  double* __restrict__ partial) {
+  using T2 = C2<T>;
+  constexpr int W3 = 3 * W;
+  constexpr int NDL = 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n1 = g.n1;
+  const int h1 = n1 / 2 + 1;
+  T2* twl = reinterpret_cast<T2*>(smem_raw);
+  T2* Z = twl + n1;
+  T* Dl = reinterpret_cast<T*>(Z + n1 * W3);
+  const int L = blockIdx.y;
+  if (*itp >= stop_iter[L]) return;
+  const Inst& in = insts[inst_of[L]];
+  const uint8_t* __restrict__ phase = in.phase;
+  const T* __restrict__ dmat = reinterpret_cast<const T*>(in.dmat);
+  const int nphase = in.nphase;
+  const int a2 = blockIdx.x % g.n2;
+  const int a30 = (blockIdx.x / g.n2) * W;
+  const long long n23 = (long long)g.n2 * g.n3;
+  const long long colbase = (long long)a2 * g.n3 + a30;
+  const int tid = threadIdx.x;
+  const int npairs = h1 * W3;
+  const T beta = (T)cg[4 * L + 2];
+  stage_twiddles<T>(twl, tw, n1);
+  const int nd = nphase < NDL ? nphase : NDL;
+  for (int i = tid; i < 36 * nd; i += NT) Dl[i] = dmat[i];
+  // new direction, written back, and its Hermitian extension (pairs of real
+  // components share one complex line, as in k_axis1)
+  for (int idx = tid; idx < npairs; idx += NT) {
+    const int w = idx % W, q = (idx / W) % 3, k = idx / W3;
+    T2 a = T2{0, 0}, b = T2{0, 0};
+    if (a30 + w < g.n3) {
+      const long long o0 = ((long long)(L * 6 + 2 * q)) * g.spec + (long long)k * n23 + colbase + w;
+      const long long o1 = o0 + g.spec;
+      const T2 za = z[o0], zb = z[o1], pa = p[o0], pb = p[o1];
+      a = T2{za.x + beta * pa.x, za.y + beta * pa.y};
+      b = T2{zb.x + beta * pb.x, zb.y + beta * pb.y};
+      p[o0] = a;
+      p[o1] = b;
+    }
+    const int col = q * W + w;
+    if (k == 0 || 2 * k == n1) {
+      Z[k * W3 + col] = T2{a.x, b.x};
+    } else {
+      Z[k * W3 + col] = T2{a.x - b.y, a.y + b.x};
+      Z[(n1 - k) * W3 + col] = T2{a.x + b.y, b.x - a.y};
+    }
+  }
+  __syncthreads();
+  fft_any<T, +1, 0, W3, true, NT>(Z, pl, 1, W3, twl);
+  double acc[1] = {0.0};
+  for (int idx = tid; idx < n1 * W; idx += NT) {
+    const int w = idx % W, a1 = idx / W;
+    if (a30 + w >= g.n3) continue;
+    const int ph = phase[(long long)a1 * n23 + colbase + w];
+    const T* D = ph < NDL ? Dl + 36 * ph : dmat + 36 * ph;
+    T2* zz = Z + a1 * W3 + w;
+    const T2 z0 = zz[0], z1 = zz[W], z2 = zz[2 * W];
+    const T E[6] = {z0.x, z0.y, z1.x, z1.y, z2.x, z2.y};
+    T t[6];
+    stress6<T>(D, E, t);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[0] += (double)E[c] * (double)t[c];
+    zz[0] = T2{t[0], t[1]};
+    zz[W] = T2{t[2], t[3]};
+    zz[2 * W] = T2{t[4], t[5]};
+  }
+  __syncthreads();
+  fft_any<T, -1, 0, W3, true, NT>(Z, pl, 1, W3, twl);
+  for (int idx = tid; idx < npairs; idx += NT) {
+    const int w = idx % W, q = (idx / W) % 3, k = idx / W3;
+    if (a30 + w >= g.n3) continue;
+    const int col = q * W + w;
+    const T2 zk = Z[k * W3 + col];
+    const T2 zn = Z[((n1 - k) % n1) * W3 + col];
+    const T hf = (T)0.5;
+    const long long off = (long long)k * n23 + colbase + w;
+    tau[((long long)(L * 6 + 2 * q)) * g.spec + off] = T2{hf * (zk.x + zn.x), hf * (zk.y - zn.y)};
+    tau[((long long)(L * 6 + 2 * q + 1)) * g.spec + off] = T2{hf * (zk.y + zn.y), hf * (zn.x - zk.x)};
+  }
+  block_sum<1>(acc, partial + (long long)L * gridDim.x + blockIdx.x);
+}
+
 // ---------------------------------------------------------- Gamma table ---
 // One thread per half-spectrum bin: the alias sums in double, stored at T.
 template <typename T>

@@ -91,6 +91,9 @@ struct KernSet {
   GR gr2[4] = {nullptr, nullptr, nullptr, nullptr};  // k_green2 per Green mode (ISO, GENERAL, TABLE, MOMENTS)
   int W1 = 0, NT1 = 0, W2 = 0, NT2 = 0, NTG = 0, lsG = 0;
   A1 a1s = nullptr;  // the stress-pass kernel in use (a candidate below)
+  using ACG = void (*)(Geo, FftPlan, const C2<T>*, const C2<T>*, C2<T>*, C2<T>*, const Inst*, const int*,
+                       const double*, const int*, const int*, double*);
+  ACG a1cg = nullptr;  // conjugate gradients: direction and stress pass (runtime plans)
   int NT1s = 0, W1s = 0;
   size_t lds1s = 0;
   // autotuner candidates per pass; entry 0 is the default
@@ -118,6 +121,7 @@ void put_axis1(KernSet<T>& K) {
   K.a1[0] = k_axis1<T, MODE_STRESS, NC, W, 256>;
   K.a1[1] = k_axis1<T, MODE_FINAL, NC, W, 256>;
   K.a1[2] = k_axis1<T, MODE_INIT, NC, W, 256>;
+  if constexpr (NC == 0) K.a1cg = k_cg_stress<T, W, 256>;
   K.W1 = W;
   K.NT1 = 256;
 }
@@ -475,7 +479,7 @@ int bind_t(lsh_pattern* p, void* dev, size_t bytes, hipStream_t st) {
     lsh_voigt_to_mandel(p->C_voigt.data() + 36 * q, Cm);
     for (int i = 0; i < 36; ++i) {
       // stress-pass matrix: C_p - C0 (Lippmann-Schwinger), C_p (variational)
-      dm[36 * q + i] = (T)(p->scheme == LSH_SCHEME_VE ? Cm[i] : Cm[i] - C0m[i]);
+      dm[36 * q + i] = (T)(p->scheme != LSH_SCHEME_LS ? Cm[i] : Cm[i] - C0m[i]);
       cm[36 * q + i] = Cm[i];
     }
   }
@@ -527,6 +531,9 @@ struct GroupWS {
   char* X;
   char* TAU;
   char* P[2];
+  char* EX[2];     // conjugate gradients: residual z and direction p
+  double* cg;      // conjugate gradients: per load {rho, alpha, beta, -}
+  double* C0m;     // conjugate gradients: C0 (Mandel)
   double* partial;
   double* eps0;
   double* e0sq;
@@ -543,7 +550,7 @@ struct GroupWS {
 };
 
 template <typename T>
-GroupWS group_layout(const Geo& g, int nload, int ninst, const KernSet<T>& K, char* base) {
+GroupWS group_layout(const Geo& g, int nload, int ninst, const KernSet<T>& K, char* base, bool cg = false) {
   const size_t fb = lsh_align(sizeof(C2<T>) * 6 * (size_t)nload * g.spec);
   GroupWS w;
   size_t off = 0;
@@ -551,9 +558,18 @@ GroupWS group_layout(const Geo& g, int nload, int ninst, const KernSet<T>& K, ch
   w.TAU = base + off; off += fb;
   w.P[0] = base + off; off += fb;
   w.P[1] = base + off; off += fb;
+  w.EX[0] = w.EX[1] = nullptr;
+  w.cg = w.C0m = nullptr;
+  if (cg) {
+    w.EX[0] = base + off; off += fb;
+    w.EX[1] = base + off; off += fb;
+    w.cg = (double*)(base + off); off += lsh_align(sizeof(double) * 4 * nload);
+    w.C0m = (double*)(base + off); off += lsh_align(sizeof(double) * 36);
+  }
   const long long nblkS = (long long)g.n2 * ((g.n3 + K.W1 - 1) / K.W1);
   const long long nblkG = (long long)g.h1 * g.n2;
-  const long long npart = std::max(nblkS * 6, nblkG * 2) * nload;
+  const long long nblkU = (g.spec + 255) / 256;
+  const long long npart = std::max(std::max(nblkS * 6, nblkG * 2), cg ? nblkU * 3 : 0LL) * nload;
   w.partial = (double*)(base + off); off += lsh_align(sizeof(double) * npart);
   w.eps0 = (double*)(base + off); off += lsh_align(sizeof(double) * 6 * nload);
   w.e0sq = (double*)(base + off); off += lsh_align(sizeof(double) * nload);
@@ -718,7 +734,7 @@ int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
   G.g = geo_of(p);
   lsh_green_params(p, &G.gp);
   G.nload = (int)G.spec.inst_of.size();
-  G.w = group_layout<T>(G.g, G.nload, (int)G.spec.inst.size(), G.K, base);
+  G.w = group_layout<T>(G.g, G.nload, (int)G.spec.inst.size(), G.K, base, p->scheme == LSH_SCHEME_CG);
   if (!base || avail < G.w.total) return lsh_fail(LSH_EWORKSPACE, "workspace too small");
   *used = G.w.total;
   const int nt3a = (G.g.n3 + G.K.W1 - 1) / G.K.W1;
@@ -1071,6 +1087,107 @@ int run_groups(std::vector<GroupRun<T>>& groups, double tol, int max_iter, const
   return status;
 }
 
+// Conjugate gradients for the Dirichlet kernel's system (scheme LSH_SCHEME_CG):
+// one application of the operator per iteration through the usual passes
+// (direction and stress, axis 2, Green pass, axis 2 inverse), with the vector
+// updates and reductions in k_cg_update / k_cg_scalars / k_cg_alpha.  Buffers:
+// x = X, z = EX[0], p = EX[1], W = -G C p = P[0], Green output P[1].
+template <typename T>
+int cg_iterate(GroupRun<T>& G, double tol, bool fixed, hipStream_t st) {
+  using T2 = C2<T>;
+  const lsh_pattern* p = G.spec.rep;
+  char* base = p->dev_persist;
+  const T2* tw0 = (const T2*)(base + p->off_tw[0]);
+  const long long nblkU = (G.g.spec + 255) / 256;
+  {
+    Timer tm(3, st);
+    hipLaunchKernelGGL(k_cg_update<T>, dim3((unsigned)nblkU, G.nload), dim3(256), 0, st, G.g, (const T2*)G.w.EX[1],
+                       (const T2*)G.w.P[0], (T2*)G.w.X, (T2*)G.w.EX[0], (const double*)G.w.cg,
+                       (const double*)G.w.C0m, (const int*)G.w.stop_iter, (const int*)G.w.itp, G.w.partial);
+    hipLaunchKernelGGL(k_cg_scalars, dim3(G.nload), dim3(256), 0, st, (const double*)G.w.partial, (int)nblkU,
+                       G.nload, (const double*)G.w.e0sq, (double)G.g.n1, tol, fixed ? 1 : 0, (const int*)G.w.itp,
+                       G.w.stop_iter, G.w.hist, G.w.nonfinite, G.w.cg);
+  }
+  {
+    Timer tm(0, st);
+    hipLaunchKernelGGL(G.K.a1cg, G.gridS, dim3(G.K.NT1), G.K.lds1, st, G.g, p->plan[0], tw0, (const T2*)G.w.EX[0],
+                       (T2*)G.w.EX[1], (T2*)G.w.TAU, (const Inst*)G.w.insts, (const int*)G.w.inst_of,
+                       (const double*)G.w.cg, (const int*)G.w.stop_iter, (const int*)G.w.itp, G.w.partial);
+    hipLaunchKernelGGL(k_cg_alpha, dim3(G.nload), dim3(256), 0, st, (const double*)G.w.partial, (int)G.nblkS,
+                       (const int*)G.w.itp, (const int*)G.w.stop_iter, G.w.cg);
+  }
+  {
+    Timer tm(1, st);
+    launch_axis2<T>(G, 0, (const T2*)G.w.TAU, (T2*)G.w.TAU, st);
+  }
+  {
+    Timer tm(2, st);
+    launch_green<T>(G, 0, st);  // TAU -> P[1] (P[0] is read as the unused previous iterate)
+  }
+  {
+    Timer tm(4, st);
+    launch_axis2<T>(G, 1, (const T2*)G.w.P[1], (T2*)G.w.P[0], st);
+  }
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, G.w.itp);
+  HIPCHK(hipGetLastError());
+  return LSH_OK;
+}
+
+template <typename T>
+int run_cg(GroupRun<T>& G, double tol, int max_iter, const double* dev_E_init, double* dev_E_out, hipStream_t st) {
+  using T2 = C2<T>;
+  const bool fixed = tol < 0.0;
+  for (auto* h : G.spec.history)
+    if (h)
+      for (int j = 0; j < max_iter; ++j) h[j] = NAN;
+  int rc = group_init<T>(G, max_iter, dev_E_init, st);  // x = X: zero or the start field
+  if (rc) return rc;
+  const lsh_pattern* p = G.spec.rep;
+  const size_t fb = sizeof(T2) * 6 * (size_t)G.nload * G.g.spec;
+  double c0m[36];
+  lsh_voigt_to_mandel(p->C0_voigt, c0m);
+  std::vector<double> cg0(4 * G.nload, 0.0);
+  HIPCHK(hipMemcpyAsync(G.w.C0m, c0m, sizeof(c0m), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(G.w.cg, cg0.data(), sizeof(double) * cg0.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(G.w.EX[1], 0, fb, st));  // p = 0
+  HIPCHK(hipMemsetAsync(G.w.P[0], 0, fb, st));   // W = 0: the first update leaves x, z as they are
+  // z = -G C (x + eps0): the usual passes on x with dmat = C and eps0
+  {
+    using T2c = C2<T>;
+    char* base = p->dev_persist;
+    const T2c* tw0 = (const T2c*)(base + p->off_tw[0]);
+    hipLaunchKernelGGL(G.K.a1[MODE_STRESS], G.gridS, dim3(G.K.NT1), G.K.lds1, st, G.g, p->plan[0], tw0,
+                       (const T2c*)G.w.X, (T2c*)G.w.TAU, (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0,
+                       (const int*)G.w.stop_iter, (const int*)G.w.itp, (const double*)nullptr,
+                       (const double*)nullptr, (double*)nullptr, (double*)nullptr);
+    launch_axis2<T>(G, 0, (const T2c*)G.w.TAU, (T2c*)G.w.TAU, st);
+    launch_green<T>(G, 0, st);
+    launch_axis2<T>(G, 1, (const T2c*)G.w.P[1], (T2c*)G.w.EX[0], st);
+    HIPCHK(hipGetLastError());
+  }
+  const int check = fixed ? 32 : 8;
+  const auto t0 = std::chrono::steady_clock::now();
+  int done = 0;
+  while (done < max_iter) {
+    const int step = std::min(check, max_iter - done);
+    for (int k = 0; k < step; ++k) {
+      rc = cg_iterate<T>(G, tol, fixed, st);
+      if (rc) return rc;
+    }
+    done += step;
+    bool all = false;
+    rc = group_poll<T>(G, done, max_iter, st, &all);
+    if (rc) return rc;
+    if (g_prof.on) g_ev.flush();
+    if (all) break;
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int status = group_finish<T>(G, done, tol, fixed, secs, dev_E_out, st);
+  if (status == LSH_ENONFINITE) return lsh_fail(status, "non-finite residual (NaN/Inf) in the iteration");
+  if (status == LSH_ENOTCONVERGED) return lsh_fail(status, "max_iter reached before the Cauchy residual met tol");
+  return status;
+}
+
 // The caller's macroscopic strain of load L (6 Voigt entries, or 3 for d = 2)
 // as the internal six-entry Voigt vector.
 void push_eps0(const lsh_pattern* p, const double* eps0_voigt, int L, std::vector<double>* out) {
@@ -1099,6 +1216,10 @@ int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int
   size_t used = 0;
   int rc = group_prepare<T>(groups[0], (char*)dev_ws, dev_ws ? ws_bytes : 0, &used);
   if (rc) return rc;
+  if (p->scheme == LSH_SCHEME_CG) {
+    if (!groups[0].K.a1cg) return lsh_fail(LSH_EUNSUPPORTED, "conjugate gradients: no kernel for this SNF grid");
+    return run_cg<T>(groups[0], tol, max_iter, dev_E_init, dev_E_out, st);
+  }
   return run_groups<T>(groups, tol, max_iter, dev_E_init, dev_E_out, st);
 }
 
@@ -1260,12 +1381,12 @@ extern "C" int lsh_solve_bytes(const lsh_pattern* p, int nload, lsh_precision pr
     KernSet<double> K;
     int rc = make_kernels<double>(p, kind_has_table(p), &K);
     if (rc) return rc;
-    *bytes = group_layout<double>(geo_of(p), nload, 1, K, nullptr).total;
+    *bytes = group_layout<double>(geo_of(p), nload, 1, K, nullptr, p->scheme == LSH_SCHEME_CG).total;
   } else if (prec == LSH_FP32_MIXED) {
     KernSet<float> K;
     int rc = make_kernels<float>(p, kind_has_table(p), &K);
     if (rc) return rc;
-    *bytes = group_layout<float>(geo_of(p), nload, 1, K, nullptr).total;
+    *bytes = group_layout<float>(geo_of(p), nload, 1, K, nullptr, p->scheme == LSH_SCHEME_CG).total;
   } else {
     return lsh_fail(LSH_EINVAL, "bad precision");
   }
@@ -1283,6 +1404,8 @@ extern "C" int lsh_solve(lsh_pattern* p, int nload, const double* eps0_voigt, do
     if (!std::isfinite(eps0_voigt[i])) return lsh_fail(LSH_EINVAL, "non-finite macroscopic strain");
   if (p->kind < 0 || p->nphase < 1) return lsh_fail(LSH_ESTATE, "kernel or stiffness not set");
   if (p->bound_prec != (int)prec) return lsh_fail(LSH_ESTATE, "pattern not bound at this precision (lsh_bind)");
+  if (p->scheme == LSH_SCHEME_CG && (p->kind != LSH_DIRICHLET || p->m % 2 == 0))
+    return lsh_fail(LSH_EUNSUPPORTED, "conjugate gradients need the Dirichlet kernel on a pattern of odd m");
   hipStream_t st = (hipStream_t)stream;
   if (prec == LSH_FP64)
     return solve_t<double>(p, nload, eps0_voigt, tol, max_iter, dev_ws, ws_bytes, st, dev_E_init, dev_E_out,
@@ -1391,6 +1514,7 @@ extern "C" int lsh_solve_batch(const lsh_task* tasks, int ntask, double tol, int
     const lsh_pattern* p = tasks[t].p;
     if (!p || p->kind < 0 || p->nphase < 1) return lsh_fail(LSH_ESTATE, "task pattern without kernel or stiffness");
     if (p->bound_prec != (int)prec) return lsh_fail(LSH_ESTATE, "task pattern not bound at this precision");
+    if (p->scheme == LSH_SCHEME_CG) return lsh_fail(LSH_EUNSUPPORTED, "conjugate gradients run through lsh_solve only");
   }
   hipStream_t st = (hipStream_t)stream;
   if (prec == LSH_FP64) return solve_batch_t<double>(tasks, ntask, tol, max_iter, dev_ws, ws_bytes, st);

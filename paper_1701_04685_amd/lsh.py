@@ -227,8 +227,9 @@ class Pattern:
         self._prec = None
 
     def set_scheme(self, scheme):
-        """'ls' (Lippmann-Schwinger, default) or 've' (variational); rebind afterwards."""
-        _check(_lib.lsh_set_scheme(self._h, {"ls": 0, "ve": 1}[scheme]))
+        """'ls' (Lippmann-Schwinger, default), 've' (variational) or 'cg' (conjugate
+        gradients, Dirichlet kernel, odd m); rebind afterwards."""
+        _check(_lib.lsh_set_scheme(self._h, {"ls": 0, "ve": 1, "cg": 2}[scheme]))
         self._prec = None
 
     def bind(self, precision="fp64"):
