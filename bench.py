@@ -412,6 +412,68 @@ def bench_plane(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_cg(args):
+    """Conjugate gradients against the Basic Scheme on the same discrete system:
+    Dirichlet kernel on diag(125, 125, 125) (odd: no Nyquist faces), RSA
+    spheres f = 0.3 with radii 6-12 grid steps, contrast 100, C0 the phase
+    mean, the six unit loads, FP64: wall time and operator applications to the
+    Cauchy residual 1e-6 and 1e-8, and the effective tensors' difference."""
+    import torch
+    from paper_1701_04685_amd import lsh, warmstart as wst
+    import lsh_inputs as li
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    n = 125
+    P = lsh.Pattern(np.diag([n, n, n]))
+    if not np.array_equal(P.point_numerators(), li.grid_points_numerators(n)):
+        raise RuntimeError("pattern storage order is not the plain grid order")
+    ph = wst.packing(60000, n)
+    Cp = np.stack([li.isotropic_voigt(1.0, 0.3), li.isotropic_voigt(100.0, 0.3)])
+    P.set_kernel("dirichlet")
+    P.set_stiffness(Cp, li.mean_reference(Cp), ph)
+    loads = np.eye(6)
+    out = {}
+    for scheme in ("ls", "cg"):
+        P.set_scheme(scheme)
+        P.bind("fp64")
+        ws = torch.empty(P.workspace_bytes(6), dtype=torch.uint8, device="cuda")
+        P.solve(loads[:1], tol=-1.0, max_iter=4, workspace=ws)       # warm-up
+        lsh.profile_enable(True)
+        P.solve(loads, tol=-1.0, max_iter=20, workspace=ws)
+        ms, cnt = lsh.profile_read()
+        lsh.profile_enable(False)
+        per_it = float(sum(ms[i] for i in range(5)) / 20)
+        rec = {"ms_per_iteration_6_loads": round(per_it, 3)}
+        for tol in (1e-6, 1e-8):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = P.solve(loads, tol=tol, max_iter=20000, workspace=ws)
+            t = time.perf_counter() - t0
+            rec[f"tol_{tol:g}"] = {"seconds": round(t, 4), "iterations": [int(v) for v in r["iterations"]],
+                                   "C_eff_voigt": r["sigma"].T.tolist()}
+            log(f"{scheme} tol {tol:g}: {t:.3f} s, iterations {r['iterations'].tolist()}")
+        out[scheme] = rec
+    C_ls = np.array(out["ls"]["tol_1e-08"]["C_eff_voigt"])
+    C_cg = np.array(out["cg"]["tol_1e-08"]["C_eff_voigt"])
+    speed = out["ls"]["tol_1e-06"]["seconds"] / out["cg"]["tol_1e-06"]["seconds"]
+    line = {"metric": "time to Cauchy residual 1e-6, Basic Scheme / conjugate gradients", "value": speed,
+            "unit": "x", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": out["cg"]["tol_1e-06"]["seconds"] * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "125^3 Dirichlet, RSA spheres f=0.3 radii 6-12, contrast 100, C0 mean, 6 unit "
+                                   "loads, FP64", "sphere_fraction": float(ph.mean())},
+            "roofline": None, "cpu_baseline": None,
+            "speedup_tol_1e-8": out["ls"]["tol_1e-08"]["seconds"] / out["cg"]["tol_1e-08"]["seconds"],
+            "C_eff_rel_diff_tol_1e-8": float(np.linalg.norm(C_cg - C_ls) / np.linalg.norm(C_ls)),
+            "runs": {k: {kk: vv for kk, vv in v.items()} for k, v in out.items()}}
+    for k in ("ls", "cg"):
+        for t in ("tol_1e-06", "tol_1e-08"):
+            line["runs"][k][t].pop("C_eff_voigt")
+    print(json.dumps(line), flush=True)
+
+
 def bench_ve(args):
     """The variational discretisation (eq. (pde_coefficients_variational)) on the
     128^3 dlVP benchmark problem: iteration rate, the solve to 1e-6, and C^eff
@@ -479,10 +541,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the converged (time-to-tol) solve")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "copy", "ve", "plane"],
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "copy", "ve", "plane", "cg"],
                     help="cfg2 (default): 128^3 FP64 dlVP; cfg3: non-diagonal Box FP32; cfg4: batched FP32; "
                          "cfg5: learned warm start; copy: counter calibration; ve: variational discretisation; "
-                         "plane: the 2-D study of Sec. 4")
+                         "plane: the 2-D study of Sec. 4; cg: conjugate gradients vs the Basic Scheme")
     ap.add_argument("--train-packings", type=int, default=334, help="cfg5: 64^3 training packings (x6 fields)")
     ap.add_argument("--epochs", type=int, default=12, help="cfg5: training epochs")
     ap.add_argument("--eval-packings", type=int, default=200, help="cfg5: unseen 128^3 packings")
@@ -512,6 +574,8 @@ def main():
         return bench_ve(args)
     if args.workload == "plane":
         return bench_plane(args)
+    if args.workload == "cg":
+        return bench_cg(args)
 
     P, Cp, C0, phase = build_problem(lsh, li)
     nload = 6
