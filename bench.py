@@ -396,6 +396,35 @@ def bench_plane(args):
                      "iterations_dirichlet_box": [itd, itb],
                      "e_eff_alpha_grid": [[round(float(v), 6) for v in row] for row in table]}
         log(f"{name}: Dirichlet {eeff(sd):.5f} Box {eeff(sb):.5f} dlVP best {table[i, j]:.5f} at {grid[i], grid[j]}")
+    # Box direction sets (the paper leaves the choice of Xi open): e_eff per pattern
+    dirs = {"(e1,e2)x4": [[1, 0, 1, 0, 1, 0, 1, 0], [0, 1, 0, 1, 0, 1, 0, 1]],
+            "(e1,e2)x2": [[1, 0, 1, 0], [0, 1, 0, 1]],
+            "(e1,e2)x3": [[1, 0, 1, 0, 1, 0], [0, 1, 0, 1, 0, 1]],
+            "(e1,e2,e1+e2)x2": [[1, 0, 1, 1, 0, 1], [0, 1, 1, 0, 1, 1]],
+            "(e1,e2,e1+e2,e1-e2)x2": [[1, 0, 1, 1, 1, 0, 1, 1], [0, 1, 1, -1, 0, 1, 1, -1]]}
+    xi_study = {}
+    for dname, Xi in dirs.items():
+        xi_study[dname] = {}
+        for name, M in pats.items():
+            try:
+                sig, _, _, _, _ = solve(M, "box", {"Xi": np.array(Xi, float), "R": 16})
+            except lsh.LshError as e:
+                # a direction subset with |det| != 1 makes the translates dependent:
+                # some bracket sum vanishes (Lemma (FI:Props) a/b), and bind refuses it
+                xi_study[dname][name] = e.args[0] if e.args else str(e)
+                continue
+            xi_study[dname][name] = eeff(sig)
+            nsolve += 1
+        log(f"Box {dname}: {xi_study[dname]}")
+    # truncation of the Box alias sums: the lowest-order set decays slowest
+    trunc = {}
+    for R in (2, 4, 8, 16, 32):
+        sig, _, _, _, _ = solve(pats["M1"], "box", {"Xi": np.array(dirs["(e1,e2)x2"], float), "R": R})
+        trunc[str(R)] = {"e_eff": eeff(sig), "sigma_e11": [float(v) for v in sig]}
+        nsolve += 1
+    s64 = np.array(trunc["32"]["sigma_e11"])
+    for R in trunc:
+        trunc[R]["rel_change_vs_R32"] = float(np.linalg.norm(np.array(trunc[R]["sigma_e11"]) - s64) / np.linalg.norm(s64))
     t_all = time.perf_counter() - t_all
     out = {"metric": "2-D study of Sec. 4: e_eff reduction, best dlVP vs Dirichlet, M1",
            "value": res["M1"]["reduction_best_vs_dirichlet"], "unit": "fraction", "n_gpus": 1, "steps": nsolve,
@@ -408,7 +437,8 @@ def bench_plane(args):
            "roofline": None, "cpu_baseline": None,
            "reference": {"kind": "Dirichlet on diag(N,N)", "sigma_e11": {str(n): [float(v) for v in s] for n, s in ref.items()},
                          "e_eff_of_coarser_vs_2048": {str(n): eeff(ref[n]) for n in (256, 512, 1024)}},
-           "patterns": res}
+           "patterns": res, "box_direction_sets_e_eff": xi_study,
+           "box_truncation_M1_(e1,e2)x2": trunc}
     print(json.dumps(out), flush=True)
 
 
