@@ -271,6 +271,10 @@ def gamma_at_frequencies(P: Pattern, C0_voigt, kind, params, H, chunk=4096):
             k = h[sel] + (MT @ z)[None, :]
             num[sel] += w[sel, None, None] * gamma0(C0_voigt, k)
             den[sel] += w[sel]
+        if kind == BOX and params.get("tail"):
+            tn, td = box_tail(P, C0_voigt, params, h, x)
+            num += tn
+            den += td
         ok = den > 0
         out[s:s + chunk][ok] = num[ok] / den[ok, None, None]
         den_all[s:s + chunk] = den
@@ -279,6 +283,67 @@ def gamma_at_frequencies(P: Pattern, C0_voigt, kind, params, H, chunk=4096):
     zero = np.all(H == 0, axis=1)
     out[zero] = 0.0
     return out, den_all
+
+
+def box_slow_axes(Xi):
+    """Axes i of the alias lattice along which the Box weight decays only like
+    1/t^2: exactly one column xi has xi_i != 0, and |xi_i| = 1.  Returns
+    [(i, s)] with s the index of that column."""
+    Xi = np.asarray(Xi, dtype=np.float64)
+    out = []
+    for i in range(Xi.shape[0]):
+        nz = [s for s in range(Xi.shape[1]) if Xi[i, s] != 0.0]
+        if len(nz) == 1 and abs(Xi[i, nz[0]]) == 1.0:
+            out.append((i, nz[0]))
+    return out
+
+
+def box_tail(P: Pattern, C0_voigt, params, H, X, gamma_fn=None):
+    """Leading term of the Box alias sum beyond the truncation box [-R, R]^d.
+
+    For integer directions xi the factor sin^2(pi xi^T (x+z)) of each weight
+    does not depend on z, so a weight is a rational function of z.  Along a
+    slow axis i (box_slow_axes) only the column xi* involves z_i: the line of
+    aliases z_perp + z_i e_i carries the weight w_perp(z_perp) sinc^2(pi (c + z_i))
+    with c = xi*^T (x + z_perp) (xi*_i = +-1), and the part beyond |z_i| > R is
+    exactly w_perp (1 - sum_{|n| <= R} sinc^2(pi (c + n))) by the identity
+    sum_n sinc^2(pi (c + n)) = 1.  On those aliases k = h + M^T z turns towards
+    +-M^T e_i, so Gamma0_k tends to Gamma0_{M^T e_i} (even, degree 0); the term
+    odd in 1/z_i cancels between the two half-lines.  The neglected parts
+    (the next order along the line, aliases beyond R on the fast axes) are
+    O(R^-3) against O(R^-1) for plain truncation.
+    gamma_fn(C0_voigt, k) gives the Green operator (default: gamma0 of this
+    module, d = 3).  Returns (num (n, q, q), den (n,)) to add to the truncated
+    sums."""
+    gamma_fn = gamma_fn or gamma0
+    Xi = np.asarray(params["Xi"], dtype=np.float64)
+    R = int(params.get("R", 16))
+    d = P.d
+    MT = np.array(P.MT, dtype=np.float64)
+    n = len(H)
+    q = 6 if d == 3 else 3
+    num = np.zeros((n, q, q))
+    den = np.zeros(n)
+    rng = np.arange(-R, R + 1)
+    for i, s in box_slow_axes(Xi):
+        G_inf = gamma_fn(C0_voigt, (MT @ np.eye(d)[i])[None])[0]
+        others = [j for j in range(d) if j != i]
+        for zp in itertools.product(rng, repeat=d - 1):
+            z = np.zeros(d)
+            z[others] = zp
+            y = X + z[None, :]                      # z_i = 0: xi*_i (x_i + 0) enters c
+            w_perp = np.ones(n)
+            for t in range(Xi.shape[1]):
+                if t != s:
+                    w_perp *= np.sinc(y @ Xi[:, t]) ** 2
+            c = y @ Xi[:, s]
+            line = np.zeros(n)
+            for m_ in rng:
+                line += np.sinc(c + m_) ** 2
+            add = w_perp * (1.0 - line)
+            num += add[:, None, None] * G_inf[None]
+            den += add
+    return num, den
 
 
 def gamma_symmetrised_at(P: Pattern, C0_voigt, kind, params, H):

@@ -147,6 +147,10 @@ def gamma_at_frequencies(P: Pattern, C0_voigt, kind, params, H, chunk=4096):
             k = h[sel] + (MT @ z)[None, :]
             num[sel] += w[sel, None, None] * gamma0(C0_voigt, k)
             den[sel] += w[sel]
+        if kind == green.BOX and params.get("tail"):
+            tn, td = green.box_tail(P, C0_voigt, params, h, x, gamma_fn=gamma0)
+            num += tn
+            den += td
         ok = den > 0
         out[s:s + chunk][ok] = num[ok] / den[ok, None, None]
         den_all[s:s + chunk] = den

@@ -227,3 +227,89 @@ def test_box_truncation_converges():
     # the weight tail beyond R decays like 1/R, so each doubling of R should
     # shrink the change by about half
     assert all(b < 0.75 * a for a, b in zip(deltas, deltas[1:]))
+
+
+# ---------------------------------------------------------------------------
+# tail of the Box alias sums (green.box_tail)
+# ---------------------------------------------------------------------------
+def _box_sum_by_moments(P, lam, mu, Xi, R, h):
+    """Truncated Box alias sum at one frequency, evaluated independently of the
+    oracle's loop: all aliases of [-R, R]^3 at once, isotropic C0 through the
+    weighted moments of the alias directions (Gamma0 = S(n)/mu - r Q(n))."""
+    M = np.array(P.M, float)
+    hr, xn = P.reduce_frequencies(np.array([h]))
+    hr = hr[0].astype(float)
+    x = xn[0].astype(float) / P.m
+    r1 = np.arange(-R, R + 1)
+    A = np.zeros((3, 3))
+    Q = np.zeros((3, 3, 3, 3))
+    W = 0.0
+    for z0 in r1:
+        Z = np.array(np.meshgrid([z0], r1, r1, indexing="ij")).reshape(3, -1).T.astype(float)
+        y = x[None] + Z
+        w = np.ones(len(Z))
+        for s in range(Xi.shape[1]):
+            w *= np.sinc(y @ Xi[:, s]) ** 2
+        k = hr[None] + Z @ M
+        nk = np.linalg.norm(k, axis=1)
+        ok = (w > 0) & (nk > 0)
+        W += w.sum()
+        n = k[ok] / nk[ok, None]
+        A += np.einsum("p,pi,pj->ij", w[ok], n, n)
+        Q += np.einsum("p,pi,pj,pk,pl->ijkl", w[ok], n, n, n, n)
+    A /= W
+    Q /= W
+    rr = (lam + mu) / (mu * (lam + 2 * mu))
+    G = np.zeros((6, 6))
+    for J in range(6):
+        e = np.zeros(6)
+        e[J] = 1
+        t = green.mandel_to_tensor(e)
+        G[:, J] = green.tensor_to_mandel((0.5 / mu) * (A @ t + t @ A) - rr * np.einsum("ijkl,kl->ij", Q, t))
+    return G
+
+
+def test_box_slow_axes():
+    assert green.box_slow_axes(np.array([[1, 0, 0, 1], [0, 1, 0, 1], [0, 0, 1, 0]])) == [(2, 2)]
+    assert green.box_slow_axes(np.eye(3)) == [(0, 0), (1, 1), (2, 2)]
+    assert green.box_slow_axes(np.array([[1, 0, 1, 0], [0, 1, 0, 1]])) == []
+    assert green.box_slow_axes(np.array([[2, 0, 1], [0, 1, 1], [0, 0, 0]])) == []   # |xi_i| = 2: no closed form
+
+
+def test_box_tail_restores_the_order_zero_denominator():
+    """Xi = I: the weights are separable and their full sum is 1 (the closed form
+    sum_n sinc^2(pi (x + n)) = 1); the corrected denominator misses only the
+    corner tails, second order in the truncated mass."""
+    P = Pattern(np.diag([6, 6, 6]))
+    C0 = li.isotropic_voigt(2.0, 0.3)
+    H = np.array([[3, 1, -2], [-3, -3, 2], [1, 2, 3]])
+    for R in (2, 4, 8):
+        _, d0 = green.gamma_at_frequencies(P, C0, "box", {"Xi": np.eye(3), "R": R}, H)
+        _, d1 = green.gamma_at_frequencies(P, C0, "box", {"Xi": np.eye(3), "R": R, "tail": True}, H)
+        e0, e1 = np.abs(1 - d0).max(), np.abs(1 - d1).max()
+        assert e0 > 1e-3 / R and e1 < 5 * e0 ** 2, (R, e0, e1)
+
+
+def test_box_tail_correction_converges_cubically():
+    """Xi = {e1, e2, e3, e1+e2} (the 3-D workload's set; e3 is a slow axis):
+    against the infinite sum (Richardson extrapolation of independently
+    evaluated truncated sums at R = 16, 32, 64), plain truncation errs like
+    1/R, the tail-corrected sum like R^-3."""
+    P = Pattern(np.diag([8, 8, 8]))
+    lam, mu = li.lame(5.5, 0.3)
+    C0 = li.isotropic_voigt(5.5, 0.3)
+    Xi = np.array([[1, 0, 0, 1], [0, 1, 0, 1], [0, 0, 1, 0]], float)
+    H = [[3, 1, 4], [1, -3, 2]]
+    T = {R: np.array([_box_sum_by_moments(P, lam, mu, Xi, R, h) for h in H]) for R in (16, 32, 64)}
+    trunc16, _ = green.gamma_at_frequencies(P, C0, "box", {"Xi": Xi, "R": 16}, np.array(H))
+    np.testing.assert_allclose(trunc16, T[16], atol=1e-13)        # the two evaluations agree
+    S = (8 * T[64] - 6 * T[32] + T[16]) / 3
+    err_t, err_c = [], []
+    for R in (4, 8, 16):
+        Tr, _ = green.gamma_at_frequencies(P, C0, "box", {"Xi": Xi, "R": R}, np.array(H))
+        Co, _ = green.gamma_at_frequencies(P, C0, "box", {"Xi": Xi, "R": R, "tail": True}, np.array(H))
+        err_t.append(np.abs(Tr - S).max())
+        err_c.append(np.abs(Co - S).max())
+    assert 1.6 < err_t[0] / err_t[1] < 2.5 and 1.6 < err_t[1] / err_t[2] < 2.5, err_t   # ~ 1/R
+    assert err_c[0] / err_c[1] > 5 and err_c[1] / err_c[2] > 5, err_c                   # ~ R^-3
+    assert err_c[2] < err_t[2] / 100
