@@ -203,6 +203,24 @@ def bench_cfg3(args):
            "cpu_baseline": None, "autotune": tuned,
            "solve_to_tol": {"tol": 1e-6, "iterations": [int(v) for v in res["iterations"]], "seconds": round(ts, 3),
                             "C_eff_asym": float(np.linalg.norm(C - C.T) / np.linalg.norm(C))}}
+    # the Box alias sums' truncation: C^eff (FP64, tol 1e-8) with R = 16 as is,
+    # with its tail, and with R = 32 and its tail as the reference
+    del ws
+    Xi = np.array([[1, 0, 0, 1], [0, 1, 0, 1], [0, 0, 1, 0]], float)
+    ceff = {}
+    for name, kp in (("R16", {"Xi": Xi, "R": 16}), ("R16_tail", {"Xi": Xi, "R": 16, "tail": True}),
+                     ("R32_tail", {"Xi": Xi, "R": 32, "tail": True})):
+        P.set_kernel("box", kp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.bind("fp64")
+        tbk = time.perf_counter() - t0
+        r = P.solve(loads, tol=1e-8, max_iter=20000)
+        ceff[name] = (r["sigma"].T, round(tbk, 3), [int(v) for v in r["iterations"]])
+    ref = ceff["R32_tail"][0]
+    out["box_truncation_fp64"] = {
+        k: {"C_eff_rel_diff_vs_R32_tail": float(np.linalg.norm(v[0] - ref) / np.linalg.norm(ref)),
+            "table_build_s": v[1], "iterations": v[2]} for k, v in ceff.items()}
     print(json.dumps(out), flush=True)
 
 

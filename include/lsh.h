@@ -115,9 +115,14 @@ int lsh_pattern_points(const lsh_pattern *p, int64_t *y_num);
  *   LSH_DLVP      : params = alpha[d], each in [0, 1], the trapezoid of Sec. 2.2
  *                   (g_alpha = B_Xi, Xi = (diag alpha, I); alpha = 1 is Fejer).
  *   LSH_BOXSPLINE : params = {s, Xi[d*s] (columns, pattern coordinates, row-major
- *                   d x s, spanning R^d), R}; the alias sum runs over z in
+ *                   d x s, spanning R^d), R, tail}; the alias sum runs over z in
  *                   [-R,R]^d (Sec. 4.2 truncates the bracket sums to a box of
- *                   terms).  s <= 16 (d = 3), <= 15 (d = 2).
+ *                   terms; R defaults to 16).  tail = 1 adds the aliases beyond R
+ *                   along the slow axes (one direction with a +-1 entry there,
+ *                   all others 0): their weight is the mass the identity
+ *                   sum_n sinc^2(pi (c + n)) = 1 leaves outside, their Green
+ *                   operator that of M^T e_i; the truncation error then falls
+ *                   like R^-3 instead of 1/R.  s <= 16 (d = 3), <= 15 (d = 2).
  * Host only.  Errors: LSH_EINVAL (kind, parameter count or range).               */
 int lsh_set_kernel(lsh_pattern *p, lsh_kernel kind, const double *params, int nparams);
 

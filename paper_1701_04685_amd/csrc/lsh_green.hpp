@@ -23,6 +23,10 @@ struct GreenParams {
   int nxi;           // Box spline: number of directions
   int R;             // Box spline: alias box [-R, R]^3
   int flat3;         // two-dimensional pattern: the third axis carries no aliases
+  int tail;          // Box spline: add the aliases beyond R along the slow axes
+  int nslow;         // slow axes: one direction with a unit entry there, all others zero
+  int slow_axis[3];
+  int slow_col[3];
   int64_t m;         // |det M|
   int64_t e[3];      // SNF diagonal
   int64_t VT[9];     // h = V^T b
@@ -139,6 +143,58 @@ __device__ inline double kernel_weight(const GreenParams& gp, const double x[3])
   return g * g;
 }
 
+// Box spline, the aliases beyond [-R, R] along a slow axis i: only the
+// direction xi* varies along the line z_perp + t e_i, and the weight the line
+// keeps outside |t| <= R is w_perp (1 - sum_{|n| <= R} sinc^2(pi (c + n))),
+// c = xi*^T (x + z_perp), by the identity sum_n sinc^2(pi (c + n)) = 1.  There
+// k = h + M^T z turns towards M^T e_i, so those aliases carry Gamma0 of M^T e_i
+// (the term odd in 1/t cancels between the half-lines; what remains is
+// O(R^-3) against O(R^-1) for plain truncation).
+__device__ inline void box_tail(const GreenParams& gp, const double x0[3], int r, double acc[21], double* den) {
+  const double PI = 3.14159265358979323846264338327950288;
+  for (int a = 0; a < gp.nslow; ++a) {
+    const int i = gp.slow_axis[a], sc = gp.slow_col[a];
+    const int j0 = i == 0 ? 1 : 0, j1 = i == 2 ? 1 : 2;
+    const int r0 = (gp.flat3 && j0 == 2) ? 0 : r, r1 = (gp.flat3 && j1 == 2) ? 0 : r;
+    double tw = 0.0;
+    for (int u = -r0; u <= r0; ++u)
+      for (int v = -r1; v <= r1; ++v) {
+        double y[3] = {x0[0], x0[1], x0[2]};
+        y[j0] += u;
+        y[j1] += v;
+        double wp = 1.0;
+        for (int s = 0; s < gp.nxi; ++s) {
+          if (s == sc) continue;
+          const double t = gp.Xi[3 * s] * y[0] + gp.Xi[3 * s + 1] * y[1] + gp.Xi[3 * s + 2] * y[2];
+          if (t != 0.0) {
+            const double g = sinpi(t) / (PI * t);
+            wp *= g * g;
+          }
+        }
+        if (wp <= 0.0) continue;
+        const double c = gp.Xi[3 * sc] * y[0] + gp.Xi[3 * sc + 1] * y[1] + gp.Xi[3 * sc + 2] * y[2];
+        const double sp = sinpi(c);
+        double line;
+        if (sp == 0.0) {  // c an integer: one term of the line carries the whole weight
+          line = fabs(rint(c)) <= (double)r ? 1.0 : 0.0;
+        } else {
+          double q2 = 0.0;
+          for (int m = -r; m <= r; ++m) {
+            const double q = c + m;
+            q2 += 1.0 / (q * q);
+          }
+          line = sp * sp * q2 / (PI * PI);
+        }
+        tw += wp * (1.0 - line);
+      }
+    if (tw != 0.0) {
+      const double kd[3] = {(double)gp.MT[i], (double)gp.MT[3 + i], (double)gp.MT[6 + i]};
+      add_gamma0(gp, kd, tw, acc);
+      *den += tw;
+    }
+  }
+}
+
 // Weighted alias sum for the representative h_rep (x_num its M^{-T} numerator):
 // acc = sum_z w Gamma0, returns sum_z w.  z over {-1,0,1}^3 (modified
 // Dirichlet, dlVP), {0} (Dirichlet) or [-R,R]^3 (Box); z3 = 0 only for a
@@ -166,6 +222,7 @@ __device__ inline double alias_sum(const GreenParams& gp, const int64_t hr[3], c
         const double kd[3] = {(double)kk[0], (double)kk[1], (double)kk[2]};
         add_gamma0(gp, kd, w, acc);
       }
+  if (gp.kind == 3 && gp.tail) box_tail(gp, x0, r, acc, &den);
   return den;
 }
 

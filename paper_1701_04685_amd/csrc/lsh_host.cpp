@@ -215,6 +215,22 @@ void lsh_green_params(const lsh_pattern* p, GreenParams* gp) {
   gp->kind = p->kind;
   gp->flat3 = p->d == 2 ? 1 : 0;
   gp->nxi = p->nxi;
+  gp->tail = p->kind == LSH_BOXSPLINE ? p->tail : 0;
+  gp->nslow = 0;
+  for (int i = 0; i < 3 && gp->tail; ++i) {
+    if (p->d == 2 && i == 2) continue;  // the embedding's third axis carries no aliases
+    int cnt = 0, col = -1;
+    for (int c = 0; c < p->nxi; ++c)
+      if (p->Xi[3 * c + i] != 0.0) {
+        ++cnt;
+        col = c;
+      }
+    if (cnt == 1 && fabs(p->Xi[3 * col + i]) == 1.0) {
+      gp->slow_axis[gp->nslow] = i;
+      gp->slow_col[gp->nslow] = col;
+      ++gp->nslow;
+    }
+  }
   gp->R = p->R;
   gp->m = p->m;
   for (int i = 0; i < 3; ++i) gp->e[i] = p->e[i];
@@ -340,7 +356,8 @@ extern "C" int lsh_set_kernel(lsh_pattern* p, lsh_kernel kind, const double* par
       // d = 2 appends the direction e3 (its factor vanishes at every alias z3 != 0)
       if (s < d || s + (3 - d) > LSH_MAX_XI || (double)s != params[0])
         return lsh_fail(LSH_EINVAL, "Box spline: s must be an integer in [d, 16 - (3 - d)]");
-      if (nparams != 1 + d * s && nparams != 2 + d * s) return lsh_fail(LSH_EINVAL, "Box spline: expected 1 + d s (+1) parameters");
+      if (nparams < 1 + d * s || nparams > 3 + d * s)
+        return lsh_fail(LSH_EINVAL, "Box spline: expected {s, Xi[d s]} and optionally R and the tail flag");
       double XiXt[9] = {0};
       memset(p->Xi, 0, sizeof(p->Xi));
       for (int c = 0; c < s; ++c)
@@ -355,7 +372,13 @@ extern "C" int lsh_set_kernel(lsh_pattern* p, lsh_kernel kind, const double* par
       if (!(dd > 1e-12)) return lsh_fail(LSH_EINVAL, "Box spline directions must span R^d (Sec. 2.2)");
       p->nxi = sx;
       p->R = 16;
-      if (nparams == 2 + d * s) {
+      p->tail = 0;
+      if (nparams == 3 + d * s) {
+        const double t = params[2 + d * s];
+        if (t != 0.0 && t != 1.0) return lsh_fail(LSH_EINVAL, "Box spline: the tail flag must be 0 or 1");
+        p->tail = (int)t;
+      }
+      if (nparams >= 2 + d * s) {
         const double r = params[1 + d * s];
         if (!(r >= 0 && r <= 64) || (double)(int)r != r) return lsh_fail(LSH_EINVAL, "Box spline: R must be an integer in [0, 64]");
         p->R = (int)r;

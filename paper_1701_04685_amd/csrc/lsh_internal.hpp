@@ -29,6 +29,7 @@ struct lsh_pattern {
   int nxi = 0;
   double Xi[3 * LSH_MAX_XI];
   int R = 16;
+  int tail = 0;                  // Box spline: tail of the alias sums beyond R
 
   // ---- Def. (weak_pde): stiffness field
   int nphase = 0;

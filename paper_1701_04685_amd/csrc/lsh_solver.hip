@@ -1228,7 +1228,8 @@ bool same_group(const lsh_pattern* a, const lsh_pattern* b) {
   if (a->d != b->d) return false;
   for (int i = 0; i < 9; ++i)
     if (a->M[i] != b->M[i]) return false;
-  if (a->kind != b->kind || a->R != b->R || a->nxi != b->nxi || a->scheme != b->scheme) return false;
+  if (a->kind != b->kind || a->R != b->R || a->nxi != b->nxi || a->scheme != b->scheme || a->tail != b->tail)
+    return false;
   for (int i = 0; i < 3; ++i)
     if (a->alpha[i] != b->alpha[i]) return false;
   for (int i = 0; i < 3 * LSH_MAX_XI; ++i)

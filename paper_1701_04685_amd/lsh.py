@@ -207,6 +207,8 @@ class Pattern:
         if k == BOXSPLINE and isinstance(params, dict):
             Xi = np.asarray(params["Xi"], dtype=np.float64)
             flat = [float(Xi.shape[1])] + list(Xi.reshape(-1)) + [float(params.get("R", 16))]
+            if params.get("tail"):
+                flat.append(1.0)
         elif k == DLVP and isinstance(params, dict):
             flat = list(np.asarray(params["alpha"], dtype=np.float64))
         else:

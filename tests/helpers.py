@@ -26,7 +26,7 @@ def two_phase(E1=1.0, E2=10.0, nu=0.3):
 
 def oracle_kernel_params(kind, params):
     if kind == "box":
-        return {"Xi": np.asarray(params["Xi"], float), "R": params.get("R", 16)}
+        return {"Xi": np.asarray(params["Xi"], float), "R": params.get("R", 16), "tail": bool(params.get("tail"))}
     if kind == "dlvp":
         return {"alpha": list(params["alpha"])}
     return {}
