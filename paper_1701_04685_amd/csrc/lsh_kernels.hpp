@@ -1210,8 +1210,9 @@ __global__ void k_cg_alpha(const double* __restrict__ partial, int nblk, const i
 // tau = C p at the points (no eps0: the operator's linear part) through the
 // axis-1 transforms of k_axis1 (runtime plan), stored as the axis-2 input, and
 // the partial sums of <p, C p> = sum_y p(y) . tau(y).  Block layout and LDS as
-// k_axis1 (twiddles, lines, the first 16 phases' C in LDS).
-template <typename T, int W, int NT>
+// k_axis1 (twiddles, lines, the first 16 phases' C in LDS); NC as in k_axis1
+// (> 0: compile-time line length, 0: runtime plan).
+template <typename T, int NC, int W, int NT>
 __global__ void __launch_bounds__(NT) k_cg_stress(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
                                                   const C2<T>* __restrict__ z, C2<T>* __restrict__ p,
                                                   C2<T>* __restrict__ tau, const Inst* __restrict__ insts,
@@ -1222,7 +1223,7 @@ __global__ void __launch_bounds__(NT) k_cg_stress(Geo g, FftPlan pl, const C2<T>
   constexpr int W3 = 3 * W;
   constexpr int NDL = 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int n1 = g.n1;
+  const int n1 = NC > 0 ? NC : g.n1;
   const int h1 = n1 / 2 + 1;
   T2* twl = reinterpret_cast<T2*>(smem_raw);
   T2* Z = twl + n1;
@@ -1266,7 +1267,7 @@ __global__ void __launch_bounds__(NT) k_cg_stress(Geo g, FftPlan pl, const C2<T>
     }
   }
   __syncthreads();
-  fft_any<T, +1, 0, W3, true, NT>(Z, pl, 1, W3, twl);
+  fft_any<T, +1, NC, W3, true, NT>(Z, pl, 1, W3, twl);
   double acc[1] = {0.0};
   for (int idx = tid; idx < n1 * W; idx += NT) {
     const int w = idx % W, a1 = idx / W;
@@ -1285,7 +1286,7 @@ __global__ void __launch_bounds__(NT) k_cg_stress(Geo g, FftPlan pl, const C2<T>
     zz[2 * W] = T2{t[4], t[5]};
   }
   __syncthreads();
-  fft_any<T, -1, 0, W3, true, NT>(Z, pl, 1, W3, twl);
+  fft_any<T, -1, NC, W3, true, NT>(Z, pl, 1, W3, twl);
   for (int idx = tid; idx < npairs; idx += NT) {
     const int w = idx % W, q = (idx / W) % 3, k = idx / W3;
     if (a30 + w >= g.n3) continue;

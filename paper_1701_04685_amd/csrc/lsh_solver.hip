@@ -114,14 +114,14 @@ constexpr int pick_w(int N, int bytes_per_col, int cap, int budget) {
 }
 
 // compile-time line lengths; every other length takes the runtime plan
-#define LSH_SPECIAL_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(128) X(256) X(512)
+#define LSH_SPECIAL_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(125) X(128) X(256) X(512)
 
 template <typename T, int NC, int W>
 void put_axis1(KernSet<T>& K) {
   K.a1[0] = k_axis1<T, MODE_STRESS, NC, W, 256>;
   K.a1[1] = k_axis1<T, MODE_FINAL, NC, W, 256>;
   K.a1[2] = k_axis1<T, MODE_INIT, NC, W, 256>;
-  if constexpr (NC == 0) K.a1cg = k_cg_stress<T, W, 256>;
+  K.a1cg = k_cg_stress<T, NC, W, 256>;
   K.W1 = W;
   K.NT1 = 256;
 }
@@ -141,6 +141,7 @@ bool axis1_special(const Geo& g, KernSet<T>& K) {
     K.a1[0] = k_axis1<T, MODE_STRESS, NC, W, 512>;
     K.a1[1] = k_axis1<T, MODE_FINAL, NC, W, 512>;
     K.a1[2] = k_axis1<T, MODE_INIT, NC, W, 512>;
+    K.a1cg = k_cg_stress<T, NC, W, 512>;
     K.W1 = W;
     K.NT1 = 512;
   } else {
