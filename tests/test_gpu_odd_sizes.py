@@ -20,19 +20,34 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-def spheres(seed):
+def spheres(seed, rmin=2.0, rmax=4.0):
     def f(Y):
-        c, r = li.rsa_spheres(seed, li.lattice_unit(len(Y)), 0.3, rmin=2.0, rmax=4.0)
+        c, r = li.rsa_spheres(seed, li.lattice_unit(len(Y)), 0.3, rmin=rmin, rmax=rmax)
         return li.spheres_phase(Y, c, r)
     return f
 
 
+@pytest.fixture(scope="module")
+def cube125(lib):
+    """125^3, Dirichlet, contrast 50: one problem (and one oracle Green
+    operator, the expensive part) for the Basic Scheme and CG tests."""
+    Cp = np.stack([li.isotropic_voigt(1.0, 0.3), li.isotropic_voigt(50.0, 0.3)])
+    # ~100 spheres of radius 8-14 grid steps (smaller ones would take thousands)
+    pr = Problem(np.diag([125, 125, 125]), "dirichlet", {}, spheres(3, 8.0, 14.0), Cp, li.mean_reference(Cp))
+    pr.gamma_oracle()
+    return pr
+
+
 @pytest.mark.parametrize("M,prec,kind", [(np.diag([125, 125, 5]), "fp64", "dlvp"),
                                          (np.diag([125, 125, 5]), "fp32", "dlvp"),
-                                         (np.diag([125, 125, 125]), "fp64", "dirichlet")])
-def test_basic_scheme_lockstep(lib, M, prec, kind):
+                                         (None, "fp64", "dirichlet")])
+def test_basic_scheme_lockstep(lib, cube125, M, prec, kind):
     params = {"alpha": [0.75] * 3} if kind == "dlvp" else {}
-    pr = Problem(M, kind, params, spheres(2))
+    if M is None:
+        pr = cube125
+        pr.G.set_scheme("ls")
+    else:
+        pr = Problem(M, kind, params, spheres(2))
     assert 125 in pr.G.e
     print(f"odd-size lockstep e={pr.G.e} {kind} {prec}", flush=True)
     pr.bind(prec)
@@ -44,10 +59,13 @@ def test_basic_scheme_lockstep(lib, M, prec, kind):
     assert rel(pr.gpu_E_to_oracle_mandel(res["E"].cpu().numpy()[0]), ref["E"]) < tol
 
 
-@pytest.mark.parametrize("M", [np.diag([125, 125, 5]), np.diag([125, 125, 125])])
-def test_cg_lockstep(lib, M):
-    Cp = np.stack([li.isotropic_voigt(1.0, 0.3), li.isotropic_voigt(50.0, 0.3)])
-    pr = Problem(M, "dirichlet", {}, spheres(3), Cp, li.mean_reference(Cp))
+@pytest.mark.parametrize("M", [np.diag([125, 125, 5]), None])
+def test_cg_lockstep(lib, cube125, M):
+    if M is None:
+        pr = cube125
+    else:
+        Cp = np.stack([li.isotropic_voigt(1.0, 0.3), li.isotropic_voigt(50.0, 0.3)])
+        pr = Problem(M, "dirichlet", {}, spheres(3), Cp, li.mean_reference(Cp))
     pr.G.set_scheme("cg")
     pr.bind("fp64")
     print(f"odd-size CG lockstep e={pr.G.e}", flush=True)
