@@ -654,8 +654,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU kernel path "
-              "(multi-GPU sharding is described in DESIGN.md, not built).", file=sys.stderr)
+        print("bench.py runs on one GPU only: it measures the single-GPU kernel path; "
+              "sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -1154,16 +1154,14 @@ int run_cg(GroupRun<T>& G, double tol, int max_iter, const double* dev_E_init, d
   HIPCHK(hipMemsetAsync(G.w.P[0], 0, fb, st));   // W = 0: the first update leaves x, z as they are
   // z = -G C (x + eps0): the usual passes on x with dmat = C and eps0
   {
-    using T2c = C2<T>;
-    char* base = p->dev_persist;
-    const T2c* tw0 = (const T2c*)(base + p->off_tw[0]);
+    const T2* tw0 = (const T2*)(p->dev_persist + p->off_tw[0]);
     hipLaunchKernelGGL(G.K.a1[MODE_STRESS], G.gridS, dim3(G.K.NT1), G.K.lds1, st, G.g, p->plan[0], tw0,
-                       (const T2c*)G.w.X, (T2c*)G.w.TAU, (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0,
+                       (const T2*)G.w.X, (T2*)G.w.TAU, (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0,
                        (const int*)G.w.stop_iter, (const int*)G.w.itp, (const double*)nullptr,
                        (const double*)nullptr, (double*)nullptr, (double*)nullptr);
-    launch_axis2<T>(G, 0, (const T2c*)G.w.TAU, (T2c*)G.w.TAU, st);
+    launch_axis2<T>(G, 0, (const T2*)G.w.TAU, (T2*)G.w.TAU, st);
     launch_green<T>(G, 0, st);
-    launch_axis2<T>(G, 1, (const T2c*)G.w.P[1], (T2c*)G.w.EX[0], st);
+    launch_axis2<T>(G, 1, (const T2*)G.w.P[1], (T2*)G.w.EX[0], st);
     HIPCHK(hipGetLastError());
   }
   const int check = fixed ? 32 : 8;
