@@ -163,7 +163,15 @@ class TuneResult(ctypes.Structure):
 
 
 class Pattern:
-    """A pattern P(M) with its generating function, stiffness and device data."""
+    """A pattern P(M) with its generating function, stiffness and device data.
+
+    M is 3x3, or 2x2 for a pattern of the plane (plane strain; strains,
+    stresses and stiffness matrices then use the 2-D Voigt order 11, 22, 12,
+    and fields carry 3 components).  Kernels: 'dirichlet',
+    'dirichlet_modified', 'dlvp' ({"alpha": [d values]}) and 'box'
+    ({"Xi": d x s directions, "R": alias radius, "tail": add the aliases
+    beyond R along slow axes}).  Schemes (set_scheme): 'ls', 've', 'cg'.
+    """
 
     def __init__(self, M):
         M = np.asarray(M, dtype=np.int64)

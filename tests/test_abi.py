@@ -192,3 +192,20 @@ def test_plane_errors_host_side(lib):
     with pytest.raises(lib.LshError) as e:
         lib.Pattern(np.diag([4, 4, 4, 4]))                   # d = 4
     assert e.value.status == -1
+
+
+def test_box_tail_and_scheme_arguments(lib):
+    """The Box tail flag must be 0 or 1; unknown schemes are refused."""
+    import ctypes
+    P = lib.Pattern(np.diag([4, 4, 4]))
+    Xi = [1, 0, 0, 1, 0, 1, 0, 1, 0, 0, 1, 0]                 # 3 x 4, row-major
+    for flag, ok in ((0.0, True), (1.0, True), (2.0, False), (0.5, False)):
+        arr = np.array([4.0] + [float(v) for v in Xi] + [8.0, flag])
+        rc = lib._lib.lsh_set_kernel(P._h, 3, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(arr))
+        assert (rc == 0) == ok, (flag, rc)
+    P.set_kernel("box", {"Xi": np.array(Xi, float).reshape(3, 4), "R": 8, "tail": True})
+    with pytest.raises(lib.LshError) as e:
+        lib._check(lib._lib.lsh_set_scheme(P._h, 7))
+    assert e.value.status == -1
+    for sc in ("ls", "ve", "cg"):
+        P.set_scheme(sc)
