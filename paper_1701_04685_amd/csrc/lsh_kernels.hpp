@@ -521,6 +521,17 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
 #define GCH 6
 __host__ __device__ constexpr int gpad(int i) { return i + (i >> 3); }
 
+// The thread index, opaque to the optimiser.  Addresses derived from it are
+// then recomputed where they are used (a few integer operations) instead of
+// being hoisted out of the load loop and held in registers across it, which
+// lowers the Green pass's register peak by about 50 VGPRs and lets it run
+// three waves per SIMD in FP64.  The empty asm emits no instruction.
+__device__ __forceinline__ int g2_tid() {
+  int t;
+  asm volatile("" : "=v"(t) : "0"((int)threadIdx.x));
+  return t;
+}
+
 template <int N> struct GreenPlan {
   static constexpr RadList RH = make_radlist(N / 2);
   // line stride: the padded length plus one, odd, so that the same entry of
@@ -544,7 +555,7 @@ __device__ __forceinline__ void g2_stage(C2<T>* lines, const C2<T>* __restrict__
   constexpr int nu = NLN * nbl;
   constexpr int NB = (nu + NT - 1) / NT;
   constexpr int tstep = N / (NS * R);
-  const int tid = threadIdx.x;
+  const int tid = g2_tid();
   T2 v[NB][R];
   int dst[NB];
 #pragma unroll
@@ -624,8 +635,9 @@ __host__ __device__ constexpr int radprod(RadList L, int upto) {
   return p;
 }
 
-template <typename T, int N, int NL, int NT, int GM>
-__global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* __restrict__ tw, GreenParams gp,
+// MINW asks the compiler for at least that many waves per SIMD.
+template <typename T, int N, int NL, int NT, int GM, int MINW = 1>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW))) k_green2(Geo g, FftPlan pl, const C2<T>* __restrict__ tw, GreenParams gp,
                                                const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
                                                C2<T>* __restrict__ Pnew, const T* __restrict__ table,
                                                const Inst* __restrict__ insts, const int* __restrict__ inst_of,
@@ -675,6 +687,7 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
   constexpr int nuL = NLN * nblL;
   constexpr int NBL = (nuL + NT - 1) / NT;
   auto load0 = [&](int Lb) {
+    const int tid = g2_tid();
     const bool a0 = Lb < Lend && it < stop_iter[Lb];
     const bool a1 = NL == 2 && Lb + 1 < Lend && it < stop_iter[Lb + 1];
 #pragma unroll
@@ -718,6 +731,7 @@ __global__ void __launch_bounds__(NT) k_green2(Geo g, FftPlan pl, const C2<T>* _
   for (int L0 = Lbeg; L0 < Lend; L0 += NL) {
     const bool act0 = it < stop_iter[L0];
     const bool act1 = NL == 2 && L0 + 1 < Lend && it < stop_iter[L0 + 1];
+    const int tid = g2_tid();  // shadows the block-level index inside the loop
     if (!act0 && !act1) {
       load0(L0 + NL);
       continue;
@@ -1051,30 +1065,46 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
 }
 
 // ------------------------------------------------------------ finalisers ---
-__global__ void k_finalize_resid(const double* __restrict__ partial, int nblk, int nload,
-                                 const double* __restrict__ e0sq, double pscale, double tol, int fixed,
-                                 const int* __restrict__ itp, int* __restrict__ stop_iter, double* __restrict__ hist,
-                                 int* __restrict__ nonfinite) {
+__global__ void __launch_bounds__(1024) k_finalize_resid(const double* __restrict__ partial, int nblk, int nload,
+                                                          const double* __restrict__ e0sq, double pscale, double tol,
+                                                          int fixed, int* __restrict__ itp,
+                                                          int* __restrict__ stop_iter, double* __restrict__ hist,
+                                                          int* __restrict__ nonfinite) {
+  // One block per load.  The iteration counter itp[0] is advanced here, by
+  // the block that finishes last (itp[1] counts finished blocks and is back
+  // at 0 when the kernel ends), so every block reads the counter before it
+  // changes and no separate launch is needed.
   const int L = blockIdx.x;
-  const int it = *itp;
-  if (it >= stop_iter[L]) return;
-  double s[2] = {0.0, 0.0};
-  for (int j = threadIdx.x; j < nblk; j += blockDim.x) {
-    s[0] += partial[((long long)L * nblk + j) * 2];
-    s[1] += partial[((long long)L * nblk + j) * 2 + 1];
+  const int it = itp[0];
+  if (it < stop_iter[L]) {
+    // partial sums come in (numerator, denominator) pairs, 16-byte aligned
+    const double2* p2 = reinterpret_cast<const double2*>(partial) + (long long)L * nblk;
+    double s[2] = {0.0, 0.0};
+    for (int j = threadIdx.x; j < nblk; j += blockDim.x) {
+      const double2 q = p2[j];
+      s[0] += q.x;
+      s[1] += q.y;
+    }
+    double out[2];
+    block_sum<2>(s, out);
+    if (threadIdx.x == 0) {
+      const double num = out[0] * pscale;
+      const double den = out[1] * pscale + e0sq[L];
+      const double r = sqrt(num / den);
+      hist[(it % LSH_HIST) * nload + L] = r;
+      if (!isfinite(r)) {
+        nonfinite[L] = 1;
+        stop_iter[L] = it + 1;
+      } else if (!fixed && r <= tol) {
+        stop_iter[L] = it + 1;
+      }
+    }
   }
-  double out[2];
-  block_sum<2>(s, out);
   if (threadIdx.x == 0) {
-    const double num = out[0] * pscale;
-    const double den = out[1] * pscale + e0sq[L];
-    const double r = sqrt(num / den);
-    hist[(it % LSH_HIST) * nload + L] = r;
-    if (!isfinite(r)) {
-      nonfinite[L] = 1;
-      stop_iter[L] = it + 1;
-    } else if (!fixed && r <= tol) {
-      stop_iter[L] = it + 1;
+    __threadfence();
+    if (atomicAdd(&itp[1], 1) == (int)gridDim.x - 1) {
+      itp[1] = 0;
+      itp[0] = it + 1;
     }
   }
 }

@@ -276,16 +276,16 @@ constexpr int green2_nt() {
   return nt < 64 ? 64 : (nt > 512 ? 512 : nt);
 }
 
-template <typename T, int NC, int NL>
+template <typename T, int NC, int NL, int MINW = 1>
 typename KernSet<T>::CGreen green2_cand() {
   constexpr int NT = green2_nt<NC, NL>();
   constexpr RadList RH = GreenPlan<NC>::RH;
   constexpr int RL = RH.r[RH.n - 1];
   typename KernSet<T>::CGreen c;
   c.fn[GREEN_ISO] = nullptr;  // the isotropic path reads the moments table
-  c.fn[GREEN_GENERAL] = k_green2<T, NC, NL, NT, GREEN_GENERAL>;
-  c.fn[GREEN_TABLE] = k_green2<T, NC, NL, NT, GREEN_TABLE>;
-  c.fn[GREEN_MOMENTS] = k_green2<T, NC, NL, NT, GREEN_MOMENTS>;
+  c.fn[GREEN_GENERAL] = k_green2<T, NC, NL, NT, GREEN_GENERAL, MINW>;
+  c.fn[GREEN_TABLE] = k_green2<T, NC, NL, NT, GREEN_TABLE, MINW>;
+  c.fn[GREEN_MOMENTS] = k_green2<T, NC, NL, NT, GREEN_MOMENTS, MINW>;
   c.nt = NT;
   c.lds = sizeof(C2<T>) * (size_t)NC + sizeof(T) * 21 * (size_t)NC + sizeof(C2<T>) * (size_t)NL * 6 * GreenPlan<NC>::LP +
           sizeof(C2<T>) * (size_t)(RL - 1) * (NC / RL);
@@ -298,6 +298,8 @@ void green_special(const Geo& g, KernSet<T>& K) {
   if constexpr (NC % 2 == 0) {
     K.cg.push_back(green2_cand<T, NC, (NC <= 128 ? 2 : 1)>());
     if constexpr (NC <= 128) K.cg.push_back(green2_cand<T, NC, 1>());
+    // FP64, two loads at a time, capped at three waves per SIMD (168 VGPRs)
+    if constexpr (sizeof(T) == 8 && NC <= 128) K.cg.push_back(green2_cand<T, NC, 2, 3>());
     for (size_t i = K.cg.size(); i-- > 0;)
       if (K.cg[i].lds > (size_t)lds_limit()) K.cg.erase(K.cg.begin() + i);
     if (!K.cg.empty()) {
@@ -579,7 +581,7 @@ GroupWS group_layout(const Geo& g, int nload, int ninst, const KernSet<T>& K, ch
   w.means = (double*)(base + off); off += lsh_align(sizeof(double) * 6 * nload);
   w.stop_iter = (int*)(base + off); off += lsh_align(sizeof(int) * nload);
   w.nonfinite = (int*)(base + off); off += lsh_align(sizeof(int) * nload);
-  w.itp = (int*)(base + off); off += lsh_align(sizeof(int));
+  w.itp = (int*)(base + off); off += lsh_align(sizeof(int) * 2);
   w.inst_of = (int*)(base + off); off += lsh_align(sizeof(int) * nload);
   w.chunks = (int*)(base + off); off += lsh_align(sizeof(int) * 2 * nload);
   w.insts = (Inst*)(base + off); off += lsh_align(sizeof(Inst) * ninst);
@@ -776,12 +778,12 @@ int group_init(GroupRun<T>& G, int max_iter, const double* dev_E_init, hipStream
   for (auto* q : G.spec.inst) ins.push_back(inst_of_pattern<T>(q));
   G.stop.assign(nload, max_iter);
   std::vector<int> zeros(nload, 0);
-  const int zero = 0;
+  const int zero2[2] = {0, 0};  // iteration counter, finished-block count
   HIPCHK(hipMemcpyAsync(G.w.eps0, e0.data(), sizeof(double) * 6 * nload, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(G.w.e0sq, e0sq.data(), sizeof(double) * nload, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(G.w.stop_iter, G.stop.data(), sizeof(int) * nload, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(G.w.nonfinite, zeros.data(), sizeof(int) * nload, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(G.w.itp, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(G.w.itp, zero2, sizeof(zero2), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(G.w.inst_of, G.spec.inst_of.data(), sizeof(int) * nload, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(G.w.chunks, G.chunks.data(), sizeof(int) * G.chunks.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(G.w.insts, ins.data(), sizeof(Inst) * ins.size(), hipMemcpyHostToDevice, st));
@@ -863,16 +865,16 @@ int group_iterate(GroupRun<T>& G, int cur, double tol, bool fixed, hipStream_t s
     launch_green<T>(G, cur, st);
   }
   {
-    Timer tm(3, st);
-    hipLaunchKernelGGL(k_finalize_resid, dim3(G.nload), dim3(256), 0, st, (const double*)G.w.partial, G.npos,
-                       G.nload, (const double*)G.w.e0sq, pscale, tol, fixed ? 1 : 0, (const int*)G.w.itp,
-                       G.w.stop_iter, G.w.hist, G.w.nonfinite);
-  }
-  {
     Timer tm(4, st);
     launch_axis2<T>(G, 1, (const T2*)G.w.P[1 - cur], (T2*)G.w.X, st);
   }
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, G.w.itp);
+  {
+    // residual, stop flags and the iteration counter's advance
+    Timer tm(3, st);
+    hipLaunchKernelGGL(k_finalize_resid, dim3(G.nload), dim3(1024), 0, st, (const double*)G.w.partial, G.npos,
+                       G.nload, (const double*)G.w.e0sq, pscale, tol, fixed ? 1 : 0, G.w.itp, G.w.stop_iter,
+                       G.w.hist, G.w.nonfinite);
+  }
   HIPCHK(hipGetLastError());
   return LSH_OK;
 }
