@@ -370,20 +370,31 @@ __global__ void __launch_bounds__(NT) k_axis2(Geo g, FftPlan pl, const C2<T>* __
 // and then hit that XCD's L2.  LDS: twiddles[n3], lines[6][ls].
 // gmode: 0 isotropic C0 (moment form, on the fly), 1 general C0 on the fly,
 // 2 table [pos][21][n3] built at bind time (double sums, stored at T).
-// GREEN_MOMENTS: isotropic C0 with the normalised alias moments (21 per bin,
-// independent of C0) precomputed at bind time in the table slot.
+// GREEN_MOMENTS: isotropic C0 with the normalised alias moments (independent
+// of C0) precomputed at bind time in the table slot: the 15 fourth moments per
+// bin, [pos][15][n3].  The second moments follow from them, since every alias
+// direction n is a unit vector: sum_k n_i n_j n_k n_k = n_i n_j.
 enum { GREEN_ISO = 0, GREEN_GENERAL = 1, GREEN_TABLE = 2, GREEN_MOMENTS = 3 };
 
-// Gamma^p entry row t at bin (pos, k3) from a moments row set [pos][21][n3].
+#define MOM_ROWS 15
+
+// Gamma^p entry row t at bin (pos, k3) from a moments row set [pos][15][n3].
 template <typename T, typename Out>
 __device__ __forceinline__ void moments_emit(const T* __restrict__ table, long long pos, int n3, int k3, double mu0,
                                              double riso, Out&& out) {
-  const T* tb = table + pos * 21 * n3 + k3;
+  const T* tb = table + pos * MOM_ROWS * n3 + k3;
   double a[6], q[15];
 #pragma unroll
-  for (int t = 0; t < 6; ++t) a[t] = (double)tb[(long long)t * n3];
-#pragma unroll
-  for (int t = 0; t < 15; ++t) q[t] = (double)tb[(long long)(6 + t) * n3];
+  for (int t = 0; t < 15; ++t) q[t] = (double)tb[(long long)t * n3];
+  // second moments, pairs (00,11,22,12,02,01): a_ij = sum_k q_ijkk, with q in
+  // the order 0000 0001 0002 0011 0012 0022 0111 0112 0122 0222 1111 1112 1122
+  // 1222 2222
+  a[0] = q[0] + q[3] + q[5];
+  a[1] = q[3] + q[10] + q[12];
+  a[2] = q[5] + q[12] + q[14];
+  a[3] = q[4] + q[11] + q[13];
+  a[4] = q[2] + q[7] + q[9];
+  a[5] = q[1] + q[6] + q[8];
   iso_emit(a, q, mu0, riso, out);
 }
 template <typename T, int NC, int NT>
@@ -1358,8 +1369,8 @@ __global__ void k_gamma_table(Geo g, GreenParams gp, T* __restrict__ table, doub
   }
 }
 
-// One thread per half-spectrum bin: the normalised alias moments (isotropic C0
-// path), stored at T in the table layout [pos][21][n3] (6 second, 15 fourth).
+// One thread per half-spectrum bin: the normalised fourth alias moments
+// (isotropic C0 path), stored at T in the layout [pos][15][n3].
 template <typename T>
 __global__ void k_moments_table(Geo g, GreenParams gp, T* __restrict__ table) {
   const long long nb = g.spec;
@@ -1371,9 +1382,7 @@ __global__ void k_moments_table(Geo g, GreenParams gp, T* __restrict__ table) {
     iso_moments(gp, k1, k2, k3, M);
     const long long pos = i / g.n3;
 #pragma unroll
-    for (int t = 0; t < 6; ++t) table[(pos * 21 + t) * g.n3 + k3] = (T)M.a[t];
-#pragma unroll
-    for (int t = 0; t < 15; ++t) table[(pos * 21 + 6 + t) * g.n3 + k3] = (T)M.q[t];
+    for (int t = 0; t < MOM_ROWS; ++t) table[(pos * MOM_ROWS + t) * g.n3 + k3] = (T)M.q[t];
   }
 }
 

@@ -296,10 +296,12 @@ template <typename T, int NC>
 void green_special(const Geo& g, KernSet<T>& K) {
   K.cg.clear();
   if constexpr (NC % 2 == 0) {
+    // FP64 at n3 = 128: two loads at a time capped at three waves per SIMD
+    // (168 VGPRs, no spills; the uncapped build takes 170 and runs two).  At
+    // the other lengths the cap either changes nothing or spills.
+    if constexpr (sizeof(T) == 8 && NC == 128) K.cg.push_back(green2_cand<T, NC, 2, 3>());
     K.cg.push_back(green2_cand<T, NC, (NC <= 128 ? 2 : 1)>());
     if constexpr (NC <= 128) K.cg.push_back(green2_cand<T, NC, 1>());
-    // FP64, two loads at a time, capped at three waves per SIMD (168 VGPRs)
-    if constexpr (sizeof(T) == 8 && NC <= 128) K.cg.push_back(green2_cand<T, NC, 2, 3>());
     for (size_t i = K.cg.size(); i-- > 0;)
       if (K.cg[i].lds > (size_t)lds_limit()) K.cg.erase(K.cg.begin() + i);
     if (!K.cg.empty()) {
@@ -419,8 +421,9 @@ int green_mode(const lsh_pattern* p) {
 }
 
 bool kind_has_table(const lsh_pattern* p) {
-  // the table slot holds Gamma^p rows (GREEN_TABLE) or alias moments
-  // (GREEN_MOMENTS); before the stiffness is known, size for it
+  // the table slot (21 rows per bin) holds Gamma^p rows (GREEN_TABLE) or the
+  // 15 fourth alias moments (GREEN_MOMENTS); before the stiffness is known,
+  // size for it
   if (p->nphase < 1) return true;
   const int gm = green_mode(p);
   return gm == GREEN_TABLE || gm == GREEN_MOMENTS;
