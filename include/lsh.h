@@ -286,8 +286,14 @@ int lsh_solve_batch(const lsh_task *tasks, int ntask, double tol, int max_iter, 
  * every launch and read back at the solver's own synchronisation points.
  * Slots: 0 axis-1 stress pass, 1 axis-2 forward, 2 Green pass (axis 3),
  * 3 residual reduction, 4 axis-2 inverse, 5 final effective-stress pass.
- * lsh_profile_enable(1) clears the counters; process-wide, not thread-safe.   */
+ * lsh_profile_enable(1) clears the counters and times every slot; process-wide,
+ * not thread-safe.  lsh_profile_select(mask) then limits the timing to the slots
+ * whose bit is set (bit i = slot i): each timed launch adds two event records to
+ * the stream, and with them a few microseconds of idle time between kernels.
+ * lsh_profile_read copies the first n slots (n <= 8) of the accumulated
+ * milliseconds and launch counts.                                              */
 int lsh_profile_enable(int on);
+int lsh_profile_select(unsigned mask);
 int lsh_profile_read(double *ms, long long *counts, int n);
 
 /* Thread-local message for the last non-zero status returned on this thread.      */

@@ -450,6 +450,7 @@ size_t persistent_bytes_t(const lsh_pattern* p, size_t scal) {
 
 struct Profile {
   bool on = false;
+  unsigned mask = ~0u;  // slots timed while on
   double ms[8] = {0};
   long long n[8] = {0};
 };
@@ -630,15 +631,16 @@ struct Timer {
   hipEvent_t a{}, b{};
   int slot;
   hipStream_t st;
-  Timer(int s, hipStream_t stream) : slot(s), st(stream) {
-    if (g_prof.on) {
+  bool rec;
+  Timer(int s, hipStream_t stream) : slot(s), st(stream), rec(g_prof.on && ((g_prof.mask >> s) & 1u)) {
+    if (rec) {
       a = g_ev.get();
       b = g_ev.get();
       (void)hipEventRecord(a, st);
     }
   }
   ~Timer() {
-    if (g_prof.on) {
+    if (rec) {
       (void)hipEventRecord(b, st);
       g_ev.pending.push_back({slot, a, b});
     }
@@ -1489,6 +1491,11 @@ extern "C" int lsh_tune_reset(lsh_pattern* p) {
 extern "C" int lsh_profile_enable(int on) {
   g_prof = Profile();
   g_prof.on = on != 0;
+  return LSH_OK;
+}
+
+extern "C" int lsh_profile_select(unsigned mask) {
+  g_prof.mask = mask;
   return LSH_OK;
 }
 

@@ -27,7 +27,7 @@ STATUS = {0: "LSH_OK", -1: "LSH_EINVAL", -2: "LSH_ESINGULAR", -3: "LSH_ENOINTERP
 EXPORTS = ["lsh_create_pattern", "lsh_destroy", "lsh_pattern_info", "lsh_pattern_snf", "lsh_pattern_points",
            "lsh_set_kernel", "lsh_set_stiffness", "lsh_persistent_bytes", "lsh_bind", "lsh_gamma_probe",
            "lsh_solve_bytes", "lsh_solve", "lsh_batch_bytes", "lsh_solve_batch", "lsh_profile_enable",
-           "lsh_profile_read", "lsh_last_error", "lsh_autotune", "lsh_tune_reset", "lsh_tune_set", "lsh_set_scheme", "lsh_unet_create", "lsh_unet_destroy", "lsh_unet_param_count",
+           "lsh_profile_select", "lsh_profile_read", "lsh_last_error", "lsh_autotune", "lsh_tune_reset", "lsh_tune_set", "lsh_set_scheme", "lsh_unet_create", "lsh_unet_destroy", "lsh_unet_param_count",
            "lsh_unet_param_bytes", "lsh_unet_bind", "lsh_unet_get_params", "lsh_unet_act_bytes",
            "lsh_unet_train_step", "lsh_unet_zero_grad", "lsh_unet_get_grads", "lsh_unet_predict", "lsh_unet_head",
            "lsh_unet_layers", "lsh_unet_pack_target"]
@@ -75,6 +75,7 @@ _sig = {
     "lsh_solve_batch": ([ctypes.POINTER(Task), ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P,
                          ctypes.c_size_t, _P], ctypes.c_int),
     "lsh_profile_enable": ([ctypes.c_int], ctypes.c_int),
+    "lsh_profile_select": ([ctypes.c_uint], ctypes.c_int),
     "lsh_profile_read": ([_DP, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int], ctypes.c_int),
     "lsh_last_error": ([], ctypes.c_char_p),
     "lsh_autotune": ([_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t, _P, _P], ctypes.c_int),
@@ -389,6 +390,15 @@ def batch_workspace_bytes(patterns, nloads, precision="fp32"):
 
 def profile_enable(on=True):
     _check(_lib.lsh_profile_enable(1 if on else 0))
+
+
+def profile_select(slots):
+    """Time only the given slots (0 stress, 1 axis-2 forward, 2 Green pass,
+    3 residual, 4 axis-2 inverse, 5 final stress) while profiling is on."""
+    mask = 0
+    for i in slots:
+        mask |= 1 << int(i)
+    _check(_lib.lsh_profile_select(mask))
 
 
 def profile_read():
