@@ -276,6 +276,27 @@ def test_workspace_too_small_rejected():
     assert e.value.status == -8
 
 
+def test_profile_select_times_only_chosen_passes():
+    """lsh_profile_select limits the event timing to the chosen slots;
+    lsh_profile_enable times every slot again."""
+    from paper_1701_04685_amd import lsh
+    pr = Problem(np.diag([8, 8, 8]), "dirichlet", {}, random_phase(15))
+    pr.bind("fp64")
+    lsh.profile_enable(True)
+    try:
+        lsh.profile_select([2])
+        pr.G.solve(np.eye(6)[:1], tol=-1.0, max_iter=5)
+        ms, cnt = lsh.profile_read()
+        assert cnt[2] == 5 and ms[2] > 0
+        assert all(cnt[i] == 0 for i in range(8) if i != 2), cnt
+        lsh.profile_enable(True)
+        pr.G.solve(np.eye(6)[:1], tol=-1.0, max_iter=2)
+        ms, cnt = lsh.profile_read()
+        assert list(cnt[:6]) == [2, 2, 2, 2, 2, 1], cnt
+    finally:
+        lsh.profile_enable(False)
+
+
 # ------------------------------------------------------ full-size configs ---
 def test_cfg2_fullsize_lockstep_3_iterations():
     """128^3, dlVP alpha = 3/4, centred sphere f = 0.2, contrast 10, six loads in
