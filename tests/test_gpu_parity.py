@@ -308,7 +308,10 @@ def test_cfg2_fullsize_lockstep_3_iterations():
                  lambda Y: li.sphere_phase(Y, np.zeros(3), r))
     pr.bind("fp64")
     loads = np.eye(6)
-    res = pr.G.solve(loads, tol=-1.0, max_iter=3, return_E=True)
+    import torch
+    ws = torch.empty(pr.G.workspace_bytes(6), dtype=torch.uint8, device="cuda")
+    pr.G.autotune(nload=6, workspace=ws)  # the variants the benchmark runs: the autotuner's choice
+    res = pr.G.solve(loads, tol=-1.0, max_iter=3, return_E=True, workspace=ws)
     for j in (0, 4):
         ref = pr.oracle_solve(loads[j], n_iter=3)
         assert rel(res["sigma"][j], ref["sigma_voigt"]) < FP64_TOL
