@@ -779,8 +779,8 @@ def main():
         "per_kernel_warmup": per_kernel,
         "bytes_per_voxel_iter_algorithmic": round(bytes_per_vi, 1),
         "hbm_roofline_voxel_iters_per_s": HBM_PEAK_GBS * 1e9 / bytes_per_vi,
-        # the method's minimum, a three-pass schedule (42 s + 1 bytes, s = 8): not
-        # reachable here, its middle pass would need a whole 2-D plane on chip
+        # the method's minimum, a three-pass schedule (42 s + 1 bytes, s = 8); the
+        # schedule built here has four passes (54 s + 1)
         "step_frac_of_three_pass_minimum": round(value * (42 * 8 + 1) / (HBM_PEAK_GBS * 1e9), 4),
         "solve_to_tol": solve_info,
         "fp32_vs_fp64": fp32,
