@@ -397,7 +397,10 @@ __device__ __forceinline__ void moments_emit(const T* __restrict__ table, long l
   a[5] = q[1] + q[6] + q[8];
   iso_emit(a, q, mu0, riso, out);
 }
-template <typename T, int NC, int NT>
+// GM >= 0 fixes the Green mode at compile time (only that branch is built,
+// which keeps the register count of the table and moment paths low); -1
+// switches on the gmode argument.
+template <typename T, int NC, int NT, int GM = -1>
 __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __restrict__ tw, GreenParams gp,
                                               const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
                                               C2<T>* __restrict__ Pnew, const T* __restrict__ table,
@@ -428,14 +431,15 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
   stage_twiddles<T>(twl, tw, n3);
   // tau lines (and the table rows) first, all loads in flight together
   if constexpr (NC > 0) {
+    // every entry assigned (zero past the end): with conditional
+    // assignments the array stayed on the stack and each load waited for
+    // its scratch store
     T2 r[ET];
 #pragma unroll
     for (int i = 0; i < ET; ++i) {
       const int idx = tid + i * NT;
-      if ((6 * NC) % NT == 0 || idx < ne) {
-        const int c = idx / NC, k3 = idx % NC;
-        r[i] = tau[((long long)(L * 6 + c)) * g.spec + row + k3];
-      }
+      const int c = idx / NC, k3 = idx % NC;
+      r[i] = ((6 * NC) % NT == 0 || idx < ne) ? tau[((long long)(L * 6 + c)) * g.spec + row + k3] : T2{0, 0};
     }
 #pragma unroll
     for (int i = 0; i < ET; ++i) {
@@ -450,17 +454,18 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
   }
   __syncthreads();
   fft_any<T, -1, NC, 6, false, NT>(lines, pl, ls, 1, twl);
+  const int gmd = GM >= 0 ? GM : gmode;
   for (int k3 = tid; k3 < n3; k3 += NT) {
     T G[21];
-    if (gmode == GREEN_TABLE) {
+    if (gmd == GREEN_TABLE) {
       const T* tb = table + (long long)pos * 21 * n3 + k3;
 #pragma unroll
       for (int t = 0; t < 21; ++t) G[t] = (T)(scale * (double)tb[(long long)t * n3]);
-    } else if (gmode == GREEN_MOMENTS) {
+    } else if (gmd == GREEN_MOMENTS) {
       moments_emit(table, pos, n3, k3, mu0, riso, [&](int t, double v) { G[t] = (T)(scale * v); });
     } else {
       double Gd[21];
-      if (gmode == GREEN_ISO)
+      if (gmd == GREEN_ISO)
         gamma_sym_iso(gp, mu0, riso, k1, k2, k3, Gd);
       else
         gamma_sym_at(gp, k1, k2, k3, Gd);
@@ -488,7 +493,8 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
 #pragma unroll
     for (int i = 0; i < ET; ++i) {
       const int idx = tid + i * NT;
-      if ((6 * NC) % NT == 0 || idx < ne) po[i] = Pold[((long long)(L * 6 + idx / NC)) * g.spec + row + idx % NC];
+      po[i] = ((6 * NC) % NT == 0 || idx < ne) ? Pold[((long long)(L * 6 + idx / NC)) * g.spec + row + idx % NC]
+                                                : T2{0, 0};
     }
   }
   __syncthreads();

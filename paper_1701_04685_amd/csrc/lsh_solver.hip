@@ -316,6 +316,14 @@ void green_special(const Geo& g, KernSet<T>& K) {
   }
   constexpr int NT = NC <= 64 ? 64 : (NC <= 128 ? 128 : 256);
   K.gr = k_green<T, NC, NT>;
+  if constexpr (NC % 2 == 1) {
+    // odd lengths: one build per Green mode (the moment and table paths
+    // then hold about 100 VGPRs instead of the on-the-fly paths' 220)
+    K.gr2[GREEN_ISO] = k_green<T, NC, NT, GREEN_ISO>;
+    K.gr2[GREEN_GENERAL] = k_green<T, NC, NT, GREEN_GENERAL>;
+    K.gr2[GREEN_TABLE] = k_green<T, NC, NT, GREEN_TABLE>;
+    K.gr2[GREEN_MOMENTS] = k_green<T, NC, NT, GREEN_MOMENTS>;
+  }
   K.NTG = NT;
   (void)g;
 }
@@ -716,6 +724,7 @@ void apply_choice(KernSet<T>& K, int gmode, const int ch[3]) {
     K.ldsG = c.lds;
   }
   if (K.green2) K.gr = K.gr2[gmode];
+  else if (K.gr2[gmode]) K.gr = K.gr2[gmode];
 }
 
 inline int prec_index(const lsh_pattern* p) { return p->bound_prec == LSH_FP32_MIXED ? 1 : 0; }
