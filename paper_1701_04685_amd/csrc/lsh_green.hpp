@@ -24,6 +24,9 @@ struct GreenParams {
   int R;             // Box spline: alias box [-R, R]^3
   int flat3;         // two-dimensional pattern: the third axis carries no aliases
   int tail;          // Box spline: add the aliases beyond R along the slow axes
+  int xi_int;        // Box spline: every direction has integer entries
+  int iso;           // C0 isotropic: Gamma0 = S(n)/mu0 - riso Q(n) (see below)
+  double mu0, riso;
   int nslow;         // slow axes: one direction with a unit entry there, all others zero
   int slow_axis[3];
   int slow_col[3];
@@ -77,10 +80,14 @@ __device__ __forceinline__ void mandel_pair(int I, int& a, int& b) {
 // acc += w * Gamma0_k (21 entries).  k need not be normalised.
 __device__ inline void add_gamma0(const GreenParams& gp, const double k[3], double w, double acc[21]) {
   double K[3][3];
+#pragma unroll
   for (int i = 0; i < 3; ++i)
+#pragma unroll
     for (int mm = 0; mm < 3; ++mm) {
       double s = 0.0;
+#pragma unroll
       for (int j = 0; j < 3; ++j)
+#pragma unroll
         for (int l = 0; l < 3; ++l) s += gp.C0[((i * 3 + j) * 3 + l) * 3 + mm] * k[j] * k[l];
       K[i][mm] = s;
     }
@@ -101,12 +108,14 @@ __device__ inline void add_gamma0(const GreenParams& gp, const double k[3], doub
   N[1][2] = (K[0][2] * K[1][0] - K[0][0] * K[1][2]) * id;
   N[2][2] = (K[0][0] * K[1][1] - K[0][1] * K[1][0]) * id;
   const double SQ2 = 1.41421356237309504880168872420969808;
-  int t = 0;
+#pragma unroll
   for (int I = 0; I < 6; ++I) {
     int a, b;
     mandel_pair(I, a, b);
     const double cI = I < 3 ? 1.0 : SQ2;
-    for (int J = I; J < 6; ++J, ++t) {
+#pragma unroll
+    for (int J = I; J < 6; ++J) {
+      const int t = tri_idx(I, J);
       int c, d;
       mandel_pair(J, c, d);
       const double cJ = J < 3 ? 1.0 : SQ2;
@@ -141,119 +150,6 @@ __device__ inline double kernel_weight(const GreenParams& gp, const double x[3])
     if (u != 0.0) g *= sinpi(u) / (3.14159265358979323846264338327950288 * u);
   }
   return g * g;
-}
-
-// Box spline, the aliases beyond [-R, R] along a slow axis i: only the
-// direction xi* varies along the line z_perp + t e_i, and the weight the line
-// keeps outside |t| <= R is w_perp (1 - sum_{|n| <= R} sinc^2(pi (c + n))),
-// c = xi*^T (x + z_perp), by the identity sum_n sinc^2(pi (c + n)) = 1.  There
-// k = h + M^T z turns towards M^T e_i, so those aliases carry Gamma0 of M^T e_i
-// (the term odd in 1/t cancels between the half-lines; what remains is
-// O(R^-3) against O(R^-1) for plain truncation).
-__device__ inline void box_tail(const GreenParams& gp, const double x0[3], int r, double acc[21], double* den) {
-  const double PI = 3.14159265358979323846264338327950288;
-  for (int a = 0; a < gp.nslow; ++a) {
-    const int i = gp.slow_axis[a], sc = gp.slow_col[a];
-    const int j0 = i == 0 ? 1 : 0, j1 = i == 2 ? 1 : 2;
-    const int r0 = (gp.flat3 && j0 == 2) ? 0 : r, r1 = (gp.flat3 && j1 == 2) ? 0 : r;
-    double tw = 0.0;
-    for (int u = -r0; u <= r0; ++u)
-      for (int v = -r1; v <= r1; ++v) {
-        double y[3] = {x0[0], x0[1], x0[2]};
-        y[j0] += u;
-        y[j1] += v;
-        double wp = 1.0;
-        for (int s = 0; s < gp.nxi; ++s) {
-          if (s == sc) continue;
-          const double t = gp.Xi[3 * s] * y[0] + gp.Xi[3 * s + 1] * y[1] + gp.Xi[3 * s + 2] * y[2];
-          if (t != 0.0) {
-            const double g = sinpi(t) / (PI * t);
-            wp *= g * g;
-          }
-        }
-        if (wp <= 0.0) continue;
-        const double c = gp.Xi[3 * sc] * y[0] + gp.Xi[3 * sc + 1] * y[1] + gp.Xi[3 * sc + 2] * y[2];
-        const double sp = sinpi(c);
-        double line;
-        if (sp == 0.0) {  // c an integer: one term of the line carries the whole weight
-          line = fabs(rint(c)) <= (double)r ? 1.0 : 0.0;
-        } else {
-          double q2 = 0.0;
-          for (int m = -r; m <= r; ++m) {
-            const double q = c + m;
-            q2 += 1.0 / (q * q);
-          }
-          line = sp * sp * q2 / (PI * PI);
-        }
-        tw += wp * (1.0 - line);
-      }
-    if (tw != 0.0) {
-      const double kd[3] = {(double)gp.MT[i], (double)gp.MT[3 + i], (double)gp.MT[6 + i]};
-      add_gamma0(gp, kd, tw, acc);
-      *den += tw;
-    }
-  }
-}
-
-// Weighted alias sum for the representative h_rep (x_num its M^{-T} numerator):
-// acc = sum_z w Gamma0, returns sum_z w.  z over {-1,0,1}^3 (modified
-// Dirichlet, dlVP), {0} (Dirichlet) or [-R,R]^3 (Box); z3 = 0 only for a
-// two-dimensional pattern (its third weight factor vanishes at every z3 != 0).
-__device__ inline double alias_sum(const GreenParams& gp, const int64_t hr[3], const int64_t xn[3], double acc[21]) {
-  for (int t = 0; t < 21; ++t) acc[t] = 0.0;
-  const double invm = 1.0 / (double)gp.m;
-  const double x0[3] = {(double)xn[0] * invm, (double)xn[1] * invm, (double)xn[2] * invm};
-  int r = 0;
-  if (gp.kind == 1 || gp.kind == 2) r = 1;
-  if (gp.kind == 3) r = gp.R;
-  const int r2 = gp.flat3 ? 0 : r;
-  double den = 0.0;
-  for (int z0 = -r; z0 <= r; ++z0)
-    for (int z1 = -r; z1 <= r; ++z1)
-      for (int z2 = -r2; z2 <= r2; ++z2) {
-        const double x[3] = {x0[0] + z0, x0[1] + z1, x0[2] + z2};
-        const double w = kernel_weight(gp, x);
-        if (w <= 0.0) continue;
-        const int64_t kk[3] = {hr[0] + gp.MT[0] * z0 + gp.MT[1] * z1 + gp.MT[2] * z2,
-                               hr[1] + gp.MT[3] * z0 + gp.MT[4] * z1 + gp.MT[5] * z2,
-                               hr[2] + gp.MT[6] * z0 + gp.MT[7] * z1 + gp.MT[8] * z2};
-        den += w;
-        if (kk[0] == 0 && kk[1] == 0 && kk[2] == 0) continue;  // Gamma0_0 = 0
-        const double kd[3] = {(double)kk[0], (double)kk[1], (double)kk[2]};
-        add_gamma0(gp, kd, w, acc);
-      }
-  if (gp.kind == 3 && gp.tail) box_tail(gp, x0, r, acc, &den);
-  return den;
-}
-
-// Hermitian-symmetrised Gamma^p at SNF bin b (b1 may be any index mod e1).
-// Returns the bracket sum of the weights at b (0 => translates degenerate).
-__device__ inline double gamma_sym_at(const GreenParams& gp, int64_t b0, int64_t b1, int64_t b2, double G[21]) {
-  const int64_t b[3] = {b0, b1, b2};
-  int64_t h[3];
-  for (int i = 0; i < 3; ++i) h[i] = gp.VT[3 * i] * b[0] + gp.VT[3 * i + 1] * b[1] + gp.VT[3 * i + 2] * b[2];
-  int64_t hr[3], xn[3];
-  reduce_freq(gp, h, hr, xn);
-  if (hr[0] == 0 && hr[1] == 0 && hr[2] == 0) {
-    for (int t = 0; t < 21; ++t) G[t] = 0.0;
-    return 1.0;
-  }
-  const bool face = (2 * xn[0] == -gp.m) || (2 * xn[1] == -gp.m) || (2 * xn[2] == -gp.m);
-  const double den = alias_sum(gp, hr, xn, G);
-  for (int t = 0; t < 21; ++t) G[t] /= den;
-  // the even kernels on the faces of the modified Dirichlet / dlVP family are
-  // already symmetric (their alias set is mirrored); Dirichlet and the
-  // truncated Box sum are not.
-  if (face && (gp.kind == 0 || gp.kind == 3)) {
-    const int64_t hm[3] = {-hr[0], -hr[1], -hr[2]};
-    int64_t hr2[3], xn2[3];
-    reduce_freq(gp, hm, hr2, xn2);
-    double G2[21];
-    const double den2 = alias_sum(gp, hr2, xn2, G2);
-    for (int t = 0; t < 21; ++t) G[t] = 0.5 * (G[t] + G2[t] / den2);
-    return den < den2 ? den : den2;
-  }
-  return den;
 }
 
 // ------------------------------------------------------ isotropic C0 path ---
@@ -466,4 +362,160 @@ __device__ inline void gamma_iso_emit(const GreenParams& gp, double mu0, double 
 __device__ inline void gamma_sym_iso(const GreenParams& gp, double mu0, double r, int64_t b0, int64_t b1, int64_t b2,
                                      double G[21]) {
   gamma_iso_emit(gp, mu0, r, b0, b1, b2, [&](int t, double v) { G[t] = v; });
+}
+
+// Box spline, the aliases beyond [-R, R] along a slow axis i: only the
+// direction xi* varies along the line z_perp + t e_i, and the weight the line
+// keeps outside |t| <= R is w_perp (1 - sum_{|n| <= R} sinc^2(pi (c + n))),
+// c = xi*^T (x + z_perp), by the identity sum_n sinc^2(pi (c + n)) = 1.  There
+// k = h + M^T z turns towards M^T e_i, so those aliases carry Gamma0 of M^T e_i
+// (the term odd in 1/t cancels between the half-lines; what remains is
+// O(R^-3) against O(R^-1) for plain truncation).
+template <typename Add>
+__device__ inline void box_tail(const GreenParams& gp, const double x0[3], int r, Add&& add, double* den) {
+  const double PI = 3.14159265358979323846264338327950288;
+  for (int a = 0; a < gp.nslow; ++a) {
+    const int i = gp.slow_axis[a], sc = gp.slow_col[a];
+    const int j0 = i == 0 ? 1 : 0, j1 = i == 2 ? 1 : 2;
+    const int r0 = (gp.flat3 && j0 == 2) ? 0 : r, r1 = (gp.flat3 && j1 == 2) ? 0 : r;
+    double tw = 0.0;
+    for (int u = -r0; u <= r0; ++u)
+      for (int v = -r1; v <= r1; ++v) {
+        double y[3] = {x0[0], x0[1], x0[2]};
+        y[j0] += u;
+        y[j1] += v;
+        double wp = 1.0;
+        for (int s = 0; s < gp.nxi; ++s) {
+          if (s == sc) continue;
+          const double t = gp.Xi[3 * s] * y[0] + gp.Xi[3 * s + 1] * y[1] + gp.Xi[3 * s + 2] * y[2];
+          if (t != 0.0) {
+            const double g = sinpi(t) / (PI * t);
+            wp *= g * g;
+          }
+        }
+        if (wp <= 0.0) continue;
+        const double c = gp.Xi[3 * sc] * y[0] + gp.Xi[3 * sc + 1] * y[1] + gp.Xi[3 * sc + 2] * y[2];
+        const double sp = sinpi(c);
+        double line;
+        if (sp == 0.0) {  // c an integer: one term of the line carries the whole weight
+          line = fabs(rint(c)) <= (double)r ? 1.0 : 0.0;
+        } else {
+          double q2 = 0.0;
+          for (int m = -r; m <= r; ++m) {
+            const double q = c + m;
+            q2 += 1.0 / (q * q);
+          }
+          line = sp * sp * q2 / (PI * PI);
+        }
+        tw += wp * (1.0 - line);
+      }
+    if (tw != 0.0) {
+      const double kd[3] = {(double)gp.MT[i], (double)gp.MT[3 + i], (double)gp.MT[6 + i]};
+      add(kd, tw);
+      *den += tw;
+    }
+  }
+}
+
+// Weighted alias sum for the representative h_rep (x_num its M^{-T} numerator):
+// acc = sum_z w Gamma0, returns sum_z w.  With an isotropic C0 the sum runs
+// over the alias directions' moments, and Gamma0's closed form is applied once
+// at the end (Gamma0 is linear in them).  z over {-1,0,1}^3 (modified
+// Dirichlet, dlVP), {0} (Dirichlet) or [-R,R]^3 (Box); z3 = 0 only for a
+// two-dimensional pattern (its third weight factor vanishes at every z3 != 0).
+// ISO: 1 moment form, 0 general form, -1 chosen by gp.iso at run time.
+template <int ISO = -1>
+__device__ inline double alias_sum(const GreenParams& gp, const int64_t hr[3], const int64_t xn[3], double acc[21]) {
+  const bool iso = ISO >= 0 ? ISO == 1 : gp.iso != 0;
+  for (int t = 0; t < 21; ++t) acc[t] = 0.0;
+  const double invm = 1.0 / (double)gp.m;
+  const double x0[3] = {(double)xn[0] * invm, (double)xn[1] * invm, (double)xn[2] * invm};
+  int r = 0;
+  if (gp.kind == 1 || gp.kind == 2) r = 1;
+  if (gp.kind == 3) r = gp.R;
+  const int r2 = gp.flat3 ? 0 : r;
+  // Box spline with integer directions: xi^T z is an integer, so every alias
+  // has the same sin^2(pi xi^T x) and only the denominators (pi xi^T x)^2 vary.
+  // sq = prod_s sin^2(pi xi_s^T x0); 0 when some xi_s^T x0 is an integer,
+  // where the direct form below decides which aliases keep weight.
+  double sq = 0.0;
+  if (gp.kind == 3 && gp.xi_int) {
+    sq = 1.0;
+    for (int s = 0; s < gp.nxi; ++s) {
+      const double sp = sinpi(gp.Xi[3 * s] * x0[0] + gp.Xi[3 * s + 1] * x0[1] + gp.Xi[3 * s + 2] * x0[2]);
+      sq *= sp * sp;
+    }
+  }
+  double den = 0.0;
+  IsoMoments M;
+  if (iso) {
+    for (int t = 0; t < 6; ++t) M.a[t] = 0.0;
+    for (int t = 0; t < 15; ++t) M.q[t] = 0.0;
+    M.w = 0.0;
+  }
+  auto add = [&](const double kd[3], double w) {
+    if (iso)
+      iso_add(M, kd, w);
+    else
+      add_gamma0(gp, kd, w, acc);
+  };
+  for (int z0 = -r; z0 <= r; ++z0)
+    for (int z1 = -r; z1 <= r; ++z1)
+      for (int z2 = -r2; z2 <= r2; ++z2) {
+        const double x[3] = {x0[0] + z0, x0[1] + z1, x0[2] + z2};
+        double w;
+        if (sq > 0.0) {
+          double pr = 1.0;
+          for (int s = 0; s < gp.nxi; ++s) {
+            const double u = 3.14159265358979323846264338327950288 *
+                             (gp.Xi[3 * s] * x[0] + gp.Xi[3 * s + 1] * x[1] + gp.Xi[3 * s + 2] * x[2]);
+            pr *= u * u;
+          }
+          w = sq / pr;
+        } else {
+          w = kernel_weight(gp, x);
+        }
+        if (w <= 0.0) continue;
+        const int64_t kk[3] = {hr[0] + gp.MT[0] * z0 + gp.MT[1] * z1 + gp.MT[2] * z2,
+                               hr[1] + gp.MT[3] * z0 + gp.MT[4] * z1 + gp.MT[5] * z2,
+                               hr[2] + gp.MT[6] * z0 + gp.MT[7] * z1 + gp.MT[8] * z2};
+        den += w;
+        if (kk[0] == 0 && kk[1] == 0 && kk[2] == 0) continue;  // Gamma0_0 = 0
+        const double kd[3] = {(double)kk[0], (double)kk[1], (double)kk[2]};
+        add(kd, w);
+      }
+  if (gp.kind == 3 && gp.tail) box_tail(gp, x0, r, add, &den);
+  if (iso) iso_emit(M.a, M.q, gp.mu0, gp.riso, [&](int t, double v) { acc[t] = v; });
+  return den;
+}
+
+// Hermitian-symmetrised Gamma^p at SNF bin b (b1 may be any index mod e1).
+// Returns the bracket sum of the weights at b (0 => translates degenerate).
+template <int ISO = -1>
+__device__ inline double gamma_sym_at(const GreenParams& gp, int64_t b0, int64_t b1, int64_t b2, double G[21]) {
+  const int64_t b[3] = {b0, b1, b2};
+  int64_t h[3];
+  for (int i = 0; i < 3; ++i) h[i] = gp.VT[3 * i] * b[0] + gp.VT[3 * i + 1] * b[1] + gp.VT[3 * i + 2] * b[2];
+  int64_t hr[3], xn[3];
+  reduce_freq(gp, h, hr, xn);
+  if (hr[0] == 0 && hr[1] == 0 && hr[2] == 0) {
+    for (int t = 0; t < 21; ++t) G[t] = 0.0;
+    return 1.0;
+  }
+  const bool face = (2 * xn[0] == -gp.m) || (2 * xn[1] == -gp.m) || (2 * xn[2] == -gp.m);
+  const double den = alias_sum<ISO>(gp, hr, xn, G);
+  for (int t = 0; t < 21; ++t) G[t] /= den;
+  // the even kernels on the faces of the modified Dirichlet / dlVP family are
+  // already symmetric (their alias set is mirrored); Dirichlet and the
+  // truncated Box sum are not.
+  if (face && (gp.kind == 0 || gp.kind == 3)) {
+    const int64_t hm[3] = {-hr[0], -hr[1], -hr[2]};
+    int64_t hr2[3], xn2[3];
+    reduce_freq(gp, hm, hr2, xn2);
+    double G2[21];
+    const double den2 = alias_sum<ISO>(gp, hr2, xn2, G2);
+    for (int t = 0; t < 21; ++t) G[t] = 0.5 * (G[t] + G2[t] / den2);
+    return den < den2 ? den : den2;
+  }
+  return den;
 }

@@ -242,8 +242,28 @@ void lsh_green_params(const lsh_pattern* p, GreenParams* gp) {
       gp->A[3 * i + j] = (p->det > 0 ? 1 : -1) * p->adjM[3 * j + i];
     }
   for (int i = 0; i < 3; ++i) gp->alpha[i] = p->alpha[i];
-  for (int i = 0; i < 3 * LSH_MAX_XI; ++i) gp->Xi[i] = p->Xi[i];
+  gp->xi_int = 1;
+  for (int i = 0; i < 3 * LSH_MAX_XI; ++i) {
+    gp->Xi[i] = p->Xi[i];
+    if (p->Xi[i] != floor(p->Xi[i])) gp->xi_int = 0;
+  }
   lsh_voigt_to_tensor(p->C0_voigt, gp->C0);
+  // isotropic C0 (to 1e-13 of its largest entry) with mu0 > 0, lam0 + 2 mu0 > 0
+  const double* C = p->C0_voigt;
+  const double lam = C[1], mu = C[21];
+  double mx = 0.0;
+  for (int i = 0; i < 36; ++i) mx = fmax(mx, fabs(C[i]));
+  bool iso = mu > 0.0 && lam + 2.0 * mu > 0.0;
+  for (int I = 0; I < 6 && iso; ++I)
+    for (int J = 0; J < 6; ++J) {
+      double want = 0.0;
+      if (I < 3 && J < 3) want = lam + (I == J ? 2.0 * mu : 0.0);
+      if (I >= 3 && I == J) want = mu;
+      if (fabs(C[6 * I + J] - want) > 1e-13 * mx) iso = false;
+    }
+  gp->iso = iso ? 1 : 0;
+  gp->mu0 = iso ? mu : 1.0;
+  gp->riso = iso ? (lam + mu) / (mu * (lam + 2.0 * mu)) : 0.0;
 }
 
 // ------------------------------------------------------------------ the ABI

@@ -1350,8 +1350,9 @@ __global__ void __launch_bounds__(NT) k_cg_stress(Geo g, FftPlan pl, const C2<T>
 
 // ---------------------------------------------------------- Gamma table ---
 // One thread per half-spectrum bin: the alias sums in double, stored at T.
-template <typename T>
-__global__ void k_gamma_table(Geo g, GreenParams gp, T* __restrict__ table, double* __restrict__ minden) {
+template <typename T, int ISO>
+__global__ void __launch_bounds__(256) k_gamma_table(Geo g, GreenParams gp, T* __restrict__ table,
+                                                     double* __restrict__ minden) {
   const long long nb = g.spec;
   double mn = 1e300;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (long long)gridDim.x * blockDim.x) {
@@ -1359,7 +1360,7 @@ __global__ void k_gamma_table(Geo g, GreenParams gp, T* __restrict__ table, doub
     const int k2 = (int)((i / g.n3) % g.n2);
     const int k1 = (int)(i / ((long long)g.n2 * g.n3));
     double G[21];
-    const double den = gamma_sym_at(gp, k1, k2, k3, G);
+    const double den = gamma_sym_at<ISO>(gp, k1, k2, k3, G);
     mn = fmin(mn, den);
     const long long pos = i / g.n3;
     for (int t = 0; t < 21; ++t) table[(pos * 21 + t) * g.n3 + k3] = (T)G[t];
@@ -1378,7 +1379,7 @@ __global__ void k_gamma_table(Geo g, GreenParams gp, T* __restrict__ table, doub
 // One thread per half-spectrum bin: the normalised fourth alias moments
 // (isotropic C0 path), stored at T in the layout [pos][15][n3].
 template <typename T>
-__global__ void k_moments_table(Geo g, GreenParams gp, T* __restrict__ table) {
+__global__ void __launch_bounds__(256) k_moments_table(Geo g, GreenParams gp, T* __restrict__ table) {
   const long long nb = g.spec;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (long long)gridDim.x * blockDim.x) {
     const int k3 = (int)(i % g.n3);
@@ -1402,7 +1403,7 @@ __global__ void k_moments_probe(const T* __restrict__ table, double* __restrict_
   moments_emit(table, pos, g.n3, (int)bins[3 * i + 2], mu0, riso, [&](int t, double v) { out[21 * i + t] = v; });
 }
 
-__global__ void k_gamma_probe(GreenParams gp, const long long* __restrict__ bins, int n, double* __restrict__ out,
+__global__ void __launch_bounds__(128) k_gamma_probe(GreenParams gp, const long long* __restrict__ bins, int n, double* __restrict__ out,
                               int gmode, double mu0, double riso) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;

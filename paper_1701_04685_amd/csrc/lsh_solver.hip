@@ -523,7 +523,11 @@ int bind_t(lsh_pattern* p, void* dev, size_t bytes, hipStream_t st) {
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(st));
     } else {
-      hipLaunchKernelGGL(k_gamma_table<T>, dim3(nblk), dim3(nthr), 0, st, g, gp, table, mins_dev);
+      // isotropic C0: the alias sums run over direction moments
+      if (gp.iso)
+        hipLaunchKernelGGL((k_gamma_table<T, 1>), dim3(nblk), dim3(nthr), 0, st, g, gp, table, mins_dev);
+      else
+        hipLaunchKernelGGL((k_gamma_table<T, 0>), dim3(nblk), dim3(nthr), 0, st, g, gp, table, mins_dev);
       HIPCHK(hipGetLastError());
       std::vector<double> mins(nblk);
       HIPCHK(hipMemcpyAsync(mins.data(), mins_dev, sizeof(double) * nblk, hipMemcpyDeviceToHost, st));
