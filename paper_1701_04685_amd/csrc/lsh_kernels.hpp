@@ -325,11 +325,28 @@ __global__ void __launch_bounds__(NT) k_axis2(Geo g, FftPlan pl, const C2<T>* __
   const int n2 = NC > 0 ? NC : g.n2;
   T2* twl = reinterpret_cast<T2*>(smem_raw);
   T2* Z = twl + n2;
-  const int L = blockIdx.z, c = blockIdx.y;
-  if (stop_iter && *itp >= stop_iter[L]) return;
+  // The grid is (h1 * ntile3, 6, nload).  The forward pass takes its blocks in
+  // dispatch order k1 downwards, every tile, component and load of one k1
+  // before the next: the Green pass reads positions upwards from k1 = 0, so
+  // the planes written last are the first it reads.  The inverse pass keeps
+  // the load-major order (neighbouring blocks on neighbouring tiles).
   const int ntile3 = (g.n3 + W - 1) / W;
-  const int k1 = blockIdx.x / ntile3;
-  const int a30 = (blockIdx.x % ntile3) * W;
+  int k1, a30, c, L;
+  if constexpr (DIR < 0) {
+    const long long per_k1 = (long long)ntile3 * 6 * gridDim.z;
+    const long long lin = blockIdx.x + (long long)gridDim.x * (blockIdx.y + 6LL * blockIdx.z);
+    k1 = g.h1 - 1 - (int)(lin / per_k1);
+    const int inner = (int)(lin % per_k1);
+    a30 = (inner % ntile3) * W;
+    c = (inner / ntile3) % 6;
+    L = inner / (ntile3 * 6);
+  } else {
+    L = blockIdx.z;
+    c = blockIdx.y;
+    k1 = blockIdx.x / ntile3;
+    a30 = (blockIdx.x % ntile3) * W;
+  }
+  if (stop_iter && *itp >= stop_iter[L]) return;
   const long long base = ((long long)(L * 6 + c)) * g.spec + (long long)k1 * n2 * g.n3 + a30;
   const int tid = threadIdx.x;
   const int ne = n2 * W;
