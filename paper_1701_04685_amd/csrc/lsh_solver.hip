@@ -283,7 +283,9 @@ typename KernSet<T>::CGreen green2_cand() {
   constexpr int RL = RH.r[RH.n - 1];
   typename KernSet<T>::CGreen c;
   c.fn[GREEN_ISO] = nullptr;  // the isotropic path reads the moments table
-  c.fn[GREEN_GENERAL] = k_green2<T, NC, NL, NT, GREEN_GENERAL, MINW>;
+  // the on-the-fly general form needs more registers than a wave cap leaves
+  // (capped at three waves it spills): always the uncapped build
+  c.fn[GREEN_GENERAL] = k_green2<T, NC, NL, NT, GREEN_GENERAL, 1>;
   c.fn[GREEN_TABLE] = k_green2<T, NC, NL, NT, GREEN_TABLE, MINW>;
   c.fn[GREEN_MOMENTS] = k_green2<T, NC, NL, NT, GREEN_MOMENTS, MINW>;
   c.nt = NT;
