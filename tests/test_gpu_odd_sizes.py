@@ -75,3 +75,35 @@ def test_cg_lockstep(lib, cube125, M):
     assert rel(res["sigma"][0], ref["sigma_voigt"]) < 1e-10
     assert rel(pr.gpu_E_to_oracle_mandel(res["E"].cpu().numpy()[0]), ref["E"]) < 1e-10
     np.testing.assert_allclose(res["history"][0], ref["history"], rtol=1e-8, atol=1e-15)
+
+
+def _anisotropic_C0():
+    """An elliptic, cubic-anisotropic reference stiffness (not isotropic)."""
+    C = li.isotropic_voigt(4.0, 0.25)
+    C[0, 1] = C[1, 0] = C[0, 1] + 0.3
+    C[3, 3] += 0.4
+    C[5, 5] -= 0.2
+    return C
+
+
+@pytest.mark.parametrize("kind,params,aniso,prec", [
+    ("dirichlet", {}, True, "fp64"),                                   # general form on the fly
+    ("dlvp", {"alpha": [0.75] * 3}, True, "fp64"),                     # table, general alias sums
+    ("box", {"Xi": np.array([[1, 0, 0, 1], [0, 1, 0, 1], [0, 0, 1, 0]], float), "R": 2}, False, "fp64"),
+    ("box", {"Xi": np.array([[1, 0, 0, 1], [0, 1, 0, 1], [0, 0, 1, 0]], float), "R": 2}, False, "fp32"),
+])
+def test_odd_length_green_modes_lockstep(lib, kind, params, aniso, prec):
+    """The odd-length Green pass in its table and general modes (the moment
+    mode is covered above): diag(125, 5, 5) puts 125 on the axis-3 pass."""
+    Cp = np.stack([li.isotropic_voigt(1.0, 0.3), li.isotropic_voigt(10.0, 0.3)])
+    C0 = _anisotropic_C0() if aniso else li.mean_reference(Cp)
+    pr = Problem(np.diag([125, 5, 5]), kind, params, spheres(5, 0.5, 1.0), Cp, C0)
+    assert pr.G.e[2] == 125
+    print(f"odd-length Green mode {kind} aniso={aniso} {prec} e={pr.G.e}", flush=True)
+    pr.bind(prec)
+    n = 4
+    ref = pr.oracle_solve(EPS0, n_iter=n)
+    res = pr.G.solve(EPS0[None], tol=-1.0, max_iter=n, return_E=True)
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert rel(res["sigma"][0], ref["sigma_voigt"]) < tol
+    assert rel(pr.gpu_E_to_oracle_mandel(res["E"].cpu().numpy()[0]), ref["E"]) < tol
