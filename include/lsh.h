@@ -264,13 +264,25 @@ int lsh_tune_set(lsh_pattern *p, lsh_precision prec, const int *choice);
  *   eps0_voigt : host nload*6 macroscopic strains; sigma_out host nload*6
  *                (nload*3 each for d = 2; tasks of 2-D and 3-D patterns may mix).
  *   stats      : optional host nload entries.
- * No start field and no field output in batch mode.                               */
+ *   dev_E_init : optional device double [nload][6][m] start fluctuation of this
+ *                task (Voigt, engineering shear; [nload][3][m] for d = 2), mean
+ *                removed per load as in lsh_solve; NULL = zero start.  Tasks with
+ *                and without a start field may mix in one call (a warm start for
+ *                some microstructures of a batch).
+ *   dev_E_out  : optional device double [nload][6][m] ([nload][3][m] for d = 2)
+ *                receiving this task's final E; NULL = none.
+ * Both fields are double at either precision: the start field is read once per
+ * solve and the output written once, against hundreds of iterations on the
+ * state, so the boundary keeps the widest type and the FP32 path converts on
+ * the device.  Both must stay alive until lsh_solve_batch returns.               */
 typedef struct {
   lsh_pattern *p;
   int nload;
   const double *eps0_voigt;
   double *sigma_out;
   lsh_stats *stats;
+  const double *dev_E_init;
+  double *dev_E_out;
 } lsh_task;
 
 /* Workspace bytes for lsh_solve_batch over these tasks.                            */

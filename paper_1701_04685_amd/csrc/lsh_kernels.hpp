@@ -110,8 +110,8 @@ k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
                                               const C2<T>* __restrict__ X, C2<T>* __restrict__ Y,
                                               const Inst* __restrict__ insts, const int* __restrict__ inst_of,
                                               const double* __restrict__ eps0, const int* __restrict__ stop_iter,
-                                              const int* __restrict__ itp, const double* __restrict__ Einit,
-                                              const double* __restrict__ means, double* __restrict__ Eout,
+                                              const int* __restrict__ itp, const double* const* __restrict__ Einit,
+                                              const double* __restrict__ means, double* const* __restrict__ Eout,
                                               double* __restrict__ partial) {
   using T2 = C2<T>;
   constexpr int W3 = 3 * W;
@@ -242,6 +242,8 @@ k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
     }
   } else if (MODE == MODE_INIT) {
     const double SQ2I = 0.70710678118654752440;
+    // this load's start field (the caller's [ncf][m] block), or none: zero start
+    const double* __restrict__ El = Einit[L];
     for (int idx = tid; idx < n1 * W; idx += NT) {
       const int w = idx % W, a1 = idx / W;
       double E[6] = {0, 0, 0, 0, 0, 0};
@@ -249,7 +251,7 @@ k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
         const long long pt = (long long)a1 * n23 + colbase + w;
         for (int c = 0; c < 6; ++c) {
           const int bc = boundary_comp(c, g.ncf);
-          const double v = bc < 0 ? 0.0 : Einit[((long long)(L * g.ncf + bc)) * g.m + pt] * (c < 3 ? 1.0 : SQ2I);
+          const double v = (bc < 0 || !El) ? 0.0 : El[(long long)bc * g.m + pt] * (c < 3 ? 1.0 : SQ2I);
           // the solver keeps X = D1[E] / n1 (D1: unnormalised DFT along axis 1)
           E[c] = (v - means[6 * L + c]) / (double)n1;
         }
@@ -262,6 +264,8 @@ k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
   } else {  // MODE_FINAL: sigma = C(y):(E + eps0) summed in double, optional E out
     const double* e0 = eps0 + 6 * L;
     const double SQ2 = 1.41421356237309504880;
+    // this load's field output (the caller's [ncf][m] block), if requested
+    double* __restrict__ Eo = Eout ? Eout[L] : nullptr;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int idx = tid; idx < n1 * W; idx += NT) {
       const int w = idx % W, a1 = idx / W;
@@ -276,10 +280,10 @@ k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
         for (int J = 0; J < 6; ++J) s += Cm[6 * I + J] * (E[J] + e0[J]);
         acc[I] += s;
       }
-      if (Eout)
+      if (Eo)
         for (int c = 0; c < 6; ++c) {
           const int bc = boundary_comp(c, g.ncf);
-          if (bc >= 0) Eout[((long long)(L * g.ncf + bc)) * g.m + pt] = E[c] * (c < 3 ? 1.0 : SQ2);
+          if (bc >= 0) Eo[(long long)bc * g.m + pt] = E[c] * (c < 3 ? 1.0 : SQ2);
         }
     }
     block_sum<6>(acc, partial + ((long long)L * gridDim.x + blockIdx.x) * 6);
@@ -930,8 +934,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
                                                const C2<T>* __restrict__ X, C2<T>* __restrict__ Y,
                                                const Inst* __restrict__ insts, const int* __restrict__ inst_of,
                                                const double* __restrict__ eps0, const int* __restrict__ stop_iter,
-                                               const int* __restrict__ itp, const double* __restrict__ Einit,
-                                               const double* __restrict__ means, double* __restrict__ Eout,
+                                               const int* __restrict__ itp, const double* const* __restrict__ Einit,
+                                               const double* __restrict__ means, double* const* __restrict__ Eout,
                                                double* __restrict__ partial) {
   using T2 = C2<T>;
   (void)pl;
@@ -1143,6 +1147,12 @@ __global__ void __launch_bounds__(1024) k_finalize_resid(const double* __restric
   }
 }
 
+// n 8-byte words set to zero (clears state buffers with a kernel, not a
+// runtime memset node)
+__global__ void __launch_bounds__(256) k_zero(unsigned long long* __restrict__ p, long long n) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) p[i] = 0ull;
+}
+
 // end of an iteration: advance the device-side iteration counter
 __global__ void k_advance(int* itp) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *itp += 1;
@@ -1158,15 +1168,17 @@ __global__ void k_finalize_sum(const double* __restrict__ partial, int nblk, int
   if (threadIdx.x == 0) out[L * nv + i] = scale * o[0];
 }
 
-// mean of the Mandel components of a start field (ncf components per load),
-// per (load, comp) block; components the field does not carry have mean 0
-__global__ void k_mean(const double* __restrict__ E, long long m, int ncf, double* __restrict__ means) {
+// mean of the Mandel components of a start field (ncf components per load,
+// one [ncf][m] block per load, null for a zero start), per (load, comp) block;
+// components the field does not carry have mean 0
+__global__ void k_mean(const double* const* __restrict__ Eptr, long long m, int ncf, double* __restrict__ means) {
   const int L = blockIdx.x, c = blockIdx.y;
   const double f = c < 3 ? 1.0 : 0.70710678118654752440;
   const int bc = boundary_comp(c, ncf);
+  const double* __restrict__ E = Eptr[L];
   double s[1] = {0.0};
-  if (bc >= 0)
-    for (long long i = threadIdx.x; i < m; i += blockDim.x) s[0] += E[((long long)(L * ncf + bc)) * m + i];
+  if (bc >= 0 && E)
+    for (long long i = threadIdx.x; i < m; i += blockDim.x) s[0] += E[(long long)bc * m + i];
   double o[1];
   block_sum<1>(s, o);
   if (threadIdx.x == 0) means[6 * L + c] = f * o[0] / (double)m;

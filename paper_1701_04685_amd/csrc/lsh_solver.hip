@@ -81,7 +81,7 @@ int lds_limit() {
 template <typename T>
 struct KernSet {
   using A1 = void (*)(Geo, FftPlan, const C2<T>*, const C2<T>*, C2<T>*, const Inst*, const int*, const double*,
-                      const int*, const int*, const double*, const double*, double*, double*);
+                      const int*, const int*, const double* const*, const double*, double* const*, double*);
   using A2 = void (*)(Geo, FftPlan, const C2<T>*, const C2<T>*, C2<T>*, const int*, const int*, T);
   using GR = void (*)(Geo, FftPlan, const C2<T>*, GreenParams, const C2<T>*, const C2<T>*, C2<T>*, const T*,
                       const Inst*, const int*, const int*, const int*, const int*, int, int, double*, int, int, int);
@@ -561,6 +561,8 @@ struct GroupWS {
   double* hist;
   double* sigma;
   double* means;
+  const double** einit;  // per load: the caller's start field ([ncf][m] block) or null
+  double** eout;         // per load: where the final field goes, or null
   int* stop_iter;
   int* nonfinite;
   int* itp;
@@ -597,6 +599,8 @@ GroupWS group_layout(const Geo& g, int nload, int ninst, const KernSet<T>& K, ch
   w.hist = (double*)(base + off); off += lsh_align(sizeof(double) * LSH_HIST * nload);
   w.sigma = (double*)(base + off); off += lsh_align(sizeof(double) * 6 * nload);
   w.means = (double*)(base + off); off += lsh_align(sizeof(double) * 6 * nload);
+  w.einit = (const double**)(base + off); off += lsh_align(sizeof(double*) * nload);
+  w.eout = (double**)(base + off); off += lsh_align(sizeof(double*) * nload);
   w.stop_iter = (int*)(base + off); off += lsh_align(sizeof(int) * nload);
   w.nonfinite = (int*)(base + off); off += lsh_align(sizeof(int) * nload);
   w.itp = (int*)(base + off); off += lsh_align(sizeof(int) * 2);
@@ -687,6 +691,8 @@ struct GroupSpec {
   std::vector<double*> sigma_out;     // per load: 6 doubles
   std::vector<lsh_stats*> stats;      // per load (may be null)
   std::vector<double*> history;       // per load: max_iter doubles (may be null)
+  std::vector<const double*> einit;   // per load: device start field [ncf][m] (may be null)
+  std::vector<double*> eout;          // per load: device field output [ncf][m] (may be null)
 };
 
 template <typename T>
@@ -779,9 +785,18 @@ int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
   return LSH_OK;
 }
 
+// Clear `bytes` (a multiple of 8) of device memory on `st` with a fill kernel.
+int zero_async(void* ptr, size_t bytes, hipStream_t st) {
+  const long long n = (long long)(bytes / 8);
+  const int nblk = (int)std::min<long long>((n + 255) / 256, 4096);
+  if (n > 0) hipLaunchKernelGGL(k_zero, dim3(nblk), dim3(256), 0, st, (unsigned long long*)ptr, n);
+  HIPCHK(hipGetLastError());
+  return LSH_OK;
+}
+
 // Upload per-load constants and clear the state (zero start) or transform a start field.
 template <typename T>
-int group_init(GroupRun<T>& G, int max_iter, const double* dev_E_init, hipStream_t st) {
+int group_init(GroupRun<T>& G, int max_iter, hipStream_t st) {
   using T2 = C2<T>;
   const int nload = G.nload;
   std::vector<double> e0(6 * nload), e0sq(nload);
@@ -812,18 +827,24 @@ int group_init(GroupRun<T>& G, int max_iter, const double* dev_E_init, hipStream
   char* base = p->dev_persist;
   const T2* tw0 = (const T2*)(base + p->off_tw[0]);
   const T2* tw1 = (const T2*)(base + p->off_tw[1]);
-  if (dev_E_init) {
-    hipLaunchKernelGGL(k_mean, dim3(nload, 6), dim3(1024), 0, st, dev_E_init, (long long)G.g.m, G.g.ncf, G.w.means);
+  bool any_init = false;
+  for (const double* e : G.spec.einit) any_init = any_init || e != nullptr;
+  if (any_init) {
+    // loads without a start field start from zero (a null entry)
+    HIPCHK(hipMemcpyAsync(G.w.einit, G.spec.einit.data(), sizeof(double*) * nload, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_mean, dim3(nload, 6), dim3(1024), 0, st, (const double* const*)G.w.einit, (long long)G.g.m,
+                       G.g.ncf, G.w.means);
     hipLaunchKernelGGL(G.K.a1[MODE_INIT], G.gridS, dim3(G.K.NT1), G.K.lds1, st, G.g, p->plan[0], tw0,
                        (const T2*)nullptr, (T2*)G.w.X, (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0,
-                       (const int*)G.w.stop_iter, (const int*)G.w.itp, dev_E_init, (const double*)G.w.means,
-                       (double*)nullptr, (double*)nullptr);
+                       (const int*)G.w.stop_iter, (const int*)G.w.itp, (const double* const*)G.w.einit,
+                       (const double*)G.w.means, (double* const*)nullptr, (double*)nullptr);
     hipLaunchKernelGGL(G.K.a2[0], G.gridB, dim3(G.K.NT2), G.K.lds2, st, G.g, p->plan[1], tw1, (const T2*)G.w.X,
                        (T2*)G.w.P[0], (const int*)nullptr, (const int*)nullptr, (T)(1.0 / G.g.n2));
     HIPCHK(hipGetLastError());
   } else {
-    HIPCHK(hipMemsetAsync(G.w.X, 0, fb, st));
-    HIPCHK(hipMemsetAsync(G.w.P[0], 0, fb, st));
+    int rc = zero_async(G.w.X, fb, st);
+    if (!rc) rc = zero_async(G.w.P[0], fb, st);
+    if (rc) return rc;
   }
   G.ring.assign(LSH_HIST * nload, NAN);
   return LSH_OK;
@@ -840,8 +861,8 @@ void launch_stress(GroupRun<T>& G, hipStream_t st) {
   hipLaunchKernelGGL(G.K.a1s, G.gridS1, dim3(G.K.NT1s), G.K.lds1s, st, G.g, p->plan[0], tw0, (const T2*)G.w.X,
                      (T2*)G.w.TAU,
                      (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0, (const int*)G.w.stop_iter,
-                     (const int*)G.w.itp, (const double*)nullptr, (const double*)nullptr, (double*)nullptr,
-                     (double*)nullptr);
+                     (const int*)G.w.itp, (const double* const*)nullptr, (const double*)nullptr,
+                     (double* const*)nullptr, (double*)nullptr);
 }
 
 template <typename T>
@@ -986,19 +1007,24 @@ int group_poll(GroupRun<T>& G, int done, int max_iter, hipStream_t st, bool* all
 
 // Final pass: sigma_bar at the last iterate (and E out), stats; returns a status.
 template <typename T>
-int group_finish(GroupRun<T>& G, int done, double tol, bool fixed, double secs, double* dev_E_out, hipStream_t st) {
+int group_finish(GroupRun<T>& G, int done, double tol, bool fixed, double secs, hipStream_t st) {
   using T2 = C2<T>;
   const lsh_pattern* p = G.spec.rep;
   char* base = p->dev_persist;
   const T2* tw0 = (const T2*)(base + p->off_tw[0]);
   std::vector<int> nonfin(G.nload, 0);
   HIPCHK(hipMemcpyAsync(nonfin.data(), G.w.nonfinite, sizeof(int) * G.nload, hipMemcpyDeviceToHost, st));
+  bool any_out = false;
+  for (double* e : G.spec.eout) any_out = any_out || e != nullptr;
+  if (any_out)
+    HIPCHK(hipMemcpyAsync(G.w.eout, G.spec.eout.data(), sizeof(double*) * G.nload, hipMemcpyHostToDevice, st));
   {
     Timer tm(5, st);
     hipLaunchKernelGGL(G.K.a1[MODE_FINAL], G.gridS, dim3(G.K.NT1), G.K.lds1, st, G.g, p->plan[0], tw0,
                        (const T2*)G.w.X, (T2*)nullptr, (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0,
-                       (const int*)G.w.stop_iter, (const int*)G.w.itp, (const double*)nullptr,
-                       (const double*)nullptr, dev_E_out, G.w.partial);
+                       (const int*)G.w.stop_iter, (const int*)G.w.itp, (const double* const*)nullptr,
+                       (const double*)nullptr, any_out ? (double* const*)G.w.eout : (double* const*)nullptr,
+                       G.w.partial);
     hipLaunchKernelGGL(k_finalize_sum, dim3(G.nload, 6), dim3(256), 0, st, (const double*)G.w.partial, G.nblkS, 6,
                        1.0 / (double)G.g.m, G.w.sigma);
   }
@@ -1038,20 +1064,19 @@ int group_finish(GroupRun<T>& G, int done, double tol, bool fixed, double secs, 
 // iteration counter and the stop flags live on the device, so a replay after
 // a load has converged only runs early-exit blocks for it.
 template <typename T>
-int run_groups(std::vector<GroupRun<T>>& groups, double tol, int max_iter, const double* dev_E_init,
-               double* dev_E_out, hipStream_t st) {
+int run_groups(std::vector<GroupRun<T>>& groups, double tol, int max_iter, hipStream_t st, bool graphs = true) {
   const bool fixed = tol < 0.0;
   for (auto& G : groups) {
     for (auto* h : G.spec.history)
       if (h)
         for (int j = 0; j < max_iter; ++j) h[j] = NAN;
-    int rc = group_init<T>(G, max_iter, dev_E_init, st);
+    int rc = group_init<T>(G, max_iter, st);
     if (rc) return rc;
   }
   const int check = fixed ? 32 : 8;
   const auto t0 = std::chrono::steady_clock::now();
   int done = 0;
-  bool use_graph = !g_prof.on && st != nullptr;
+  bool use_graph = graphs && !g_prof.on && st != nullptr;
   hipGraphExec_t gexec = nullptr;
   if (use_graph) {
     hipGraph_t graph = nullptr;
@@ -1102,7 +1127,7 @@ int run_groups(std::vector<GroupRun<T>>& groups, double tol, int max_iter, const
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   int status = LSH_OK;
   for (auto& G : groups) {
-    int rc = group_finish<T>(G, done, tol, fixed, secs, dev_E_out, st);
+    int rc = group_finish<T>(G, done, tol, fixed, secs, st);
     if (rc == LSH_ENONFINITE || (rc && status == LSH_OK)) status = rc;
   }
   if (status == LSH_ENONFINITE) return lsh_fail(status, "non-finite residual (NaN/Inf) in the iteration");
@@ -1157,13 +1182,13 @@ int cg_iterate(GroupRun<T>& G, double tol, bool fixed, hipStream_t st) {
 }
 
 template <typename T>
-int run_cg(GroupRun<T>& G, double tol, int max_iter, const double* dev_E_init, double* dev_E_out, hipStream_t st) {
+int run_cg(GroupRun<T>& G, double tol, int max_iter, hipStream_t st) {
   using T2 = C2<T>;
   const bool fixed = tol < 0.0;
   for (auto* h : G.spec.history)
     if (h)
       for (int j = 0; j < max_iter; ++j) h[j] = NAN;
-  int rc = group_init<T>(G, max_iter, dev_E_init, st);  // x = X: zero or the start field
+  int rc = group_init<T>(G, max_iter, st);  // x = X: zero or the start field
   if (rc) return rc;
   const lsh_pattern* p = G.spec.rep;
   const size_t fb = sizeof(T2) * 6 * (size_t)G.nload * G.g.spec;
@@ -1172,15 +1197,16 @@ int run_cg(GroupRun<T>& G, double tol, int max_iter, const double* dev_E_init, d
   std::vector<double> cg0(4 * G.nload, 0.0);
   HIPCHK(hipMemcpyAsync(G.w.C0m, c0m, sizeof(c0m), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(G.w.cg, cg0.data(), sizeof(double) * cg0.size(), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemsetAsync(G.w.EX[1], 0, fb, st));  // p = 0
-  HIPCHK(hipMemsetAsync(G.w.P[0], 0, fb, st));   // W = 0: the first update leaves x, z as they are
+  rc = zero_async(G.w.EX[1], fb, st);           // p = 0
+  if (!rc) rc = zero_async(G.w.P[0], fb, st);  // W = 0: the first update leaves x, z as they are
+  if (rc) return rc;
   // z = -G C (x + eps0): the usual passes on x with dmat = C and eps0
   {
     const T2* tw0 = (const T2*)(p->dev_persist + p->off_tw[0]);
     hipLaunchKernelGGL(G.K.a1[MODE_STRESS], G.gridS, dim3(G.K.NT1), G.K.lds1, st, G.g, p->plan[0], tw0,
                        (const T2*)G.w.X, (T2*)G.w.TAU, (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0,
-                       (const int*)G.w.stop_iter, (const int*)G.w.itp, (const double*)nullptr,
-                       (const double*)nullptr, (double*)nullptr, (double*)nullptr);
+                       (const int*)G.w.stop_iter, (const int*)G.w.itp, (const double* const*)nullptr,
+                       (const double*)nullptr, (double* const*)nullptr, (double*)nullptr);
     launch_axis2<T>(G, 0, (const T2*)G.w.TAU, (T2*)G.w.TAU, st);
     launch_green<T>(G, 0, st);
     launch_axis2<T>(G, 1, (const T2*)G.w.P[1], (T2*)G.w.EX[0], st);
@@ -1203,7 +1229,7 @@ int run_cg(GroupRun<T>& G, double tol, int max_iter, const double* dev_E_init, d
     if (all) break;
   }
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  int status = group_finish<T>(G, done, tol, fixed, secs, dev_E_out, st);
+  int status = group_finish<T>(G, done, tol, fixed, secs, st);
   if (status == LSH_ENONFINITE) return lsh_fail(status, "non-finite residual (NaN/Inf) in the iteration");
   if (status == LSH_ENOTCONVERGED) return lsh_fail(status, "max_iter reached before the Cauchy residual met tol");
   return status;
@@ -1222,7 +1248,7 @@ void push_eps0(const lsh_pattern* p, const double* eps0_voigt, int L, std::vecto
 template <typename T>
 int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int max_iter, void* dev_ws,
             size_t ws_bytes, hipStream_t st, const double* dev_E_init, double* dev_E_out, double* sigma_out,
-            lsh_stats* stats, double* history) {
+            lsh_stats* stats, double* history, bool graphs = true) {
   std::vector<GroupRun<T>> groups(1);
   GroupSpec& S = groups[0].spec;
   S.rep = p;
@@ -1233,15 +1259,18 @@ int solve_t(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int
     S.sigma_out.push_back(sigma_out + (p->d == 2 ? 3 : 6) * L);
     S.stats.push_back(stats ? stats + L : nullptr);
     S.history.push_back(history ? history + (long long)L * max_iter : nullptr);
+    const long long fl = (long long)L * (p->d == 2 ? 3 : 6) * p->m;  // one load's [ncf][m] block
+    S.einit.push_back(dev_E_init ? dev_E_init + fl : nullptr);
+    S.eout.push_back(dev_E_out ? dev_E_out + fl : nullptr);
   }
   size_t used = 0;
   int rc = group_prepare<T>(groups[0], (char*)dev_ws, dev_ws ? ws_bytes : 0, &used);
   if (rc) return rc;
   if (p->scheme == LSH_SCHEME_CG) {
     if (!groups[0].K.a1cg) return lsh_fail(LSH_EUNSUPPORTED, "conjugate gradients: no kernel for this SNF grid");
-    return run_cg<T>(groups[0], tol, max_iter, dev_E_init, dev_E_out, st);
+    return run_cg<T>(groups[0], tol, max_iter, st);
   }
-  return run_groups<T>(groups, tol, max_iter, dev_E_init, dev_E_out, st);
+  return run_groups<T>(groups, tol, max_iter, st, graphs);
 }
 
 // Batched solve: tasks grouped by SNF grid, M and generating function.
@@ -1287,6 +1316,9 @@ int build_groups(const lsh_task* tasks, int ntask, int max_iter, std::vector<Gro
       S.sigma_out.push_back(tk.sigma_out + (tk.p->d == 2 ? 3 : 6) * L);
       S.stats.push_back(tk.stats ? tk.stats + L : nullptr);
       S.history.push_back(nullptr);
+      const long long fl = (long long)L * (tk.p->d == 2 ? 3 : 6) * tk.p->m;
+      S.einit.push_back(tk.dev_E_init ? tk.dev_E_init + fl : nullptr);
+      S.eout.push_back(tk.dev_E_out ? tk.dev_E_out + fl : nullptr);
     }
   }
   (void)max_iter;
@@ -1324,7 +1356,7 @@ int solve_batch_t(const lsh_task* tasks, int ntask, double tol, int max_iter, vo
     base += used;
     left -= used;
   }
-  return run_groups<T>(groups, tol, max_iter, nullptr, nullptr, st);
+  return run_groups<T>(groups, tol, max_iter, st);
 }
 
 template <typename T>
@@ -1415,9 +1447,9 @@ extern "C" int lsh_solve_bytes(const lsh_pattern* p, int nload, lsh_precision pr
   return LSH_OK;
 }
 
-extern "C" int lsh_solve(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int max_iter,
-                         lsh_precision prec, void* dev_ws, size_t ws_bytes, void* stream, const double* dev_E_init,
-                         double* dev_E_out, double* sigma_out, lsh_stats* stats, double* history) {
+// Argument checks of lsh_solve.
+static int check_solve_args(const lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int max_iter,
+                            lsh_precision prec, const double* sigma_out) {
   if (!p || !eps0_voigt || !sigma_out) return lsh_fail(LSH_EINVAL, "null argument");
   if (nload < 1 || nload > 64) return lsh_fail(LSH_EINVAL, "nload must be in [1, 64]");
   if (max_iter < 1) return lsh_fail(LSH_EINVAL, "max_iter must be >= 1");
@@ -1428,6 +1460,14 @@ extern "C" int lsh_solve(lsh_pattern* p, int nload, const double* eps0_voigt, do
   if (p->bound_prec != (int)prec) return lsh_fail(LSH_ESTATE, "pattern not bound at this precision (lsh_bind)");
   if (p->scheme == LSH_SCHEME_CG && (p->kind != LSH_DIRICHLET || p->m % 2 == 0))
     return lsh_fail(LSH_EUNSUPPORTED, "conjugate gradients need the Dirichlet kernel on a pattern of odd m");
+  return LSH_OK;
+}
+
+extern "C" int lsh_solve(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int max_iter,
+                         lsh_precision prec, void* dev_ws, size_t ws_bytes, void* stream, const double* dev_E_init,
+                         double* dev_E_out, double* sigma_out, lsh_stats* stats, double* history) {
+  const int rc = check_solve_args(p, nload, eps0_voigt, tol, max_iter, prec, sigma_out);
+  if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   if (prec == LSH_FP64)
     return solve_t<double>(p, nload, eps0_voigt, tol, max_iter, dev_ws, ws_bytes, st, dev_E_init, dev_E_out,
@@ -1456,7 +1496,7 @@ int autotune_t(lsh_pattern* p, int nload, void* dev_ws, size_t ws_bytes, hipStre
   size_t used = 0;
   int rc = group_prepare<T>(G, (char*)dev_ws, dev_ws ? ws_bytes : 0, &used);
   if (rc) return rc;
-  rc = group_init<T>(G, 1, nullptr, st);
+  rc = group_init<T>(G, 1, st);
   if (rc) return rc;
   int choice[3] = {0, 0, 0}, ncand[3] = {1, 1, 1};
   float ms[3][LSH_TUNE_MAX] = {{0}};
@@ -1548,3 +1588,4 @@ extern "C" int lsh_solve_batch(const lsh_task* tasks, int ntask, double tol, int
   if (prec == LSH_FP32_MIXED) return solve_batch_t<float>(tasks, ntask, tol, max_iter, dev_ws, ws_bytes, st);
   return lsh_fail(LSH_EINVAL, "bad precision");
 }
+

@@ -53,7 +53,7 @@ class Stats(ctypes.Structure):
 
 class Task(ctypes.Structure):
     _fields_ = [("p", _P), ("nload", ctypes.c_int), ("eps0_voigt", _DP), ("sigma_out", _DP),
-                ("stats", ctypes.POINTER(Stats))]
+                ("stats", ctypes.POINTER(Stats)), ("dev_E_init", _P), ("dev_E_out", _P)]
 
 
 _sig = {
@@ -333,14 +333,18 @@ class Pattern:
 
 
 def solve_batch(patterns, eps0_list, tol=1e-6, max_iter=1000, precision="fp32", workspace=None,
-                allow_notconverged=False):
+                allow_notconverged=False, E_init=None, return_E=False):
     """Solve many bound patterns at once (lsh_solve_batch).
 
     patterns: list of Pattern (bound at `precision`); eps0_list: per pattern an
     (nload, nc) array of Voigt strains (nc = 6, or 3 for a 2-D pattern).
+    E_init: optional list (one entry per pattern, None for a zero start) of cuda
+    float64 tensors (nload, nc, m).  return_E: also return each task's final
+    field (nload, nc, m) as "E".
     Returns per pattern a dict with sigma (nload, nc), iterations, converged,
     residual, and the call's status.
     """
+    torch = _torch()
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     n = len(patterns)
     tasks = (Task * n)()
@@ -356,7 +360,17 @@ def solve_batch(patterns, eps0_list, tol=1e-6, max_iter=1000, precision="fp32", 
         tasks[i].eps0_voigt = _dptr(e)
         tasks[i].sigma_out = _dptr(sig)
         tasks[i].stats = st
-        outs.append((sig, st))
+        E0 = None if E_init is None else E_init[i]
+        if E0 is not None:
+            if E0.dtype != torch.float64 or not E0.is_cuda or E0.numel() != e.shape[0] * P.nc * P.m:
+                raise ValueError(f"E_init[{i}] must be a cuda float64 tensor with nload*{P.nc}*m entries")
+            E0 = E0.contiguous()
+            keep.append(E0)
+            tasks[i].dev_E_init = E0.data_ptr()
+        Eo = torch.empty((e.shape[0], P.nc, P.m), dtype=torch.float64, device="cuda") if return_E else None
+        if Eo is not None:
+            tasks[i].dev_E_out = Eo.data_ptr()
+        outs.append((sig, st, Eo))
     nb = ctypes.c_size_t()
     _check(_lib.lsh_batch_bytes(tasks, n, prec, ctypes.byref(nb)))
     ws = workspace if workspace is not None and workspace.numel() >= nb.value else _device_bytes(nb.value)
@@ -366,10 +380,13 @@ def solve_batch(patterns, eps0_list, tol=1e-6, max_iter=1000, precision="fp32", 
     _done_on(S)
     _check(rc, allow=(-5,) if allow_notconverged else ())
     res = []
-    for sig, st in outs:
-        res.append(dict(sigma=sig, iterations=np.array([s.iterations for s in st]),
-                        converged=np.array([bool(s.converged) for s in st]),
-                        residual=np.array([s.residual for s in st]), status=rc))
+    for sig, st, Eo in outs:
+        r = dict(sigma=sig, iterations=np.array([s.iterations for s in st]),
+                 converged=np.array([bool(s.converged) for s in st]),
+                 residual=np.array([s.residual for s in st]), status=rc)
+        if Eo is not None:
+            r["E"] = Eo
+        res.append(r)
     return res
 
 
