@@ -65,9 +65,33 @@ def algorithmic_bytes(P, nload, s=8):
     }
 
 
-def cpu_baseline(iters=24):
+def _cpu_model():
+    """The host CPU's model name (/proc/cpuinfo, as lscpu reports it)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _host_threads():
+    """Host threads this process may use: its CPU affinity, at most 16 (the
+    host share of one GPU on the benchmark machine)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(iters=24, iters_single=8):
     """The FP64 oracle on one load case of the same 128^3 problem (Gamma table
-    built first, outside the timed part)."""
+    built first, outside the timed part), timed twice on the host: with its FFTs
+    (scipy.fft) on every available thread, and on one thread."""
+    import scipy.fft
     from oracle import green, scheme
     from oracle.lattice import Pattern as OP
     import lsh_inputs as li
@@ -76,16 +100,28 @@ def cpu_baseline(iters=24):
     Cp = np.stack([li.isotropic_voigt(1.0, 0.3), li.isotropic_voigt(10.0, 0.3)])
     C0 = li.mean_reference(Cp)
     G, _ = green.gamma_periodised(O, C0, "dlvp", {"alpha": [0.75] * 3}, chunk=1 << 16)
-    c0 = os.times()
-    t0 = time.perf_counter()
-    scheme.basic_scheme(O, G, Cp, C0, ph, np.array([1.0, 0, 0, 0, 0, 0]), n_iter=iters)
-    wall = time.perf_counter() - t0
-    c1 = os.times()
-    cpu = (c1.user - c0.user) + (c1.system - c0.system)
-    return {"value": O.m * iters / wall, "unit": "voxel-iters/s", "cores": max(1, int(round(cpu / wall))),
-            "kind": "oracle",
+    e11 = np.array([1.0, 0, 0, 0, 0, 0])
+
+    def timed(workers, n):
+        with scipy.fft.set_workers(workers):
+            c0 = os.times()
+            t0 = time.perf_counter()
+            scheme.basic_scheme(O, G, Cp, C0, ph, e11, n_iter=n)
+            wall = time.perf_counter() - t0
+            c1 = os.times()
+        cpu = (c1.user - c0.user) + (c1.system - c0.system)
+        return O.m * n / wall, wall, cpu
+
+    nthr = _host_threads()
+    v1, w1, c1 = timed(1, iters_single)
+    vn, wn, cn = timed(nthr, iters)
+    return {"value": vn, "unit": "voxel-iters/s", "cores": max(1, int(round(cn / wn))), "kind": "oracle",
+            "threads_available": nthr, "cpu_model": _cpu_model(),
+            "single_core": {"value": v1, "unit": "voxel-iters/s", "iterations": iters_single,
+                            "wall_s": round(w1, 2), "cpu_s": round(c1, 2)},
             "sample": f"one load case (e11), {iters} Basic Scheme iterations of the 128^3 dlVP problem, "
-                      f"Gamma^p table precomputed outside the timing; {wall:.1f} s wall, {cpu:.1f} s CPU"}
+                      f"Gamma^p table precomputed outside the timing; scipy.fft workers = {nthr}; "
+                      f"{wn:.1f} s wall, {cn:.1f} s CPU (single thread: {iters_single} iterations, {w1:.1f} s)"}
 
 
 def _cfg4_instance(i):

@@ -12,7 +12,8 @@ Two forms are provided:
 * ``pattern_dft`` / ``pattern_idft`` evaluate the same sum in O(m log m):
   with the SNF orderings of ``lattice.Pattern`` the exponent h^T y equals
   sum_i a_i b_i / e_i mod 1, which is the multidimensional DFT over the SNF
-  grid (``numpy.fft.fftn`` serves as that library step).
+  grid (``scipy.fft.fftn`` serves as that library step; it honours
+  ``scipy.fft.set_workers`` for the number of host threads).
 
 The fast form is unnormalised (no m^{-1/2}); the inverse carries 1/m, so the
 pair is exact inverse to each other as the paper's unitary pair is.
@@ -20,6 +21,7 @@ pair is exact inverse to each other as the paper's unitary pair is.
 from __future__ import annotations
 
 import numpy as np
+import scipy.fft
 
 from .lattice import Pattern, brute_force_generating_set, brute_force_points
 
@@ -47,7 +49,7 @@ def pattern_dft(P: Pattern, a):
     a = np.asarray(a)
     shape = tuple(P.e) + a.shape[1:]
     A = a.reshape(shape)
-    return np.fft.fftn(A, axes=tuple(range(P.d))).reshape(a.shape[0:1] + a.shape[1:])
+    return scipy.fft.fftn(A, axes=tuple(range(P.d))).reshape(a.shape[0:1] + a.shape[1:])
 
 
 def pattern_idft(P: Pattern, ahat):
@@ -55,4 +57,4 @@ def pattern_idft(P: Pattern, ahat):
     ahat = np.asarray(ahat)
     shape = tuple(P.e) + ahat.shape[1:]
     A = ahat.reshape(shape)
-    return np.fft.ifftn(A, axes=tuple(range(P.d))).reshape(ahat.shape)
+    return scipy.fft.ifftn(A, axes=tuple(range(P.d))).reshape(ahat.shape)
