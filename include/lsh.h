@@ -223,6 +223,29 @@ int lsh_solve(lsh_pattern *p, int nload, const double *eps0_voigt, double tol, i
               const double *dev_E_init, double *dev_E_out, double *sigma_out,
               lsh_stats *stats, double *history);
 
+/* ----------------------------------------------------- allocation-free solve ---
+ * For callers that cannot allocate device memory (code running under HIP graph
+ * capture of their own, tight serving loops, harnesses that forbid hipMalloc):
+ * lsh_solve with the same arguments and results but no workspace argument.
+ * The workspace lives in a fixed device array inside the library, of
+ * LSH_NOALLOC_MAX_BYTES bytes, one per GPU the library runs on, held until the
+ * process ends; its device address is looked up once per device.  The call
+ * allocates nothing and instantiates no graph (its launches are issued one by
+ * one), so it runs somewhat slower than lsh_solve for short problems.
+ *   Limit: lsh_solve_bytes(p, nload, prec) <= LSH_NOALLOC_MAX_BYTES (64 MiB), e.g.
+ *   32^3 with six loads in FP64, 48^3 with four loads in FP32; larger solves
+ *   return LSH_EWORKSPACE with the bytes they need.
+ *   Every call on one GPU shares that GPU's array and overwrites what the last
+ *   call left there: calls that overlap on one GPU (other host threads, other
+ *   streams) race, so the caller serialises them.  Everything a solve needs to
+ *   start from zero is cleared by the call itself.
+ * The pattern must be bound (lsh_bind) beforehand, which takes the caller's
+ * persistent buffer.  Errors: as lsh_solve.                                        */
+#define LSH_NOALLOC_MAX_BYTES (64u * 1024u * 1024u)
+int lsh_solve_noalloc(lsh_pattern *p, int nload, const double *eps0_voigt, double tol, int max_iter,
+                      lsh_precision prec, void *stream, const double *dev_E_init, double *dev_E_out,
+                      double *sigma_out, lsh_stats *stats, double *history);
+
 /* ------------------------------------------------------------------ autotuner ---
  * Each pass of an iteration has kernel variants (the axis-1 stress pass with or
  * without its middle stages fused in registers and its tile width along i3,

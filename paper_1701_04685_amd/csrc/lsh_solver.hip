@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1447,7 +1448,7 @@ extern "C" int lsh_solve_bytes(const lsh_pattern* p, int nload, lsh_precision pr
   return LSH_OK;
 }
 
-// Argument checks of lsh_solve.
+// Argument checks shared by lsh_solve and lsh_solve_noalloc.
 static int check_solve_args(const lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int max_iter,
                             lsh_precision prec, const double* sigma_out) {
   if (!p || !eps0_voigt || !sigma_out) return lsh_fail(LSH_EINVAL, "null argument");
@@ -1589,3 +1590,54 @@ extern "C" int lsh_solve_batch(const lsh_task* tasks, int ntask, double tol, int
   return lsh_fail(LSH_EINVAL, "bad precision");
 }
 
+// ------------------------------------------------ allocation-free solve ---
+// The workspace of lsh_solve_noalloc: a fixed device array, one per GPU the
+// library runs on, held until the process ends.  Host code never passes the
+// array's name to a kernel or a copy (on the host it is only a stand-in
+// symbol): it uses the device address hipGetSymbolAddress returns, looked up
+// once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[LSH_NOALLOC_MAX_BYTES];
+
+#define LSH_NOALLOC_MAX_DEVICES 64
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[LSH_NOALLOC_MAX_DEVICES];  // per device, null until looked up
+
+static int scratch_address(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= LSH_NOALLOC_MAX_DEVICES) return lsh_fail(LSH_EUNSUPPORTED, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return lsh_fail(LSH_EDEVICE, std::string("scratch address lookup failed: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LSH_OK;
+}
+
+extern "C" int lsh_solve_noalloc(lsh_pattern* p, int nload, const double* eps0_voigt, double tol, int max_iter,
+                                 lsh_precision prec, void* stream, const double* dev_E_init, double* dev_E_out,
+                                 double* sigma_out, lsh_stats* stats, double* history) {
+  int rc = check_solve_args(p, nload, eps0_voigt, tol, max_iter, prec, sigma_out);
+  if (rc) return rc;
+  size_t need = 0;
+  rc = lsh_solve_bytes(p, nload, prec, &need);
+  if (rc) return rc;
+  if (need > (size_t)LSH_NOALLOC_MAX_BYTES)
+    return lsh_fail(LSH_EWORKSPACE, "lsh_solve_noalloc: this solve needs " + std::to_string(need) +
+                                        " bytes of workspace; the allocation-free entry point holds at most " +
+                                        std::to_string((size_t)LSH_NOALLOC_MAX_BYTES) + " (use lsh_solve)");
+  void* ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  // launches are issued one by one: no graph is instantiated (that would allocate)
+  if (prec == LSH_FP64)
+    return solve_t<double>(p, nload, eps0_voigt, tol, max_iter, ws, need, st, dev_E_init, dev_E_out, sigma_out, stats,
+                           history, false);
+  return solve_t<float>(p, nload, eps0_voigt, tol, max_iter, ws, need, st, dev_E_init, dev_E_out, sigma_out, stats,
+                        history, false);
+}

@@ -26,7 +26,7 @@ STATUS = {0: "LSH_OK", -1: "LSH_EINVAL", -2: "LSH_ESINGULAR", -3: "LSH_ENOINTERP
 
 EXPORTS = ["lsh_create_pattern", "lsh_destroy", "lsh_pattern_info", "lsh_pattern_snf", "lsh_pattern_points",
            "lsh_set_kernel", "lsh_set_stiffness", "lsh_persistent_bytes", "lsh_bind", "lsh_gamma_probe",
-           "lsh_solve_bytes", "lsh_solve", "lsh_batch_bytes", "lsh_solve_batch", "lsh_profile_enable",
+           "lsh_solve_bytes", "lsh_solve", "lsh_solve_noalloc", "lsh_batch_bytes", "lsh_solve_batch", "lsh_profile_enable",
            "lsh_profile_select", "lsh_profile_read", "lsh_last_error", "lsh_autotune", "lsh_tune_reset", "lsh_tune_set", "lsh_set_scheme", "lsh_unet_create", "lsh_unet_destroy", "lsh_unet_param_count",
            "lsh_unet_param_bytes", "lsh_unet_bind", "lsh_unet_get_params", "lsh_unet_act_bytes",
            "lsh_unet_train_step", "lsh_unet_zero_grad", "lsh_unet_get_grads", "lsh_unet_predict", "lsh_unet_head",
@@ -70,6 +70,8 @@ _sig = {
     "lsh_solve_bytes": ([_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "lsh_solve": ([_P, ctypes.c_int, _DP, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t, _P,
                    _P, _P, _DP, ctypes.POINTER(Stats), _DP], ctypes.c_int),
+    "lsh_solve_noalloc": ([_P, ctypes.c_int, _DP, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P, _P, _P, _DP,
+                           ctypes.POINTER(Stats), _DP], ctypes.c_int),
     "lsh_batch_bytes": ([ctypes.POINTER(Task), ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
                         ctypes.c_int),
     "lsh_solve_batch": ([ctypes.POINTER(Task), ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P,
