@@ -254,6 +254,13 @@ int lsh_solve_noalloc(lsh_pattern *p, int nload, const double *eps0_voigt, doubl
  * from a zero start; a warm-up launch, then the mean of three) with HIP events
  * on `stream`, and keeps the fastest for later lsh_solve and lsh_solve_batch
  * calls of this pattern (as a batch group's first pattern) at that precision.
+ * Last it times the schedule: a whole four-pass iteration with the variants
+ * just chosen (entry 0) against each variant of the two-pass iteration, which
+ * splits the axis-2 transform between the stress pass and the Green pass (a
+ * four-step DFT) and moves 30 s + 1 bytes per voxel and load instead of
+ * 54 s + 1 (s = 8 in FP64, 4 in FP32); it exists for the cubic SNF grids 32,
+ * 48, 64, 96 and 128 (FP32) and 32, 48, 64 (FP64), with an isotropic C0 or a
+ * tabled Green operator, and not for conjugate gradients.
  * The choice is dropped by lsh_set_kernel and lsh_tune_reset.  Needs the solve
  * workspace (lsh_solve_bytes); its contents are scratch.  Synchronises `stream`.
  *   out (optional): the chosen variant per pass (0 = the default), the number
@@ -261,16 +268,17 @@ int lsh_solve_noalloc(lsh_pattern *p, int nload, const double *eps0_voigt, doubl
  * Errors: LSH_EINVAL, LSH_ESTATE, LSH_EWORKSPACE, LSH_EDEVICE.                      */
 #define LSH_TUNE_MAX 8   /* variants timed per pass, at most */
 typedef struct {
-  int choice[3];   /* stress pass, axis-2 passes, Green pass */
-  int ncand[3];
-  float ms[3][LSH_TUNE_MAX];
+  int choice[4];   /* stress pass, axis-2 passes, Green pass, schedule (0: four passes) */
+  int ncand[4];
+  float ms[4][LSH_TUNE_MAX];
 } lsh_tune_result;
 
 int lsh_autotune(lsh_pattern *p, int nload, lsh_precision prec, void *dev_workspace, size_t ws_bytes,
                  void *stream, lsh_tune_result *out);
 int lsh_tune_reset(lsh_pattern *p);
-/* Force the variants (choice[3], as in lsh_tune_result; an index beyond a
- * pass's variant count selects its last variant), e.g. to check each variant.   */
+/* Force the variants (choice[4], as in lsh_tune_result; an index beyond a
+ * pass's variant count selects its last variant; a two-pass schedule where none
+ * is built selects the four passes), e.g. to check each variant.                 */
 int lsh_tune_set(lsh_pattern *p, lsh_precision prec, const int *choice);
 
 /* -------------------------------------------------------------------- batches ---

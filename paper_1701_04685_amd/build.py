@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblsh.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["lsh_host.cpp", "lsh_solver.hip", "lsh_unet.hip"]
+SOURCES = ["lsh_host.cpp", "lsh_solver.hip", "lsh_twopass.hip", "lsh_unet.hip"]
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed FP32 instructions stay off
@@ -40,15 +40,18 @@ def torch_lib_dir() -> str:
 def build(verbose: bool = True) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src in SOURCES:
+    objs, procs = [], []
+    for src in SOURCES:  # the sources compile side by side
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc, *CFLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    for cmd, pr in procs:
+        if pr.wait() != 0:
+            raise subprocess.CalledProcessError(pr.returncode, cmd)
     tl = torch_lib_dir()
     link = ["g++", "-shared", "-o", OUT + ".tmp", *objs, f"-L{tl}", "-l:libamdhip64.so",
             f"-Wl,-rpath,{tl}", "-Wl,--no-undefined"]

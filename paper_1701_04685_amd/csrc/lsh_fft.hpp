@@ -309,3 +309,41 @@ __device__ __forceinline__ void fft_any(typename cpx<T>::t* buf, const FftPlan& 
     fft_lines<T, DIR, 16>(buf, pl, L, ls, es, LF, tw);
   }
 }
+
+// ------------------------------------------------- in-register line DFT ---
+// The same Stockham stages on one thread's P values v[0..P) held in
+// registers (P a compile-time length with radices from make_radlist): every
+// index is a constant, so the data never leaves registers.  twP[k] =
+// exp(-2 pi i k / P), k < P (forward; DIR = +1 conjugates, unnormalised).
+template <typename T, int DIR, int P, int S = 0, int NS = 1>
+__device__ __forceinline__ void reg_fft(typename cpx<T>::t (&v)[P], const typename cpx<T>::t* __restrict__ twP) {
+  using T2 = typename cpx<T>::t;
+  constexpr RadList RL = make_radlist(P);
+  if constexpr (S < RL.n) {
+    constexpr int R = RL.r[S];
+    constexpr int nbl = P / R;
+    constexpr int tstep = P / (NS * R);
+    T2 y[P];
+#pragma unroll
+    for (int j = 0; j < nbl; ++j) {
+      const int k = j % NS;
+      T2 u[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[r] = v[j + r * nbl];
+      if (NS > 1 && k != 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          T2 w = twP[r * tstep * k];
+          if (DIR > 0) w.y = -w.y;
+          u[r] = cmul(u[r], w);
+        }
+      }
+      Bfly<T, DIR, R>::run(u);
+#pragma unroll
+      for (int r = 0; r < R; ++r) y[(j - k) * R + k + r * NS] = u[r];
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[i] = y[i];
+    reg_fft<T, DIR, P, S + 1, NS * R>(v, twP);
+  }
+}

@@ -46,7 +46,7 @@ struct lsh_pattern {
 
   // ---- kernel variants chosen by lsh_autotune, per precision (0: FP64, 1: FP32)
   int tuned[2] = {0, 0};
-  int tune_choice[2][3] = {{0, 0, 0}, {0, 0, 0}};  // stress, axis 2, Green pass
+  int tune_choice[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // stress, axis 2, Green pass, schedule
 };
 
 // ---- helpers implemented in lsh_host.cpp

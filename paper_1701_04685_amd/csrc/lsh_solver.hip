@@ -30,6 +30,7 @@
 #include "lsh_internal.hpp"
 
 #include "lsh_kernels.hpp"
+#include "lsh_twopass.hpp"
 
 namespace {
 
@@ -106,6 +107,9 @@ struct KernSet {
   std::vector<CGreen> cg;
   int green2 = 0;  // 1: k_green2 (grid: positions x load chunks), 0: k_green
   size_t lds1 = 0, lds2 = 0, ldsG = 0;
+  // two-pass schedule (lsh_twopass.hpp): its variants and the one in use (-1: four passes)
+  std::vector<TwoPass<T>> tp;
+  int tpi = -1;
 };
 
 constexpr int pick_w(int N, int bytes_per_col, int cap, int budget) {
@@ -391,6 +395,13 @@ int make_kernels(const lsh_pattern* p, bool table, KernSet<T>* K) {
   if (!choose_axis1<T>(g, p->plan[0], *K)) return lsh_fail(LSH_EUNSUPPORTED, "SNF factor e1 too large for one block");
   if (!choose_axis2<T>(g, p->plan[1], *K)) return lsh_fail(LSH_EUNSUPPORTED, "SNF factor e2 too large for one block");
   if (!choose_green<T>(g, p->plan[2], table, *K)) return lsh_fail(LSH_EUNSUPPORTED, "SNF factor e3 too large for one block");
+  K->tp.clear();
+  if (p->scheme != LSH_SCHEME_CG) {
+    TwoPass<T> c[8];
+    const int n = twopass_candidates(g, c, 8);
+    for (int i = 0; i < n; ++i)
+      if (c[i].ldss <= (size_t)lds_limit() && c[i].ldsg <= (size_t)lds_limit()) K->tp.push_back(c[i]);
+  }
   return LSH_OK;
 }
 
@@ -712,9 +723,11 @@ struct GroupRun {
   std::vector<double> ring;
 };
 
-// Select candidate ch[pass] for each pass (stress, axis 2, Green pass).
+// Select candidate ch[pass] for each pass (stress, axis 2, Green pass) and the
+// schedule ch[3] (0: four passes; i > 0: two-pass variant i - 1, if it holds a
+// kernel for this Green mode).
 template <typename T>
-void apply_choice(KernSet<T>& K, int gmode, const int ch[3]) {
+void apply_choice(KernSet<T>& K, int gmode, const int ch[4]) {
   if (!K.c1.empty()) {
     const auto& c = K.c1[std::min<size_t>((size_t)ch[0], K.c1.size() - 1)];
     K.a1s = c.fn;
@@ -738,6 +751,11 @@ void apply_choice(KernSet<T>& K, int gmode, const int ch[3]) {
   }
   if (K.green2) K.gr = K.gr2[gmode];
   else if (K.gr2[gmode]) K.gr = K.gr2[gmode];
+  K.tpi = -1;
+  if (ch[3] > 0 && !K.tp.empty()) {
+    const int i = std::min<int>(ch[3], (int)K.tp.size()) - 1;
+    if (K.tp[i].g3[gmode]) K.tpi = i;
+  }
 }
 
 inline int prec_index(const lsh_pattern* p) { return p->bound_prec == LSH_FP32_MIXED ? 1 : 0; }
@@ -750,8 +768,13 @@ int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
   G.gmode = green_mode(p);
   {
     const int pi = prec_index(p);
-    const int zero[3] = {0, 0, 0};
+    const int zero[4] = {0, 0, 0, 0};
     apply_choice(G.K, G.gmode, p->tuned[pi] ? p->tune_choice[pi] : zero);
+  }
+  if (G.K.tpi >= 0) {
+    rc = allow_lds(G.K.tp[G.K.tpi].s2, G.K.tp[G.K.tpi].ldss);
+    if (!rc) rc = allow_lds(G.K.tp[G.K.tpi].g3[G.gmode], G.K.tp[G.K.tpi].ldsg);
+    if (rc) return rc;
   }
   rc = allow_lds(G.K.gr, G.K.ldsG);
   if (rc) return rc;
@@ -839,8 +862,11 @@ int group_init(GroupRun<T>& G, int max_iter, hipStream_t st) {
                        (const T2*)nullptr, (T2*)G.w.X, (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0,
                        (const int*)G.w.stop_iter, (const int*)G.w.itp, (const double* const*)G.w.einit,
                        (const double*)G.w.means, (double* const*)nullptr, (double*)nullptr);
-    hipLaunchKernelGGL(G.K.a2[0], G.gridB, dim3(G.K.NT2), G.K.lds2, st, G.g, p->plan[1], tw1, (const T2*)G.w.X,
-                       (T2*)G.w.P[0], (const int*)nullptr, (const int*)nullptr, (T)(1.0 / G.g.n2));
+    if (G.K.tpi >= 0)  // the two-pass state: split along axis 2 (lsh_twopass.hpp)
+      twopass_to_split(G.g, G.K.tp[G.K.tpi].Q, tw1, (const T2*)G.w.X, (T2*)G.w.P[0], nload, st);
+    else
+      hipLaunchKernelGGL(G.K.a2[0], G.gridB, dim3(G.K.NT2), G.K.lds2, st, G.g, p->plan[1], tw1, (const T2*)G.w.X,
+                         (T2*)G.w.P[0], (const int*)nullptr, (const int*)nullptr, (T)(1.0 / G.g.n2));
     HIPCHK(hipGetLastError());
   } else {
     int rc = zero_async(G.w.X, fb, st);
@@ -888,11 +914,55 @@ void launch_green(GroupRun<T>& G, int cur, hipStream_t st) {
                      G.spec.rep->scheme == LSH_SCHEME_VE ? 1 : 0);
 }
 
+// The two passes of the two-pass schedule: P[cur] -> TAU -> P[1 - cur].
+template <typename T>
+void launch_twopass(GroupRun<T>& G, int cur, int which, hipStream_t st) {
+  using T2 = C2<T>;
+  const lsh_pattern* p = G.spec.rep;
+  const TwoPass<T>& c = G.K.tp[G.K.tpi];
+  const T2* tw0 = (const T2*)(p->dev_persist + p->off_tw[0]);
+  const T2* tw1 = (const T2*)(p->dev_persist + p->off_tw[1]);
+  const T2* tw2 = (const T2*)(p->dev_persist + p->off_tw[2]);
+  if (which & 1)
+    hipLaunchKernelGGL(c.s2, dim3(c.P * (G.g.n3 / c.W), G.nload), dim3(c.nts), c.ldss, st, G.g, tw0, tw1,
+                       (const T2*)G.w.P[cur], (T2*)G.w.TAU, (const Inst*)G.w.insts, (const int*)G.w.inst_of,
+                       (const double*)G.w.eps0, (const int*)G.w.stop_iter, (const int*)G.w.itp);
+  if (which & 2) {
+    const T* table = p->has_table ? (const T*)(p->dev_persist + p->off_table) : nullptr;
+    hipLaunchKernelGGL(c.g3[G.gmode], dim3(G.g.h1 * c.Q, (unsigned)(G.chunks.size() / 2)), dim3(c.ntg), c.ldsg, st,
+                       G.g, tw1, tw2, (const T2*)G.w.TAU, (const T2*)G.w.P[cur], (T2*)G.w.P[1 - cur], table,
+                       (const Inst*)G.w.insts, (const int*)G.w.inst_of, (const int*)G.w.chunks,
+                       (const int*)G.w.stop_iter, (const int*)G.w.itp, G.g.h1 * c.Q, G.w.partial,
+                       p->scheme == LSH_SCHEME_VE ? 1 : 0);
+  }
+}
+
 // One Basic Scheme iteration of a group: stress (axis 1), axis 2, Green pass
-// (axis 3), residual, inverse axis 2.
+// (axis 3), residual, inverse axis 2; or the two passes of the two-pass
+// schedule and the residual.
 template <typename T>
 int group_iterate(GroupRun<T>& G, int cur, double tol, bool fixed, hipStream_t st) {
   using T2 = C2<T>;
+  if (G.K.tpi >= 0) {
+    const int Q = G.K.tp[G.K.tpi].Q;
+    {
+      Timer tm(0, st);
+      launch_twopass<T>(G, cur, 1, st);
+    }
+    {
+      Timer tm(2, st);
+      launch_twopass<T>(G, cur, 2, st);
+    }
+    {
+      // Parseval in the split domain: sum_y |E|^2 = n1 Q sum w(k1) |X'|^2
+      Timer tm(3, st);
+      hipLaunchKernelGGL(k_finalize_resid, dim3(G.nload), dim3(1024), 0, st, (const double*)G.w.partial,
+                         G.g.h1 * Q, G.nload, (const double*)G.w.e0sq, (double)G.g.n1 * (double)Q, tol,
+                         fixed ? 1 : 0, G.w.itp, G.w.stop_iter, G.w.hist, G.w.nonfinite);
+    }
+    HIPCHK(hipGetLastError());
+    return LSH_OK;
+  }
   const double pscale = (double)G.g.n1 * (double)G.g.n2;
   {
     Timer tm(0, st);
@@ -924,15 +994,20 @@ int group_iterate(GroupRun<T>& G, int cur, double tol, bool fixed, hipStream_t s
 // Autotuner: time each candidate of each pass on the group's own data (after
 // a zero-start init) and keep the fastest; the caller re-initialises the state.
 template <typename T>
-int tune_group(GroupRun<T>& G, hipStream_t st, int choice[3], int ncand[3], float ms[3][LSH_TUNE_MAX]) {
+int tune_group(GroupRun<T>& G, hipStream_t st, int choice[4], int ncand[4], float ms[4][LSH_TUNE_MAX]) {
   using T2 = C2<T>;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  int ch[3] = {0, 0, 0};
-  const int nc[3] = {(int)G.K.c1.size(), (int)G.K.c2.size(), G.K.green2 ? (int)G.K.cg.size() : 1};
+  int ch[4] = {0, 0, 0, 0};
+  // "pass" 3 is the schedule: a whole four-pass iteration with the variants
+  // chosen before, against each two-pass variant's iteration
+  int ntp = 0;
+  for (const auto& c : G.K.tp) ntp += c.g3[G.gmode] ? 1 : 0;
+  const int nc[4] = {(int)G.K.c1.size(), (int)G.K.c2.size(), G.K.green2 ? (int)G.K.cg.size() : 1,
+                     1 + (ntp == (int)G.K.tp.size() ? ntp : 0)};
   int rc = LSH_OK;
-  for (int pass = 0; pass < 3 && rc == LSH_OK; ++pass) {
+  for (int pass = 0; pass < 4 && rc == LSH_OK; ++pass) {
     ncand[pass] = nc[pass];
     float best = 1e30f;
     int bi = 0;
@@ -948,6 +1023,10 @@ int tune_group(GroupRun<T>& G, hipStream_t st, int choice[3], int ncand[3], floa
         if (!rc) rc = allow_lds(G.K.a2[1], G.K.lds2);
       }
       if (pass == 2) rc = allow_lds(G.K.gr, G.K.ldsG);
+      if (pass == 3 && G.K.tpi >= 0) {
+        rc = allow_lds(G.K.tp[G.K.tpi].s2, G.K.tp[G.K.tpi].ldss);
+        if (!rc) rc = allow_lds(G.K.tp[G.K.tpi].g3[G.gmode], G.K.tp[G.K.tpi].ldsg);
+      }
       if (rc) break;
       auto run = [&]() {
         if (pass == 0) launch_stress<T>(G, st);
@@ -956,6 +1035,16 @@ int tune_group(GroupRun<T>& G, hipStream_t st, int choice[3], int ncand[3], floa
           launch_axis2<T>(G, 1, (const T2*)G.w.P[1], (T2*)G.w.X, st);
         }
         if (pass == 2) launch_green<T>(G, 0, st);
+        if (pass == 3) {
+          if (G.K.tpi >= 0) {
+            launch_twopass<T>(G, 0, 3, st);
+          } else {
+            launch_stress<T>(G, st);
+            launch_axis2<T>(G, 0, (const T2*)G.w.TAU, (T2*)G.w.TAU, st);
+            launch_green<T>(G, 0, st);
+            launch_axis2<T>(G, 1, (const T2*)G.w.P[1], (T2*)G.w.X, st);
+          }
+        }
       };
       run();
       (void)hipEventRecord(e0, st);
@@ -983,7 +1072,7 @@ int tune_group(GroupRun<T>& G, hipStream_t st, int choice[3], int ncand[3], floa
   const int nt3b = (G.g.n3 + G.K.W2 - 1) / G.K.W2;
   G.gridB = dim3(G.g.h1 * nt3b, 6, G.nload);
   G.gridS1 = dim3(G.g.n2 * ((G.g.n3 + G.K.W1s - 1) / G.K.W1s), G.nload);
-  for (int i = 0; i < 3; ++i) choice[i] = ch[i];
+  for (int i = 0; i < 4; ++i) choice[i] = ch[i];
   return LSH_OK;
 }
 
@@ -1015,6 +1104,9 @@ int group_finish(GroupRun<T>& G, int done, double tol, bool fixed, double secs, 
   const T2* tw0 = (const T2*)(base + p->off_tw[0]);
   std::vector<int> nonfin(G.nload, 0);
   HIPCHK(hipMemcpyAsync(nonfin.data(), G.w.nonfinite, sizeof(int) * G.nload, hipMemcpyDeviceToHost, st));
+  if (G.K.tpi >= 0)  // back to the four-pass layout X, from the buffer each load's last iteration wrote
+    twopass_from_split(G.g, G.K.tp[G.K.tpi].Q, (const T2*)(base + p->off_tw[1]), (const T2*)G.w.P[0],
+                       (const T2*)G.w.P[1], (T2*)G.w.X, (const int*)G.w.stop_iter, (const int*)G.w.itp, G.nload, st);
   bool any_out = false;
   for (double* e : G.spec.eout) any_out = any_out || e != nullptr;
   if (any_out)
@@ -1499,15 +1591,15 @@ int autotune_t(lsh_pattern* p, int nload, void* dev_ws, size_t ws_bytes, hipStre
   if (rc) return rc;
   rc = group_init<T>(G, 1, st);
   if (rc) return rc;
-  int choice[3] = {0, 0, 0}, ncand[3] = {1, 1, 1};
-  float ms[3][LSH_TUNE_MAX] = {{0}};
+  int choice[4] = {0, 0, 0, 0}, ncand[4] = {1, 1, 1, 1};
+  float ms[4][LSH_TUNE_MAX] = {{0}};
   rc = tune_group<T>(G, st, choice, ncand, ms);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(st));
   p->tuned[pi] = 1;
-  for (int i = 0; i < 3; ++i) p->tune_choice[pi][i] = choice[i];
+  for (int i = 0; i < 4; ++i) p->tune_choice[pi][i] = choice[i];
   if (out) {
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < 4; ++i) {
       out->choice[i] = choice[i];
       out->ncand[i] = ncand[i];
       for (int c = 0; c < LSH_TUNE_MAX; ++c) out->ms[i][c] = c < ncand[i] ? ms[i][c] : 0.f;
@@ -1530,10 +1622,10 @@ extern "C" int lsh_autotune(lsh_pattern* p, int nload, lsh_precision prec, void*
 extern "C" int lsh_tune_set(lsh_pattern* p, lsh_precision prec, const int* choice) {
   if (!p || !choice) return lsh_fail(LSH_EINVAL, "null argument");
   if (prec != LSH_FP64 && prec != LSH_FP32_MIXED) return lsh_fail(LSH_EINVAL, "bad precision");
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 4; ++i)
     if (choice[i] < 0 || choice[i] >= LSH_TUNE_MAX) return lsh_fail(LSH_EINVAL, "variant index out of range");
   const int pi = prec == LSH_FP32_MIXED ? 1 : 0;
-  for (int i = 0; i < 3; ++i) p->tune_choice[pi][i] = choice[i];
+  for (int i = 0; i < 4; ++i) p->tune_choice[pi][i] = choice[i];
   p->tuned[pi] = 1;
   return LSH_OK;
 }

@@ -1,0 +1,499 @@
+// lsh_twopass.hip -- the Basic Scheme iteration in two passes for gfx950.
+//
+// Thm. (pde_discretization), eq. (pde_coefficients), iterated as in Sec. 4 on
+// the SNF grid (the pattern DFT of eq. (Fouriermatrix) as a 3-D DFT); the
+// schedule and the state layout are described in lsh_twopass.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "lsh_twopass.hpp"
+
+namespace {
+
+// ------------------------------------------------------------- stress pass ---
+// One block: load L, coset r of axis 2 (i2 = r + P j, j < Q) and W consecutive
+// i3.  LDS: axis-1 twiddles [N1], w_Q^k [Q], w_n2^{r q} [Q], the tile
+// Z[k < N1][(pair, j, w)] (component pairs (0,1), (2,3), (4,5) share one complex
+// axis-1 line), then (C_p - C0) of the first NDL phases.  Blocks take r
+// fastest: neighbouring blocks' runs lie P n3 elements apart.
+template <typename T, int N1, int Q, int W, int NT, int NDL = 16>
+__global__ void __launch_bounds__(NT) k_stress2(Geo g, const C2<T>* __restrict__ tw0, const C2<T>* __restrict__ tw1,
+                                                const C2<T>* __restrict__ X, C2<T>* __restrict__ Y,
+                                                const Inst* __restrict__ insts, const int* __restrict__ inst_of,
+                                                const double* __restrict__ eps0, const int* __restrict__ stop_iter,
+                                                const int* __restrict__ itp) {
+  using T2 = C2<T>;
+  constexpr int H = N1 / 2 + 1;
+  constexpr int NC3 = 3 * Q * W;  // LDS columns (pair, j, w)
+  constexpr int NU = H * 3 * W;   // load and store items (k, pair, w), all Q at once
+  constexpr int UT = (NU + NT - 1) / NT;
+  constexpr int NP = N1 * Q * W;  // points of the tile
+  constexpr int PT = (NP + NT - 1) / NT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* twl = reinterpret_cast<T2*>(smem_raw);
+  T2* twq = twl + N1;
+  T2* twr = twq + Q;
+  T2* Z = twr + Q;
+  T* Dl = reinterpret_cast<T*>(Z + N1 * NC3);
+  const int L = blockIdx.y;
+  if (*itp >= stop_iter[L]) return;
+  const int P = g.n2 / Q;
+  const int r = blockIdx.x % P;
+  const int a30 = (blockIdx.x / P) * W;
+  const Inst& in = insts[inst_of[L]];
+  const uint8_t* __restrict__ phase = in.phase;
+  const T* __restrict__ dmat = reinterpret_cast<const T*>(in.dmat);
+  const int nphase = in.nphase;
+  const long long n23 = (long long)g.n2 * g.n3;
+  const long long PN3 = (long long)P * g.n3;
+  const int tid = threadIdx.x;
+
+  // the state at every q for item (k, pair, w), both components of the pair
+  T2 xa[UT][Q], xb[UT][Q];
+#pragma unroll
+  for (int i = 0; i < UT; ++i) {
+    const int u = tid + i * NT;
+    const int w = u % W, p = (u / W) % 3, k = u / (3 * W);
+    const bool ok = NU % NT == 0 || u < NU;
+    const long long off = ((long long)k * Q * P + r) * g.n3 + a30 + w;
+    const T2* pa = X + (long long)(L * 6 + 2 * p) * g.spec + off;
+    const T2* pb = pa + g.spec;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      xa[i][q] = ok ? pa[q * PN3] : T2{0, 0};
+      xb[i][q] = ok ? pb[q * PN3] : T2{0, 0};
+    }
+  }
+  // phase indices of the tile's points (a1, j, w), used after the C2R
+  int ph[PT];
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int idx = tid + i * NT;
+    const int w = idx % W, j = (idx / W) % Q, a1 = idx / (Q * W);
+    ph[i] = (NP % NT == 0 || idx < NP) ? phase[(long long)a1 * n23 + (long long)(r + P * j) * g.n3 + a30 + w] : 0;
+  }
+  stage_twiddles<T>(twl, tw0, N1);
+  for (int i = tid; i < Q; i += NT) {
+    twq[i] = tw1[i * P];
+    twr[i] = tw1[i * r];
+  }
+  {
+    const int nd = nphase < NDL ? nphase : NDL;
+    for (int i = tid; i < 36 * nd; i += NT) Dl[i] = dmat[i];
+  }
+  __syncthreads();
+
+  // conjugate twiddle, Q-point inverse DFT over q (to j), Hermitian extension
+  // of the pair lines: Z_p[k] = X_{2p}[k] + i X_{2p+1}[k] on the full axis
+#pragma unroll
+  for (int i = 0; i < UT; ++i) {
+    const int u = tid + i * NT;
+    if (NU % NT == 0 || u < NU) {
+      const int w = u % W, p = (u / W) % 3, k = u / (3 * W);
+#pragma unroll
+      for (int q = 1; q < Q; ++q) {
+        T2 t = twr[q];
+        t.y = -t.y;
+        xa[i][q] = cmul(xa[i][q], t);
+        xb[i][q] = cmul(xb[i][q], t);
+      }
+      reg_fft<T, +1, Q>(xa[i], twq);
+      reg_fft<T, +1, Q>(xb[i], twq);
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const int col = (p * Q + j) * W + w;
+        const T2 a = xa[i][j], b = xb[i][j];
+        if (k == 0 || 2 * k == N1) {
+          Z[k * NC3 + col] = T2{a.x, b.x};
+        } else {
+          Z[k * NC3 + col] = T2{a.x - b.y, a.y + b.x};
+          Z[(N1 - k) * NC3 + col] = T2{a.x + b.y, b.x - a.y};
+        }
+      }
+    }
+  }
+  __syncthreads();
+  fft_static<T, +1, N1, NC3, true, NT>(Z, 1, NC3, twl);
+
+  // tau = (C_p - C0):(E + eps0) at the tile's points
+  {
+    const double* e0 = eps0 + 6 * L;
+    const T ep[6] = {(T)e0[0], (T)e0[1], (T)e0[2], (T)e0[3], (T)e0[4], (T)e0[5]};
+    auto stress = [&](int idx, const T* D) {
+      const int w = idx % W, j = (idx / W) % Q, a1 = idx / (Q * W);
+      T2* z = Z + a1 * NC3 + j * W + w;
+      const T2 z0 = z[0], z1 = z[Q * W], z2 = z[2 * Q * W];
+      const T E[6] = {z0.x + ep[0], z0.y + ep[1], z1.x + ep[2], z1.y + ep[3], z2.x + ep[4], z2.y + ep[5]};
+      T t[6];
+      stress6<T>(D, E, t);
+      z[0] = T2{t[0], t[1]};
+      z[Q * W] = T2{t[2], t[3]};
+      z[2 * Q * W] = T2{t[4], t[5]};
+    };
+    // separate loops so that the LDS reads stay LDS instructions
+    if (nphase <= NDL) {
+#pragma unroll
+      for (int i = 0; i < PT; ++i) {
+        const int idx = tid + i * NT;
+        if (NP % NT == 0 || idx < NP) stress(idx, Dl + 36 * ph[i]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < PT; ++i) {
+        const int idx = tid + i * NT;
+        if (NP % NT == 0 || idx < NP) stress(idx, dmat + 36 * ph[i]);
+      }
+    }
+  }
+  __syncthreads();
+  fft_static<T, -1, N1, NC3, true, NT>(Z, 1, NC3, twl);
+
+  // unpack the pairs (half spectrum k < H), Q-point DFT over j (to q), twiddle
+#pragma unroll
+  for (int i = 0; i < UT; ++i) {
+    const int u = tid + i * NT;
+    if (NU % NT == 0 || u < NU) {
+      const int w = u % W, p = (u / W) % 3, k = u / (3 * W);
+      T2 ya[Q], yb[Q];
+      const T hf = (T)0.5;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const int col = (p * Q + j) * W + w;
+        const T2 zk = Z[k * NC3 + col];
+        const T2 zn = Z[((N1 - k) % N1) * NC3 + col];
+        ya[j] = T2{hf * (zk.x + zn.x), hf * (zk.y - zn.y)};
+        yb[j] = T2{hf * (zk.y + zn.y), hf * (zn.x - zk.x)};
+      }
+      reg_fft<T, -1, Q>(ya, twq);
+      reg_fft<T, -1, Q>(yb, twq);
+      const long long off = ((long long)k * Q * P + r) * g.n3 + a30 + w;
+      T2* qa = Y + (long long)(L * 6 + 2 * p) * g.spec + off;
+      T2* qb = qa + g.spec;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const T2 t = twr[q];
+        qa[q * PN3] = q ? cmul(ya[q], t) : ya[q];
+        qb[q * PN3] = q ? cmul(yb[q], t) : yb[q];
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------- Green pass ---
+// One block: position (k1, q) and a chunk of up to six loads of one instance,
+// one load at a time.  LDS: axis-3 twiddles [N3], w_P^k [P], lines
+// [(s, comp)][LS] along axis 3.  Per load: the tile's P n3 values of each
+// component come in with the P-point DFT over r done in registers, the axis-3
+// transforms run in LDS, -Gamma^p/m is applied per bin (k1, q + Q s, k3), and
+// the values go out through the inverse transforms, the inverse P-point DFT
+// again in registers, with the Cauchy residual's partial sums (double).
+template <typename T, int P, int N3, int NT, int GM>
+__global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ tw1, const C2<T>* __restrict__ tw2,
+                                               const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
+                                               C2<T>* __restrict__ Pnew, const T* __restrict__ table,
+                                               const Inst* __restrict__ insts, const int* __restrict__ inst_of,
+                                               const int* __restrict__ chunks, const int* __restrict__ stop_iter,
+                                               const int* __restrict__ itp, int npos, double* __restrict__ partial,
+                                               int ve) {
+  using T2 = C2<T>;
+  static_assert(GM == GREEN_TABLE || GM == GREEN_MOMENTS, "tabled Green operators only");
+  constexpr int LS = N3 + 1;  // odd line stride: the same entry of neighbouring lines in other banks
+  constexpr int NLN = 6 * P;  // lines (s, comp)
+  constexpr int NI = 6 * N3;  // items (comp, i3) of the P-point stages
+  constexpr int IT = (NI + NT - 1) / NT;
+  constexpr int NB = P * N3;  // bins of the tile
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* tw3 = reinterpret_cast<T2*>(smem_raw);
+  T2* twP = tw3 + N3;
+  T2* lines = twP + P;
+  const int Q = g.n2 / P;
+  const int pos = blockIdx.x;
+  const int k1 = pos / Q, q = pos % Q;
+  const int Lbeg = chunks[2 * blockIdx.y], Lend = chunks[2 * blockIdx.y + 1];
+  const int it = *itp;
+  {
+    bool any = false;
+    for (int L = Lbeg; L < Lend; ++L) any = any || it < stop_iter[L];
+    if (!any) return;
+  }
+  const int tid = threadIdx.x;
+  const double wk1 = (k1 == 0 || 2 * k1 == g.n1) ? 1.0 : 2.0;
+  const long long row = (long long)(k1 * Q + q) * P * N3;  // the tile's first element in a component
+  const double scale = -1.0 / (double)g.m;
+  const double mu0 = insts[inst_of[Lbeg]].mu0, riso = insts[inst_of[Lbeg]].riso;
+  stage_twiddles<T>(tw3, tw2, N3);
+  for (int i = tid; i < P; i += NT) twP[i] = tw1[i * Q];
+  __syncthreads();
+
+  for (int L = Lbeg; L < Lend; ++L) {
+    if (it >= stop_iter[L]) continue;  // uniform over the block
+    // P-point DFT over r on the way in: item (c, i3) holds the P values of
+    // its axis-2 positions, consecutive items consecutive i3
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int u = tid + i * NT;
+      if (NI % NT == 0 || u < NI) {
+        const int c = u / N3, i3 = u % N3;
+        const T2* src = tau + (long long)(L * 6 + c) * g.spec + row + i3;
+        T2 v[P];
+#pragma unroll
+        for (int rr = 0; rr < P; ++rr) v[rr] = src[rr * N3];
+        reg_fft<T, -1, P>(v, twP);
+#pragma unroll
+        for (int s = 0; s < P; ++s) lines[(s * 6 + c) * LS + i3] = v[s];
+      }
+    }
+    __syncthreads();
+    fft_static<T, -1, N3, NLN, false, NT>(lines, LS, 1, tw3);
+
+    // -Gamma^p_h / m at the bins (k1, k2 = q + Q s, k3)
+    for (int b = tid; b < NB; b += NT) {
+      const int s = b / N3, k3 = b - s * N3;
+      const long long pos2 = (long long)k1 * g.n2 + q + Q * s;
+      T G[21];
+      if constexpr (GM == GREEN_TABLE) {
+        const T* tb = table + pos2 * 21 * N3 + k3;
+#pragma unroll
+        for (int t = 0; t < 21; ++t) G[t] = (T)(scale * (double)tb[(long long)t * N3]);
+      } else {
+        moments_emit(table, pos2, N3, k3, mu0, riso, [&](int t, double v) { G[t] = (T)(scale * v); });
+      }
+      T2 v[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c] = lines[(s * 6 + c) * LS + k3];
+#pragma unroll
+      for (int I = 0; I < 6; ++I) {
+        T2 y = T2{0, 0};
+#pragma unroll
+        for (int J = 0; J < 6; ++J) {
+          const T gij = G[I <= J ? tri_idx(I, J) : tri_idx(J, I)];
+          y.x += gij * v[J].x;
+          y.y += gij * v[J].y;
+        }
+        lines[(s * 6 + I) * LS + k3] = y;
+      }
+    }
+    __syncthreads();
+    fft_static<T, +1, N3, NLN, false, NT>(lines, LS, 1, tw3);
+
+    // inverse P-point DFT over s on the way out; the residual against the
+    // previous iterate in this (k1, q, r, i3) domain
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int u = tid + i * NT;
+      if (NI % NT == 0 || u < NI) {
+        const int c = u / N3, i3 = u % N3;
+        const long long g0 = (long long)(L * 6 + c) * g.spec + row + i3;
+        T2 po[P];
+#pragma unroll
+        for (int rr = 0; rr < P; ++rr) po[rr] = Pold[g0 + rr * N3];
+        T2 v[P];
+#pragma unroll
+        for (int s = 0; s < P; ++s) v[s] = lines[(s * 6 + c) * LS + i3];
+        reg_fft<T, +1, P>(v, twP);
+#pragma unroll
+        for (int rr = 0; rr < P; ++rr) {
+          // variational scheme: the pass computes the correction, added to the old state
+          const T2 nv = ve ? cadd(v[rr], po[rr]) : v[rr];
+          Pnew[g0 + rr * N3] = nv;
+          const double dx = (double)nv.x - (double)po[rr].x, dy = (double)nv.y - (double)po[rr].y;
+          acc[0] += dx * dx + dy * dy;
+          acc[1] += (double)nv.x * (double)nv.x + (double)nv.y * (double)nv.y;
+        }
+      }
+    }
+    double tot[2];
+    block_sum<2>(acc, tot);  // ends with a barrier: the lines are free for the next load
+    if (tid == 0) {
+      partial[((long long)L * npos + pos) * 2] = wk1 * tot[0];
+      partial[((long long)L * npos + pos) * 2 + 1] = wk1 * tot[1];
+    }
+  }
+}
+
+// ------------------------------------------------------ state conversions ---
+// One thread per (load, comp, k1, r, i3); Q <= 8 values each.
+template <typename T>
+__global__ void __launch_bounds__(256) k_to_split(Geo g, int Q, const C2<T>* __restrict__ tw1,
+                                                  const C2<T>* __restrict__ X, C2<T>* __restrict__ Xs, int nload) {
+  using T2 = C2<T>;
+  const int P = g.n2 / Q;
+  const long long per = (long long)g.h1 * P * g.n3;
+  const long long n = per * 6 * nload;
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
+    const long long lc = t / per;
+    const long long rem = t % per;
+    const int i3 = (int)(rem % g.n3);
+    const int r = (int)((rem / g.n3) % P);
+    const int k1 = (int)(rem / ((long long)g.n3 * P));
+    const T2* src = X + lc * g.spec + (long long)k1 * g.n2 * g.n3 + i3;
+    T2* dst = Xs + lc * g.spec + (long long)k1 * Q * P * g.n3 + (long long)r * g.n3 + i3;
+    T2 x[8];
+    for (int j = 0; j < Q; ++j) x[j] = src[(long long)(r + P * j) * g.n3];
+    const T inv = (T)(1.0 / Q);
+    for (int q = 0; q < Q; ++q) {
+      T2 acc = T2{0, 0};
+      for (int j = 0; j < Q; ++j) acc = cadd(acc, cmul(x[j], tw1[((j * q) % Q) * P]));
+      acc = cmul(acc, tw1[r * q]);
+      dst[(long long)q * P * g.n3] = T2{acc.x * inv, acc.y * inv};
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_from_split(Geo g, int Q, const C2<T>* __restrict__ tw1,
+                                                    const C2<T>* __restrict__ Xs0, const C2<T>* __restrict__ Xs1,
+                                                    C2<T>* __restrict__ X, const int* __restrict__ stop_iter,
+                                                    const int* __restrict__ itp, int nload) {
+  using T2 = C2<T>;
+  const int P = g.n2 / Q;
+  const long long per = (long long)g.h1 * P * g.n3;
+  const long long n = per * 6 * nload;
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
+    const long long lc = t / per;
+    const int L = (int)(lc / 6);
+    const int its = min(stop_iter[L], *itp);
+    const T2* Xs = (its & 1) ? Xs1 : Xs0;
+    const long long rem = t % per;
+    const int i3 = (int)(rem % g.n3);
+    const int r = (int)((rem / g.n3) % P);
+    const int k1 = (int)(rem / ((long long)g.n3 * P));
+    const T2* src = Xs + lc * g.spec + (long long)k1 * Q * P * g.n3 + (long long)r * g.n3 + i3;
+    T2* dst = X + lc * g.spec + (long long)k1 * g.n2 * g.n3 + i3;
+    T2 x[8];
+    for (int q = 0; q < Q; ++q) {
+      T2 w = tw1[r * q];
+      w.y = -w.y;
+      x[q] = cmul(src[(long long)q * P * g.n3], w);
+    }
+    for (int j = 0; j < Q; ++j) {
+      T2 acc = T2{0, 0};
+      for (int q = 0; q < Q; ++q) {
+        T2 w = tw1[((j * q) % Q) * P];
+        w.y = -w.y;
+        acc = cadd(acc, cmul(x[q], w));
+      }
+      dst[(long long)(r + P * j) * g.n3] = acc;
+    }
+  }
+}
+
+// ----------------------------------------------------------- candidates ---
+template <int N1, int Q, int W>
+constexpr int stress2_nt() {
+  return N1 * Q * W >= 2048 ? 512 : 256;
+}
+template <int N3>
+constexpr int green3_nt() {
+  int nt = (6 * N3 + 63) / 64 * 64;
+  return nt > 1024 ? 1024 : nt;
+}
+
+template <typename T, int N, int Q, int W>
+void add_cand(const Geo& g, TwoPass<T>* out, int maxn, int* n) {
+  constexpr int P = N / Q;
+  static_assert(P * Q == N, "Q divides the axis-2 length");
+  if (*n >= maxn || g.n2 % Q != 0 || g.n3 % W != 0) return;
+  TwoPass<T> c;
+  constexpr int NTS = stress2_nt<N, Q, W>();
+  constexpr int NTG = green3_nt<N>();
+  c.s2 = k_stress2<T, N, Q, W, NTS>;
+  c.g3[GREEN_TABLE] = k_green3<T, P, N, NTG, GREEN_TABLE>;
+  c.g3[GREEN_MOMENTS] = k_green3<T, P, N, NTG, GREEN_MOMENTS>;
+  c.Q = Q;
+  c.P = P;
+  c.W = W;
+  c.nts = NTS;
+  c.ntg = NTG;
+  c.ldss = sizeof(C2<T>) * ((size_t)N + 2 * Q + (size_t)N * 3 * Q * W) + sizeof(T) * 36 * 16;
+  c.ldsg = sizeof(C2<T>) * ((size_t)N + P + (size_t)6 * P * (N + 1));
+  out[(*n)++] = c;
+}
+
+template <typename T>
+int candidates_t(const Geo& g, TwoPass<T>* out, int maxn) {
+  int n = 0;
+  // cubic SNF grids of the batched size classes and the 128^3 workloads;
+  // the first candidate of each is the default
+  if (g.n1 != g.n2 || g.n2 != g.n3) return 0;
+  if constexpr (sizeof(T) == 4) {
+    switch (g.n1) {
+      case 32:
+        add_cand<T, 32, 4, 8>(g, out, maxn, &n);
+        add_cand<T, 32, 2, 16>(g, out, maxn, &n);
+        break;
+      case 48:
+        add_cand<T, 48, 4, 8>(g, out, maxn, &n);
+        add_cand<T, 48, 3, 8>(g, out, maxn, &n);
+        break;
+      case 64:
+        add_cand<T, 64, 4, 8>(g, out, maxn, &n);
+        add_cand<T, 64, 8, 4>(g, out, maxn, &n);
+        break;
+      case 96:
+        add_cand<T, 96, 4, 8>(g, out, maxn, &n);
+        add_cand<T, 96, 8, 4>(g, out, maxn, &n);
+        add_cand<T, 96, 6, 4>(g, out, maxn, &n);
+        break;
+      case 128:
+        add_cand<T, 128, 8, 4>(g, out, maxn, &n);
+        break;
+      default:
+        break;
+    }
+  } else {
+    switch (g.n1) {
+      case 32:
+        add_cand<T, 32, 4, 8>(g, out, maxn, &n);
+        break;
+      case 48:
+        add_cand<T, 48, 4, 8>(g, out, maxn, &n);
+        break;
+      case 64:
+        add_cand<T, 64, 4, 8>(g, out, maxn, &n);
+        break;
+      default:
+        break;
+    }
+  }
+  return n;
+}
+
+template <typename T>
+void to_split_t(const Geo& g, int Q, const C2<T>* tw1, const C2<T>* X, C2<T>* Xs, int nload, hipStream_t st) {
+  const long long n = (long long)g.h1 * (g.n2 / Q) * g.n3 * 6 * nload;
+  const int nblk = (int)std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_to_split<T>, dim3(nblk), dim3(256), 0, st, g, Q, tw1, X, Xs, nload);
+}
+
+template <typename T>
+void from_split_t(const Geo& g, int Q, const C2<T>* tw1, const C2<T>* Xs0, const C2<T>* Xs1, C2<T>* X,
+                  const int* stop_iter, const int* itp, int nload, hipStream_t st) {
+  const long long n = (long long)g.h1 * (g.n2 / Q) * g.n3 * 6 * nload;
+  const int nblk = (int)std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_from_split<T>, dim3(nblk), dim3(256), 0, st, g, Q, tw1, Xs0, Xs1, X, stop_iter, itp, nload);
+}
+
+}  // namespace
+
+int twopass_candidates(const Geo& g, TwoPass<float>* out, int maxn) { return candidates_t<float>(g, out, maxn); }
+int twopass_candidates(const Geo& g, TwoPass<double>* out, int maxn) { return candidates_t<double>(g, out, maxn); }
+
+void twopass_to_split(const Geo& g, int Q, const C2<float>* tw1, const C2<float>* X, C2<float>* Xs, int nload,
+                      hipStream_t st) {
+  to_split_t<float>(g, Q, tw1, X, Xs, nload, st);
+}
+void twopass_to_split(const Geo& g, int Q, const C2<double>* tw1, const C2<double>* X, C2<double>* Xs, int nload,
+                      hipStream_t st) {
+  to_split_t<double>(g, Q, tw1, X, Xs, nload, st);
+}
+void twopass_from_split(const Geo& g, int Q, const C2<float>* tw1, const C2<float>* Xs0, const C2<float>* Xs1,
+                        C2<float>* X, const int* stop_iter, const int* itp, int nload, hipStream_t st) {
+  from_split_t<float>(g, Q, tw1, Xs0, Xs1, X, stop_iter, itp, nload, st);
+}
+void twopass_from_split(const Geo& g, int Q, const C2<double>* tw1, const C2<double>* Xs0, const C2<double>* Xs1,
+                        C2<double>* X, const int* stop_iter, const int* itp, int nload, hipStream_t st) {
+  from_split_t<double>(g, Q, tw1, Xs0, Xs1, X, stop_iter, itp, nload, st);
+}

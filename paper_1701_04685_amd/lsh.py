@@ -162,7 +162,7 @@ def _device_bytes(n):
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("choice", ctypes.c_int * 3), ("ncand", ctypes.c_int * 3), ("ms", (ctypes.c_float * 8) * 3)]
+    _fields_ = [("choice", ctypes.c_int * 4), ("ncand", ctypes.c_int * 4), ("ms", (ctypes.c_float * 8) * 4)]
 
 
 class Pattern:
@@ -283,7 +283,7 @@ class Pattern:
                                ctypes.byref(res))
         _done_on(S)
         _check(rc)
-        names = ["stress", "axis2", "green"]
+        names = ["stress", "axis2", "green", "schedule"]
         return {n: {"choice": res.choice[i], "ms": [round(res.ms[i][c], 5) for c in range(res.ncand[i])]}
                 for i, n in enumerate(names)}
 
@@ -291,8 +291,11 @@ class Pattern:
         _check(_lib.lsh_tune_reset(self._h))
 
     def tune_set(self, choice, precision=None):
+        """Force the variants: (stress, axis2, green[, schedule]); schedule 0 is
+        the four-pass iteration, i > 0 the two-pass variant i - 1."""
         p = self._prec if precision is None else (PRECISIONS[precision] if isinstance(precision, str) else precision)
-        arr = (ctypes.c_int * 3)(*[int(c) for c in choice])
+        ch = [int(c) for c in choice] + [0] * (4 - len(choice))
+        arr = (ctypes.c_int * 4)(*ch)
         _check(_lib.lsh_tune_set(self._h, int(p), arr))
 
     def solve(self, eps0_voigt, tol=1e-10, max_iter=1000, E_init=None, return_E=False, history=False,

@@ -1,0 +1,176 @@
+"""The two-pass iteration (axis 2 split between the stress and Green passes as a
+four-step DFT) against the FP64 oracle.
+
+Every two-pass variant built for a grid is forced with lsh_tune_set and run in
+lock step (a fixed iteration count on both sides): element by element on E and
+sigma_bar at 1e-10 (FP64) and 1e-5 (FP32), the residual history at 100 times
+that.  Also: both tabled Green forms (alias moments for an isotropic C0, the
+Box table), the variational scheme, a start field and field output through the
+layout conversions, converged solves whose loads stop at different iterations
+(each load's last state sits in the buffer of its own parity), a batch, and the
+autotuner's schedule choice.
+"""
+import numpy as np
+import pytest
+
+import lsh_inputs as li
+from helpers import BOX_CFG3, Problem, two_phase
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+LOADS = np.eye(6)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300)
+
+
+def rsa_phase(seed, frac, rmin=2.0, rmax=4.0):
+    def f(Y):
+        c, r = li.rsa_spheres(seed, li.lattice_unit(len(Y)), frac, rmin=rmin, rmax=rmax, max_attempts=200_000)
+        return li.spheres_phase(Y, c, r)
+    return f
+
+
+_CACHE = {}
+
+
+def problem(n, kind):
+    key = (n, kind)
+    if key not in _CACHE:
+        Cp, C0 = two_phase(1.0, 20.0)
+        params = {"dlvp": {"alpha": [0.75] * 3}, "box": {"Xi": BOX_CFG3["Xi"], "R": 1}}.get(kind, {})
+        _CACHE[key] = (Problem(np.diag([n, n, n]), kind, params, rsa_phase(700 + n, 0.3), Cp, C0), {})
+    return _CACHE[key]
+
+
+def oracle(pr, refs, j, n_iter):
+    if (j, n_iter) not in refs:
+        refs[(j, n_iter)] = pr.oracle_solve(LOADS[j], n_iter=n_iter)
+    return refs[(j, n_iter)]
+
+
+def two_pass_variants(pr, prec):
+    """Number of two-pass variants the autotuner times for this grid (its
+    schedule entry lists the four-pass iteration first)."""
+    info = pr.G.autotune(nload=2)
+    return len(info["schedule"]["ms"]) - 1
+
+
+def lockstep(pr, refs, prec, variant, loads=(0, 3), n_iter=4):
+    pr.G.tune_set([0, 0, 0, variant + 1])
+    res = pr.G.solve(LOADS[list(loads)], tol=-1.0, max_iter=n_iter, return_E=True, history=True)
+    for i, j in enumerate(loads):
+        ref = oracle(pr, refs, j, n_iter)
+        assert rel(res["sigma"][i], ref["sigma_voigt"]) < TOL[prec], (variant, j)
+        assert rel(pr.gpu_E_to_oracle_mandel(res["E"][i].cpu().numpy()), ref["E"]) < TOL[prec], (variant, j)
+        np.testing.assert_allclose(res["history"][i], ref["history"], rtol=100 * TOL[prec])
+
+
+CASES = [(32, "dlvp", "fp32"), (48, "dlvp", "fp32"), (64, "dlvp", "fp32"), (96, "dirichlet", "fp32"),
+         (128, "dirichlet", "fp32"), (32, "dlvp", "fp64"), (48, "dirichlet", "fp64"), (64, "dlvp", "fp64"),
+         (32, "box", "fp32"), (32, "box", "fp64")]
+
+
+@pytest.mark.parametrize("n,kind,prec", CASES)
+def test_every_two_pass_variant_lockstep(n, kind, prec):
+    pr, refs = problem(n, kind)
+    pr.bind(prec)
+    nv = two_pass_variants(pr, prec)
+    assert nv >= 1, "no two-pass variant for this grid"
+    for v in range(nv):
+        print(f"two-pass variant {v} n={n} {kind} {prec}", flush=True)
+        lockstep(pr, refs, prec, v)
+    pr.G.tune_reset()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_two_pass_converged_loads_stop_apart(prec):
+    """Six loads to 1e-9 (FP64) or 1e-5 (FP32): the loads stop at different
+    iterations; iteration counts, sigma_bar and E equal the four-pass solve's."""
+    pr, _ = problem(32, "dlvp")
+    pr.bind(prec)
+    tol = 1e-9 if prec == "fp64" else 1e-5
+    pr.G.tune_set([0, 0, 0, 0])
+    four = pr.G.solve(LOADS, tol=tol, max_iter=500, return_E=True)
+    pr.G.tune_set([0, 0, 0, 1])
+    two = pr.G.solve(LOADS, tol=tol, max_iter=500, return_E=True)
+    pr.G.tune_reset()
+    assert len(set(four["iterations"].tolist())) > 1, four["iterations"]  # the loads do stop apart
+    assert list(two["iterations"]) == list(four["iterations"])
+    assert rel(two["sigma"], four["sigma"]) < TOL[prec]
+    assert rel(two["E"].cpu().numpy(), four["E"].cpu().numpy()) < TOL[prec]
+
+
+def test_two_pass_start_field_lockstep():
+    """A random start field (mean removed on both sides) through the conversion
+    into the split layout, against the oracle from the same field."""
+    import torch
+    from oracle import green, scheme
+    pr, _ = problem(48, "dlvp")
+    pr.bind("fp64")
+    rng = np.random.default_rng(71)
+    Eo = rng.standard_normal((pr.O.m, 6)) * 0.05 + 0.02
+    Ev = np.zeros((6, pr.O.m))
+    Ev[:, pr.q] = green.mandel_strain_to_voigt(Eo).T
+    eps0 = np.array([0.1, 0.2, -0.3, 0.05, 0.0, 0.15])
+    pr.G.tune_set([0, 0, 0, 1])
+    res = pr.G.solve(eps0[None], tol=-1.0, max_iter=4, E_init=torch.tensor(Ev[None], device="cuda"),
+                     return_E=True, history=True)
+    pr.G.tune_reset()
+    ref = scheme.basic_scheme(pr.O, pr.gamma_oracle(), pr.Cp, pr.C0, pr.phase_o, eps0, n_iter=4, E_init=Eo)
+    np.testing.assert_allclose(res["history"][0], ref["history"], rtol=1e-8)
+    assert rel(pr.gpu_E_to_oracle_mandel(res["E"][0].cpu().numpy()), ref["E"]) < TOL["fp64"]
+    assert rel(res["sigma"][0], ref["sigma_voigt"]) < TOL["fp64"]
+
+
+def test_two_pass_variational_lockstep():
+    """The variational scheme (the Green pass adds its correction to the old
+    state) on the two-pass iteration against the oracle's variational scheme."""
+    from helpers import Problem as Pb
+    Cp, C0 = two_phase(1.0, 20.0)
+    pr = Pb(np.diag([32, 32, 32]), "dlvp", {"alpha": [0.75] * 3}, rsa_phase(77, 0.3), Cp, C0)
+    pr.G.set_scheme("ve")
+    pr.bind("fp64")
+    pr.G.tune_set([0, 0, 0, 1])
+    eps0 = LOADS[0]
+    res = pr.G.solve(eps0[None], tol=-1.0, max_iter=5, return_E=True)
+    pr.G.tune_reset()
+    ref = pr.oracle_solve_ve(eps0, n_iter=5)
+    assert rel(res["sigma"][0], ref["sigma_voigt"]) < TOL["fp64"]
+    assert rel(pr.gpu_E_to_oracle_mandel(res["E"][0].cpu().numpy()), ref["E"]) < TOL["fp64"]
+
+
+def test_two_pass_batch_lockstep():
+    """A batch of 32^3 and 48^3 packings of several contrasts, each size class
+    on its two-pass schedule (chosen on its first pattern), FP32, 3 iterations:
+    every task against the oracle."""
+    from paper_1701_04685_amd import lsh
+    prs = []
+    for i, (n, contrast) in enumerate([(32, 5.0), (48, 30.0), (32, 50.0), (48, 8.0)]):
+        Cp, C0 = two_phase(1.0, contrast)
+        prs.append(Problem(np.diag([n, n, n]), "dirichlet", {}, rsa_phase(800 + i, 0.25), Cp, C0))
+    for pr in prs:
+        pr.bind("fp32")
+        pr.G.tune_set([0, 0, 0, 1])
+    loads = [LOADS[[0, 5]]] * len(prs)
+    out = lsh.solve_batch([pr.G for pr in prs], loads, tol=-1.0, max_iter=3, precision="fp32", return_E=True)
+    for pr, o in zip(prs, out):
+        for i, j in enumerate((0, 5)):
+            ref = pr.oracle_solve(LOADS[j], n_iter=3)
+            assert rel(o["sigma"][i], ref["sigma_voigt"]) < TOL["fp32"]
+            assert rel(pr.gpu_E_to_oracle_mandel(o["E"][i].cpu().numpy()), ref["E"]) < TOL["fp32"]
+
+
+def test_autotune_reports_schedule():
+    pr, refs = problem(64, "dlvp")
+    pr.bind("fp32")
+    info = pr.G.autotune(nload=6)
+    ms = info["schedule"]["ms"]
+    assert len(ms) >= 2 and all(t > 0 for t in ms)
+    assert ms[info["schedule"]["choice"]] == min(ms)
+    res = pr.G.solve(LOADS[[0]], tol=-1.0, max_iter=4, return_E=True)
+    ref = oracle(pr, refs, 0, 4)
+    assert rel(res["sigma"][0], ref["sigma_voigt"]) < TOL["fp32"]
+    pr.G.tune_reset()
