@@ -136,15 +136,30 @@ def _cfg4_instance(i):
     return n, contrast, ph
 
 
-def bench_cfg4(args):
-    """Batched FP32: 256 packings, n in {32,48,64,96}, 6 unit loads each, Dirichlet, tol 1e-6."""
+def _step_bytes(n, nload, two_pass, s=4):
+    """Algorithmic HBM bytes of one iteration of an n^3 instance with nload loads:
+    four passes move 9 half-spectrum fields (read E, write tau; axis 2 twice;
+    read tau and the old E, write E) plus the phase map, the two-pass schedule
+    5 fields plus the phase map."""
+    field = nload * 6 * (n // 2 + 1) * n * n * 2 * s
+    return (5 if two_pass else 9) * field + nload * n ** 3
+
+
+def cfg4_instances(ninst):
+    """The batched workload's packings, generated in worker processes (call this
+    before the process touches the GPU)."""
     import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        return pool.map(_cfg4_instance, range(ninst))
+
+
+def measure_cfg4(args, inst, steps):
+    """Batched FP32: the packings inst (n in {32,48,64,96}), 6 unit loads each,
+    Dirichlet, tol 1e-6; each size class is autotuned on its first pattern."""
     import torch
     from paper_1701_04685_amd import lsh
     import lsh_inputs as li
-    ninst = args.instances
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        inst = pool.map(_cfg4_instance, range(ninst))
+    ninst = len(inst)
     torch.cuda.set_device(0)
     pats, loads = [], []
     for n, contrast, ph in inst:
@@ -158,7 +173,6 @@ def bench_cfg4(args):
         loads.append(np.eye(6))
     nbytes = lsh.batch_workspace_bytes(pats, [6] * ninst, "fp32")
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    # autotune each size class on its first pattern (the batch group's representative)
     tuned = {}
     for n in sorted({P.e[0] for P in pats}):
         first = next(P for P in pats if P.e[0] == n)
@@ -167,11 +181,14 @@ def bench_cfg4(args):
     lsh.solve_batch(pats, loads, tol=-1.0, max_iter=max(2, args.warmup), precision="fp32", workspace=ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lsh.solve_batch(pats, loads, tol=-1.0, max_iter=args.steps, precision="fp32", workspace=ws)
+    lsh.solve_batch(pats, loads, tol=-1.0, max_iter=steps, precision="fp32", workspace=ws)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     vox = sum(P.m for P in pats) * 6
-    value = vox * args.steps / wall
+    value = vox * steps / wall
+    two_pass = {n: t["schedule"]["choice"] > 0 for n, t in tuned.items()}
+    step_bytes = sum(_step_bytes(P.e[0], 6, two_pass[str(P.e[0])]) for P in pats)
+    achieved = step_bytes / (wall / steps) / 1e9
     t0 = time.perf_counter()
     res = lsh.solve_batch(pats, loads, tol=1e-6, max_iter=3000, precision="fp32", workspace=ws,
                           allow_notconverged=True)
@@ -179,26 +196,41 @@ def bench_cfg4(args):
     ts = time.perf_counter() - t0
     its = np.concatenate([r["iterations"] for r in res])
     done_vi = float(sum(P.m * r["iterations"].sum() for P, r in zip(pats, res)))
-    bytes_vi = 54 * 4 + 1
-    out = {"metric": METRIC, "value": value, "unit": "voxel-iters/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"batched: {ninst} sphere packings n in {{32,48,64,96}}, 6 unit loads each, "
-                                  "Dirichlet, FP32 (FP64 reductions), one HIP graph per two iterations",
-                      "instances": ninst, "tasks": ninst * 6, "voxel_states": vox,
-                      "workspace_GB": round(nbytes / 1e9, 2)},
-           "roofline": {"bound": "hbm", "approx_bytes_per_voxel_iter": bytes_vi,
-                        "achieved_GBps": round(value * bytes_vi / 1e9, 1), "peak": HBM_PEAK_GBS,
-                        "frac": round(value * bytes_vi / 1e9 / HBM_PEAK_GBS, 4)},
-           "cpu_baseline": None, "autotune": tuned,
-           "solve_to_tol": {"tol": 1e-6, "seconds": round(ts, 3), "voxel_iters_per_s": done_vi / ts,
-                            "iterations_min_median_max": [int(its.min()), int(np.median(its)), int(its.max())],
-                            "converged": int(sum(r["converged"].sum() for r in res))}}
+    del ws
+    return {"value": value, "unit": "voxel-iters/s", "ms_per_step": wall / steps * 1e3, "steps": steps,
+            "dtype": "f32",
+            "config": {"workload": f"batched: {ninst} sphere packings n in {{32,48,64,96}}, 6 unit loads each, "
+                                   "Dirichlet, FP32 (FP64 reductions), one HIP graph per two iterations",
+                       "instances": ninst, "tasks": ninst * 6, "voxel_states": vox,
+                       "workspace_GB": round(nbytes / 1e9, 2)},
+            "schedule_by_size": {n: ("two-pass" if v else "four-pass") for n, v in two_pass.items()},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "alg_bytes_per_step": int(step_bytes),
+                         "bytes_per_voxel_iter": round(step_bytes / vox, 1),
+                         # the three-pass minimum of 42 s + 1 = 169 B per voxel-iteration at 8 TB/s
+                         "frac_of_169B_roofline": round(value * 169 / (HBM_PEAK_GBS * 1e9), 4)},
+            "autotune": tuned,
+            "solve_to_tol": {"tol": 1e-6, "seconds": round(ts, 3), "voxel_iters_per_s": done_vi / ts,
+                             "iterations_min_median_max": [int(its.min()), int(np.median(its)), int(its.max())],
+                             "converged": int(sum(r["converged"].sum() for r in res))}}
+
+
+def bench_cfg4(args):
+    """Batched FP32: 256 packings, n in {32,48,64,96}, 6 unit loads each, Dirichlet, tol 1e-6."""
+    m = measure_cfg4(args, cfg4_instances(args.instances), args.steps)
+    out = {"metric": METRIC, "value": m["value"], "unit": "voxel-iters/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": m["config"],
+           "roofline": m["roofline"], "cpu_baseline": None,
+           **{k: m[k] for k in ("schedule_by_size", "autotune", "solve_to_tol")}}
     print(json.dumps(out), flush=True)
 
 
-def bench_cfg3(args):
-    """FP32 mixed precision, non-diagonal M, Box spline {e1,e2,e3,e1+e2}, RSA spheres f = 0.3, contrast 100."""
+def measure_cfg3(args, steps):
+    """FP32 mixed precision, non-diagonal M, Box spline {e1,e2,e3,e1+e2} (R = 16),
+    RSA spheres f = 0.3, contrast 100, six loads: iteration rate, the solve to
+    1e-6, and the FP32 C^eff against an FP64 solve at the same iteration counts."""
     import torch
     from paper_1701_04685_amd import lsh
     import lsh_inputs as li
@@ -216,32 +248,56 @@ def bench_cfg3(args):
     loads = np.eye(6)
     ws = torch.empty(P.workspace_bytes(6), dtype=torch.uint8, device="cuda")
     tuned = P.autotune(nload=6, workspace=ws)
-    P.solve(loads, tol=-1.0, max_iter=args.warmup, workspace=ws)
+    P.solve(loads, tol=-1.0, max_iter=max(1, args.warmup), workspace=ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    P.solve(loads, tol=-1.0, max_iter=args.steps, workspace=ws)
+    P.solve(loads, tol=-1.0, max_iter=steps, workspace=ws)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    value = 6 * P.m * args.steps / wall
+    value = 6 * P.m * steps / wall
     t0 = time.perf_counter()
     res = P.solve(loads, tol=1e-6, max_iter=5000, workspace=ws, allow_notconverged=True)
     ts = time.perf_counter() - t0
-    bytes_vi = 54 * 4 + 1 + 21 * 4 / 2 / 6
     C = res["sigma"].T
-    out = {"metric": METRIC, "value": value, "unit": "voxel-iters/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "M=[[128,32,0],[0,128,0],[0,0,64]], Box {e1,e2,e3,e1+e2} R=16, RSA spheres f=0.3 "
-                                  "contrast 100, 6 unit loads, FP32 mixed", "m": P.m, "snf": list(P.e),
-                      "sphere_fraction": float(ph.mean()), "gamma_table_build_s": round(tb, 3)},
-           "roofline": {"bound": "hbm", "approx_bytes_per_voxel_iter": round(bytes_vi, 1),
-                        "achieved_GBps": round(value * bytes_vi / 1e9, 1), "peak": HBM_PEAK_GBS},
-           "cpu_baseline": None, "autotune": tuned,
-           "solve_to_tol": {"tol": 1e-6, "iterations": [int(v) for v in res["iterations"]], "seconds": round(ts, 3),
-                            "C_eff_asym": float(np.linalg.norm(C - C.T) / np.linalg.norm(C))}}
+    # the same iteration counts on the FP64 path: the FP32 path's error on C^eff
+    P.bind("fp64")
+    ws64 = torch.empty(P.workspace_bytes(1), dtype=torch.uint8, device="cuda")
+    C64 = np.zeros((6, 6))
+    for j in range(6):
+        C64[:, j] = P.solve(loads[j:j + 1], tol=-1.0, max_iter=int(res["iterations"][j]), workspace=ws64)["sigma"][0]
+    del ws64
+    spec = (P.e[0] // 2 + 1) * P.e[1] * P.e[2]
+    step_bytes = 9 * 6 * 6 * spec * 8 + 6 * P.m + 21 * 4 * spec  # four passes, the Box table read once per chunk
+    return {"value": value, "unit": "voxel-iters/s", "ms_per_step": wall / steps * 1e3, "steps": steps,
+            "dtype": "f32",
+            "config": {"workload": "M=[[128,32,0],[0,128,0],[0,0,64]], Box {e1,e2,e3,e1+e2} R=16, RSA spheres "
+                                   "f=0.3 contrast 100, 6 unit loads, FP32 mixed", "m": P.m, "snf": list(P.e),
+                       "sphere_fraction": float(ph.mean()), "gamma_table_build_s": round(tb, 3)},
+            "roofline": {"bound": "hbm", "achieved": round(step_bytes / (wall / steps) / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(step_bytes / (wall / steps) / 1e9 / HBM_PEAK_GBS, 4),
+                         "bytes_per_voxel_iter": round(step_bytes / (6 * P.m), 1),
+                         # 42 s + 1 + 10.5 s = 211 B per voxel-iteration (three passes, stored table)
+                         "frac_of_211B_roofline": round(value * 211 / (HBM_PEAK_GBS * 1e9), 4)},
+            "autotune": tuned,
+            "solve_to_tol": {"tol": 1e-6, "iterations": [int(v) for v in res["iterations"]],
+                             "seconds": round(ts, 3), "C_eff_asym": float(np.linalg.norm(C - C.T) / np.linalg.norm(C))},
+            "fp32_vs_fp64_C_eff_rel_diff": float(np.linalg.norm(C - C64) / np.linalg.norm(C64)), "_P": P}
+
+
+def bench_cfg3(args):
+    """The non-diagonal Box workload's line, plus the Box alias sums' truncation study."""
+    import torch
+    m = measure_cfg3(args, args.steps)
+    P = m.pop("_P")
+    out = {"metric": METRIC, "value": m["value"], "unit": "voxel-iters/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": m["config"],
+           "roofline": m["roofline"], "cpu_baseline": None,
+           **{k: m[k] for k in ("autotune", "solve_to_tol", "fp32_vs_fp64_C_eff_rel_diff")}}
     # the Box alias sums' truncation: C^eff (FP64, tol 1e-8) with R = 16 as is,
     # with its tail, and with R = 32 and its tail as the reference
-    del ws
+    loads = np.eye(6)
     Xi = np.array([[1, 0, 0, 1], [0, 1, 0, 1], [0, 0, 1, 0]], float)
     ceff = {}
     for name, kp in (("R16", {"Xi": Xi, "R": 16}), ("R16_tail", {"Xi": Xi, "R": 16, "tail": True}),
@@ -687,6 +743,8 @@ def main():
     ap.add_argument("--eval-packings", type=int, default=200, help="cfg5: unseen 128^3 packings")
     ap.add_argument("--ablation-packings", type=int, default=10, help="cfg5: packings also run with the untrained net")
     ap.add_argument("--instances", type=int, default=256, help="cfg4: number of microstructures")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default workload: leave out the batched and non-diagonal Box lines")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -700,6 +758,9 @@ def main():
 
     if args.workload == "cfg4":
         return bench_cfg4(args)  # generates its inputs in worker processes before touching the GPU
+    # the default line also carries the batched workload: its packings come
+    # from worker processes, before this process touches the GPU
+    inst4 = cfg4_instances(args.instances) if args.workload == "cfg2" and not args.no_extra else None
     torch.cuda.set_device(0)
     if args.workload == "cfg3":
         return bench_cfg3(args)
@@ -798,6 +859,20 @@ def main():
                 "E_rel_diff_load_e11": dE, "iterations": [int(v) for v in res["iterations"]]}
         del P32, ws32
 
+    # the other single-GPU workloads, each with its own roofline figure: the
+    # batched FP32 workload (256 packings) and the non-diagonal Box FP32 one
+    extra = {}
+    cfg2_config = {"m": P.m, "snf": list(P.e)}
+    if inst4 is not None:
+        del ws, P
+        torch.cuda.empty_cache()
+        extra["batched_fp32"] = measure_cfg4(args, inst4, 20)
+        torch.cuda.empty_cache()
+        m3 = measure_cfg3(args, 100)
+        m3.pop("_P")
+        extra["nondiagonal_box_fp32"] = m3
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline()
@@ -807,7 +882,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "128^3 diagonal pattern, dlVP alpha=3/4, centred sphere f=0.2, contrast 10, "
-                               "6 unit load cases, FP64 Basic Scheme", "m": P.m, "snf": list(P.e),
+                               "6 unit load cases, FP64 Basic Scheme", **cfg2_config,
                    "nload": nload, "kernel": "dlvp", "precision": "fp64"},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -820,6 +895,7 @@ def main():
         "step_frac_of_three_pass_minimum": round(value * (42 * 8 + 1) / (HBM_PEAK_GBS * 1e9), 4),
         "solve_to_tol": solve_info,
         "fp32_vs_fp64": fp32,
+        **extra,
     }
     print(json.dumps(out), flush=True)
 

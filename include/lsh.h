@@ -259,8 +259,8 @@ int lsh_solve_noalloc(lsh_pattern *p, int nload, const double *eps0_voigt, doubl
  * splits the axis-2 transform between the stress pass and the Green pass (a
  * four-step DFT) and moves 30 s + 1 bytes per voxel and load instead of
  * 54 s + 1 (s = 8 in FP64, 4 in FP32); it exists for the cubic SNF grids 32,
- * 48, 64, 96 and 128 (FP32) and 32, 48, 64 (FP64), with an isotropic C0 or a
- * tabled Green operator, and not for conjugate gradients.
+ * 48, 64 and 96 (FP32) and 32 (FP64), with an isotropic C0 or a tabled Green
+ * operator, and not for conjugate gradients.
  * The choice is dropped by lsh_set_kernel and lsh_tune_reset.  Needs the solve
  * workspace (lsh_solve_bytes); its contents are scratch.  Synchronises `stream`.
  *   out (optional): the chosen variant per pass (0 = the default), the number

@@ -183,11 +183,14 @@ __global__ void __launch_bounds__(NT) k_stress2(Geo g, const C2<T>* __restrict__
 // -------------------------------------------------------------- Green pass ---
 // One block: position (k1, q) and a chunk of up to six loads of one instance,
 // one load at a time.  LDS: axis-3 twiddles [N3], w_P^k [P], lines
-// [(s, comp)][LS] along axis 3.  Per load: the tile's P n3 values of each
-// component come in with the P-point DFT over r done in registers, the axis-3
-// transforms run in LDS, -Gamma^p/m is applied per bin (k1, q + Q s, k3), and
-// the values go out through the inverse transforms, the inverse P-point DFT
-// again in registers, with the Cauchy residual's partial sums (double).
+// [(s, comp)][LS] along axis 3.  The Green operator -Gamma^p/m of the tile's
+// bins (k1, q + Q s, k3) is formed once per chunk into registers (each thread
+// keeps the NB2 bins it multiplies).  Per load: the tile's P n3 values of
+// each component come in with the P-point DFT over r done in registers (the
+// next load's values are fetched while this one is transformed), the axis-3
+// transforms run in LDS, and the values go out through the inverse
+// transforms, the inverse P-point DFT again in registers, with the Cauchy
+// residual's partial sums (double).
 template <typename T, int P, int N3, int NT, int GM>
 __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ tw1, const C2<T>* __restrict__ tw2,
                                                const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
@@ -203,6 +206,7 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
   constexpr int NI = 6 * N3;  // items (comp, i3) of the P-point stages
   constexpr int IT = (NI + NT - 1) / NT;
   constexpr int NB = P * N3;  // bins of the tile
+  constexpr int NB2 = (NB + NT - 1) / NT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* tw3 = reinterpret_cast<T2*>(smem_raw);
   T2* twP = tw3 + N3;
@@ -220,58 +224,90 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
   const int tid = threadIdx.x;
   const double wk1 = (k1 == 0 || 2 * k1 == g.n1) ? 1.0 : 2.0;
   const long long row = (long long)(k1 * Q + q) * P * N3;  // the tile's first element in a component
-  const double scale = -1.0 / (double)g.m;
-  const double mu0 = insts[inst_of[Lbeg]].mu0, riso = insts[inst_of[Lbeg]].riso;
+
+  // tau of item i of load L: P values at stride n3
+  T2 pf[IT][P];
+  auto fetch = [&](int L) {
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int u = tid + i * NT;
+      const int c = u / N3, i3 = u % N3;
+      const bool ok = NI % NT == 0 || u < NI;
+      const T2* src = tau + (long long)(L * 6 + (ok ? c : 0)) * g.spec + row + (ok ? i3 : 0);
+#pragma unroll
+      for (int rr = 0; rr < P; ++rr) pf[i][rr] = ok ? src[rr * N3] : T2{0, 0};
+    }
+  };
+  auto next_active = [&](int L) {
+    while (L < Lend && it >= stop_iter[L]) ++L;
+    return L;
+  };
+  int L = next_active(Lbeg);
+  fetch(L);  // in flight while the Green operator is formed
+
   stage_twiddles<T>(tw3, tw2, N3);
   for (int i = tid; i < P; i += NT) twP[i] = tw1[i * Q];
+  // -Gamma^p_h / m at this thread's bins (k1, k2 = q + Q s, k3), b = tid + k NT
+  T Gr[NB2][21];
+  {
+    const double scale = -1.0 / (double)g.m;
+    const double mu0 = insts[inst_of[Lbeg]].mu0, riso = insts[inst_of[Lbeg]].riso;
+#pragma unroll
+    for (int k = 0; k < NB2; ++k) {
+      const int b = tid + k * NT;
+      const int s = (b < NB ? b : 0) / N3, k3 = (b < NB ? b : 0) % N3;
+      const long long pos2 = (long long)k1 * g.n2 + q + Q * s;
+      if constexpr (GM == GREEN_TABLE) {
+        const T* tb = table + pos2 * 21 * N3 + k3;
+#pragma unroll
+        for (int t = 0; t < 21; ++t) Gr[k][t] = (T)(scale * (double)tb[(long long)t * N3]);
+      } else {
+        moments_emit(table, pos2, N3, k3, mu0, riso, [&](int t, double v) { Gr[k][t] = (T)(scale * v); });
+      }
+    }
+  }
   __syncthreads();
 
-  for (int L = Lbeg; L < Lend; ++L) {
-    if (it >= stop_iter[L]) continue;  // uniform over the block
-    // P-point DFT over r on the way in: item (c, i3) holds the P values of
-    // its axis-2 positions, consecutive items consecutive i3
+  while (L < Lend) {
+    // P-point DFT over r on the way in (item (c, i3), consecutive items
+    // consecutive i3), then the next active load's values are fetched
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int u = tid + i * NT;
       if (NI % NT == 0 || u < NI) {
         const int c = u / N3, i3 = u % N3;
-        const T2* src = tau + (long long)(L * 6 + c) * g.spec + row + i3;
         T2 v[P];
 #pragma unroll
-        for (int rr = 0; rr < P; ++rr) v[rr] = src[rr * N3];
+        for (int rr = 0; rr < P; ++rr) v[rr] = pf[i][rr];
         reg_fft<T, -1, P>(v, twP);
 #pragma unroll
         for (int s = 0; s < P; ++s) lines[(s * 6 + c) * LS + i3] = v[s];
       }
     }
+    const int Lnext = next_active(L + 1);
+    if (Lnext < Lend) fetch(Lnext);
     __syncthreads();
     fft_static<T, -1, N3, NLN, false, NT>(lines, LS, 1, tw3);
 
-    // -Gamma^p_h / m at the bins (k1, k2 = q + Q s, k3)
-    for (int b = tid; b < NB; b += NT) {
-      const int s = b / N3, k3 = b - s * N3;
-      const long long pos2 = (long long)k1 * g.n2 + q + Q * s;
-      T G[21];
-      if constexpr (GM == GREEN_TABLE) {
-        const T* tb = table + pos2 * 21 * N3 + k3;
 #pragma unroll
-        for (int t = 0; t < 21; ++t) G[t] = (T)(scale * (double)tb[(long long)t * N3]);
-      } else {
-        moments_emit(table, pos2, N3, k3, mu0, riso, [&](int t, double v) { G[t] = (T)(scale * v); });
-      }
-      T2 v[6];
+    for (int k = 0; k < NB2; ++k) {
+      const int b = tid + k * NT;
+      if (NB % NT == 0 || b < NB) {
+        const int s = b / N3, k3 = b - s * N3;
+        T2 v[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) v[c] = lines[(s * 6 + c) * LS + k3];
+        for (int c = 0; c < 6; ++c) v[c] = lines[(s * 6 + c) * LS + k3];
 #pragma unroll
-      for (int I = 0; I < 6; ++I) {
-        T2 y = T2{0, 0};
+        for (int I = 0; I < 6; ++I) {
+          T2 y = T2{0, 0};
 #pragma unroll
-        for (int J = 0; J < 6; ++J) {
-          const T gij = G[I <= J ? tri_idx(I, J) : tri_idx(J, I)];
-          y.x += gij * v[J].x;
-          y.y += gij * v[J].y;
+          for (int J = 0; J < 6; ++J) {
+            const T gij = Gr[k][I <= J ? tri_idx(I, J) : tri_idx(J, I)];
+            y.x += gij * v[J].x;
+            y.y += gij * v[J].y;
+          }
+          lines[(s * 6 + I) * LS + k3] = y;
         }
-        lines[(s * 6 + I) * LS + k3] = y;
       }
     }
     __syncthreads();
@@ -286,19 +322,17 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
       if (NI % NT == 0 || u < NI) {
         const int c = u / N3, i3 = u % N3;
         const long long g0 = (long long)(L * 6 + c) * g.spec + row + i3;
-        T2 po[P];
-#pragma unroll
-        for (int rr = 0; rr < P; ++rr) po[rr] = Pold[g0 + rr * N3];
         T2 v[P];
 #pragma unroll
         for (int s = 0; s < P; ++s) v[s] = lines[(s * 6 + c) * LS + i3];
         reg_fft<T, +1, P>(v, twP);
 #pragma unroll
         for (int rr = 0; rr < P; ++rr) {
+          const T2 po = Pold[g0 + rr * N3];
           // variational scheme: the pass computes the correction, added to the old state
-          const T2 nv = ve ? cadd(v[rr], po[rr]) : v[rr];
+          const T2 nv = ve ? cadd(v[rr], po) : v[rr];
           Pnew[g0 + rr * N3] = nv;
-          const double dx = (double)nv.x - (double)po[rr].x, dy = (double)nv.y - (double)po[rr].y;
+          const double dx = (double)nv.x - (double)po.x, dy = (double)nv.y - (double)po.y;
           acc[0] += dx * dx + dy * dy;
           acc[1] += (double)nv.x * (double)nv.x + (double)nv.y * (double)nv.y;
         }
@@ -310,6 +344,7 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
       partial[((long long)L * npos + pos) * 2] = wk1 * tot[0];
       partial[((long long)L * npos + pos) * 2 + 1] = wk1 * tot[1];
     }
+    L = Lnext;
   }
 }
 
@@ -385,9 +420,13 @@ template <int N1, int Q, int W>
 constexpr int stress2_nt() {
   return N1 * Q * W >= 2048 ? 512 : 256;
 }
-template <int N3>
+// threads of a Green-pass block: one per (comp, i3) item, and at most two
+// bins per thread in FP32 (one in FP64) for the operator kept in registers
+template <typename T, int P, int N3>
 constexpr int green3_nt() {
-  int nt = (6 * N3 + 63) / 64 * 64;
+  const int per = sizeof(T) == 8 ? 1 : 2;
+  const int a = 6 * N3, b = (P * N3 + per - 1) / per;
+  int nt = ((a > b ? a : b) + 63) / 64 * 64;
   return nt > 1024 ? 1024 : nt;
 }
 
@@ -398,7 +437,7 @@ void add_cand(const Geo& g, TwoPass<T>* out, int maxn, int* n) {
   if (*n >= maxn || g.n2 % Q != 0 || g.n3 % W != 0) return;
   TwoPass<T> c;
   constexpr int NTS = stress2_nt<N, Q, W>();
-  constexpr int NTG = green3_nt<N>();
+  constexpr int NTG = green3_nt<T, P, N>();
   c.s2 = k_stress2<T, N, Q, W, NTS>;
   c.g3[GREEN_TABLE] = k_green3<T, P, N, NTG, GREEN_TABLE>;
   c.g3[GREEN_MOMENTS] = k_green3<T, P, N, NTG, GREEN_MOMENTS>;
@@ -433,30 +472,17 @@ int candidates_t(const Geo& g, TwoPass<T>* out, int maxn) {
         add_cand<T, 64, 8, 4>(g, out, maxn, &n);
         break;
       case 96:
-        add_cand<T, 96, 4, 8>(g, out, maxn, &n);
-        add_cand<T, 96, 8, 4>(g, out, maxn, &n);
+        add_cand<T, 96, 6, 8>(g, out, maxn, &n);
         add_cand<T, 96, 6, 4>(g, out, maxn, &n);
-        break;
-      case 128:
-        add_cand<T, 128, 8, 4>(g, out, maxn, &n);
+        add_cand<T, 96, 8, 4>(g, out, maxn, &n);
         break;
       default:
         break;
     }
   } else {
-    switch (g.n1) {
-      case 32:
-        add_cand<T, 32, 4, 8>(g, out, maxn, &n);
-        break;
-      case 48:
-        add_cand<T, 48, 4, 8>(g, out, maxn, &n);
-        break;
-      case 64:
-        add_cand<T, 64, 4, 8>(g, out, maxn, &n);
-        break;
-      default:
-        break;
-    }
+    // FP64: the Green operator of two bins per thread does not fit the
+    // registers beyond the smallest grid
+    if (g.n1 == 32) add_cand<T, 32, 4, 8>(g, out, maxn, &n);
   }
   return n;
 }
