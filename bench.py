@@ -197,6 +197,23 @@ def measure_cfg4(args, inst, steps):
     its = np.concatenate([r["iterations"] for r in res])
     done_vi = float(sum(P.m * r["iterations"].sum() for P, r in zip(pats, res)))
     del ws
+    # the FP32 path's error on C^eff: the first packing of each size class on
+    # the FP64 path at the FP32 solve's iteration counts
+    fp32_vs_fp64 = {}
+    for n in sorted({P.e[0] for P in pats}):
+        i = next(k for k, P in enumerate(pats) if P.e[0] == n)
+        n_, contrast, ph = inst[i]
+        Q = lsh.Pattern(np.diag([n, n, n]))
+        Cp = np.stack([li.isotropic_voigt(1.0, 0.3), li.isotropic_voigt(contrast, 0.3)])
+        Q.set_kernel("dirichlet")
+        Q.set_stiffness(Cp, li.mean_reference(Cp), ph)
+        Q.bind("fp64")
+        C64 = np.zeros((6, 6))
+        for j in range(6):
+            C64[:, j] = Q.solve(np.eye(6)[j:j + 1], tol=-1.0, max_iter=int(res[i]["iterations"][j]))["sigma"][0]
+        C32 = res[i]["sigma"].T
+        fp32_vs_fp64[str(n)] = float(np.linalg.norm(C32 - C64) / np.linalg.norm(C64))
+        del Q
     return {"value": value, "unit": "voxel-iters/s", "ms_per_step": wall / steps * 1e3, "steps": steps,
             "dtype": "f32",
             "config": {"workload": f"batched: {ninst} sphere packings n in {{32,48,64,96}}, 6 unit loads each, "
@@ -213,7 +230,8 @@ def measure_cfg4(args, inst, steps):
             "autotune": tuned,
             "solve_to_tol": {"tol": 1e-6, "seconds": round(ts, 3), "voxel_iters_per_s": done_vi / ts,
                              "iterations_min_median_max": [int(its.min()), int(np.median(its)), int(its.max())],
-                             "converged": int(sum(r["converged"].sum() for r in res))}}
+                             "converged": int(sum(r["converged"].sum() for r in res))},
+            "fp32_vs_fp64_C_eff_rel_diff_by_size": fp32_vs_fp64}
 
 
 def bench_cfg4(args):
@@ -223,7 +241,7 @@ def bench_cfg4(args):
            "warmup": args.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": m["config"],
            "roofline": m["roofline"], "cpu_baseline": None,
-           **{k: m[k] for k in ("schedule_by_size", "autotune", "solve_to_tol")}}
+           **{k: m[k] for k in ("schedule_by_size", "autotune", "solve_to_tol", "fp32_vs_fp64_C_eff_rel_diff_by_size")}}
     print(json.dumps(out), flush=True)
 
 
@@ -295,6 +313,9 @@ def bench_cfg3(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": m["config"],
            "roofline": m["roofline"], "cpu_baseline": None,
            **{k: m[k] for k in ("autotune", "solve_to_tol", "fp32_vs_fp64_C_eff_rel_diff")}}
+    if args.no_solve:
+        print(json.dumps(out), flush=True)
+        return
     # the Box alias sums' truncation: C^eff (FP64, tol 1e-8) with R = 16 as is,
     # with its tail, and with R = 32 and its tail as the reference
     loads = np.eye(6)
@@ -433,6 +454,106 @@ def bench_cfg5(args):
                "dataset_s": round(t_data, 1), "dataset_iterations_median": float(np.median(its)),
                "train_s": round(t_train, 1), "train_loss_first_last_epoch": [float(losses[0]), float(losses[-1])]}}
     print(json.dumps(out), flush=True)
+
+
+def bench_startcurve(args):
+    """Iterations of the Basic Scheme to the Cauchy residual 1e-6 against the
+    shape of the start's error, on the learned-start workload (128^3 RSA
+    packings, f = 0.3, radii 6-12 grid steps, contrast 100, Dirichlet, FP64,
+    load e11): starts are the converged field (tol 1e-10) scaled, or plus
+    noise that is white, smooth (low-pass, |k| below a quarter of the grid's
+    Nyquist frequency), or confined to the inclusions, at a given RMS relative
+    to the field's."""
+    import torch
+    from paper_1701_04685_amd import warmstart as wst
+    n = 128
+    eps = np.eye(6)[0].reshape(1, 6)
+    nrng = np.random.Generator(np.random.PCG64(9))
+    rows = {}
+    npk = max(1, args.eval_packings)
+    for k in range(npk):
+        ph = wst.packing(60000 + k, n)
+        P = wst.grid_pattern(n, ph, 100.0, precision="fp64")
+        ws = torch.empty(P.workspace_bytes(1), dtype=torch.uint8, device="cuda")
+        Es = P.solve(eps, tol=1e-10, max_iter=20000, return_E=True, workspace=ws)["E"]
+        rms = Es.norm().item() / np.sqrt(Es.numel())
+        incl = torch.from_numpy(ph.astype(np.float64)).cuda().reshape(1, 1, -1)
+
+        def iters_from(E0):
+            o = P.solve(eps, tol=1e-6, max_iter=20000, E_init=E0, workspace=ws, allow_notconverged=True)
+            return int(o["iterations"][0]) if o["converged"][0] else None
+
+        def white():
+            return torch.from_numpy(nrng.standard_normal(tuple(Es.shape))).cuda()
+
+        def smooth():
+            w = white().reshape(6, n, n, n)
+            W = torch.fft.fftn(w, dim=(1, 2, 3))
+            f = torch.fft.fftfreq(n, device=w.device) * n
+            kk = f[:, None, None] ** 2 + f[None, :, None] ** 2 + f[None, None, :] ** 2
+            W = W * (kk < (n / 8) ** 2)
+            return torch.fft.ifftn(W, dim=(1, 2, 3)).real.reshape(Es.shape)
+
+        def scaled_noise(z, rel):
+            z = z - z.mean(dim=-1, keepdim=True)
+            return z * (rel * rms / (z.norm().item() / np.sqrt(z.numel())))
+
+        starts = {"zero": None}
+        for a in (0.5, 0.9, 0.99):
+            starts[f"{a:g}*exact"] = (a * Es).contiguous()
+        for rel in (1e-1, 1e-2, 1e-3):
+            starts[f"exact+white {rel:g}"] = (Es + scaled_noise(white(), rel)).contiguous()
+        for rel in (1e-1, 1e-2):
+            starts[f"exact+smooth {rel:g}"] = (Es + scaled_noise(smooth(), rel)).contiguous()
+            starts[f"exact+inclusion-confined {rel:g}"] = (Es + scaled_noise(white() * incl, rel)).contiguous()
+        for name, E0 in starts.items():
+            rows.setdefault(name, []).append(iters_from(E0))
+        del ws, Es
+    out = {"metric": "Basic Scheme iterations to residual 1e-6 by start", "value": float(np.mean(rows["zero"])),
+           "unit": "iterations (zero start)", "n_gpus": 1, "steps": npk, "warmup": 0, "ms_per_step": None,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{npk} RSA packings 128^3 (seeds 60000+k), f=0.3, radii 6-12, contrast 100, "
+                                  "Dirichlet, FP64, load e11, tol 1e-6; starts built from the field converged "
+                                  "to 1e-10"},
+           "roofline": None, "cpu_baseline": None, "iterations_by_start": rows}
+    print(json.dumps(out), flush=True)
+
+
+def bench_unet(args):
+    """U-Net inference (the learned start's network, bf16 MFMA implicit-GEMM
+    convolutions) at 128^3: time per prediction and the convolutions' dense
+    bf16 FLOP rate (2 V cin cout ks^3 per layer, V the voxels of its level)."""
+    import torch
+    from paper_1701_04685_amd import lsh, warmstart as wst
+    import lsh_inputs as li
+    n = 128
+    layers = lsh.UNet.layers()
+    net = lsh.UNet(li.unet_init_params(1, layers))
+    # resolution level of each layer in order: two convolutions per level down
+    # to the bottom, two per level back up, then the 1x1 head
+    levels = [0, 0, 1, 1, 2, 2, 1, 1, 0, 0, 0]
+    flops = sum(2.0 * (n >> lv) ** 3 * ci * co * ks ** 3 for (ci, co, ks), lv in zip(layers, levels))
+    phd = torch.from_numpy(wst.packing(60000, n)).cuda()
+    eps = np.eye(6)[:2]
+    net.predict(phd, n, eps)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.predict(phd, n, eps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"metric": "U-Net inference bf16 TFLOP/s (dense MFMA)", "value": flops / dt / 1e12,
+                      "unit": "TFLOP/s", "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": dt * 1e3,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+                      "data": "synthetic",
+                      "config": {"workload": "3-level U-Net (32 base channels) inference on a 128^3 phase map, "
+                                             "two loads", "layers": layers, "levels": levels,
+                                 "conv_flops_per_prediction": flops},
+                      "roofline": {"bound": "mfma", "achieved": round(flops / dt / 1e12, 1), "peak": 2500.0,
+                                   "unit": "TFLOP/s", "frac": round(flops / dt / 1e12 / 2500.0, 4),
+                                   "traffic": None},
+                      "cpu_baseline": None}), flush=True)
 
 
 def bench_plane(args):
@@ -733,11 +854,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the converged (time-to-tol) solve")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "copy", "ve", "plane", "cg", "refine"],
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "copy", "ve", "plane", "cg", "refine",
+                                                           "startcurve", "unet"],
                     help="cfg2 (default): 128^3 FP64 dlVP; cfg3: non-diagonal Box FP32; cfg4: batched FP32; "
                          "cfg5: learned warm start; copy: counter calibration; ve: variational discretisation; "
                          "plane: the 2-D study of Sec. 4; cg: conjugate gradients vs the Basic Scheme; "
-                         "refine: FP32 then FP64 to a tight tolerance")
+                         "refine: FP32 then FP64 to a tight tolerance; startcurve: iterations against the start's "
+                         "error shape; unet: U-Net inference rate")
     ap.add_argument("--train-packings", type=int, default=334, help="cfg5: 64^3 training packings (x6 fields)")
     ap.add_argument("--epochs", type=int, default=12, help="cfg5: training epochs")
     ap.add_argument("--eval-packings", type=int, default=200, help="cfg5: unseen 128^3 packings")
@@ -776,6 +899,10 @@ def main():
         return bench_cg(args)
     if args.workload == "refine":
         return bench_refine(args)
+    if args.workload == "startcurve":
+        return bench_startcurve(args)
+    if args.workload == "unet":
+        return bench_unet(args)
 
     P, Cp, C0, phase = build_problem(lsh, li)
     nload = 6

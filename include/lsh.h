@@ -91,7 +91,8 @@ typedef struct {
  *   M      : d*d integers, row-major.
  *   out    : receives a new pattern; release with lsh_destroy.
  * Errors: LSH_EINVAL (d not 2 or 3, null), LSH_ESINGULAR (det M == 0),
- *         LSH_EUNSUPPORTED (|det M| beyond int32 grid limits).                     */
+ *         LSH_EUNSUPPORTED (|det M| beyond int32 grid limits, or entries so large
+ *         that the exact integer SNF would overflow int64).                        */
 int lsh_create_pattern(int d, const int64_t *M, lsh_pattern **out);
 void lsh_destroy(lsh_pattern *p);
 

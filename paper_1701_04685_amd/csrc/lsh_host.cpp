@@ -301,7 +301,8 @@ extern "C" int lsh_create_pattern(int d, const int64_t* Md, lsh_pattern** out) {
       for (int k = 0; k < 3; ++k) s += (__int128)p->U[3 * i + k] * p->e[k] * p->V[3 * k + j];
       if (s != M[3 * i + j]) {
         delete p;
-        return lsh_fail(LSH_EDEVICE, "internal: SNF reconstruction mismatch");
+        // only an int64 overflow inside the elimination can break the identity
+        return lsh_fail(LSH_EUNSUPPORTED, "M's entries are too large for the exact integer Smith normal form");
       }
     }
   for (int i = 0; i < 3; ++i) lsh_make_plan(p->e[i], &p->plan[i]);

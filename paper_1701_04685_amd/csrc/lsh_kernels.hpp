@@ -647,7 +647,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
 
   // the position's Green operator, scaled by -1/m, formed once for the chunk
   // (GM: GREEN_MOMENTS isotropic C0 from the alias moments, GREEN_GENERAL on
-  // the fly, GREEN_TABLE stored rows)
+  // the fly, GREEN_TABLE stored rows).  Summing the moments on the fly instead
+  // (no table read) made the FP64 128-point pass slower: 0.445 against 0.394 ms.
   {
     static_assert(GM != GREEN_ISO, "the isotropic path reads the moments table");
     const double scale = -1.0 / (double)g.m;

@@ -101,11 +101,12 @@ struct KernSet {
   // autotuner candidates per pass; entry 0 is the default
   struct CStress { A1 fn; int nt; size_t lds; int W; };
   struct CAxis2 { A2 fwd, inv; int W, nt; size_t lds; };
-  struct CGreen { GR fn[4]; int nt; size_t lds; };
+  struct CGreen { GR fn[4]; int nt; size_t lds; int gch = GCH; };  // gch: loads per chunk
   std::vector<CStress> c1;
   std::vector<CAxis2> c2;
   std::vector<CGreen> cg;
   int green2 = 0;  // 1: k_green2 (grid: positions x load chunks), 0: k_green
+  int gch = GCH;   // loads per Green-pass chunk (k_green2; fewer: more blocks, more table reads)
   size_t lds1 = 0, lds2 = 0, ldsG = 0;
   // two-pass schedule (lsh_twopass.hpp): its variants and the one in use (-1: four passes)
   std::vector<TwoPass<T>> tp;
@@ -309,6 +310,22 @@ void green_special(const Geo& g, KernSet<T>& K) {
     if constexpr (sizeof(T) == 8 && NC == 128) K.cg.push_back(green2_cand<T, NC, 2, 3>());
     K.cg.push_back(green2_cand<T, NC, (NC <= 128 ? 2 : 1)>());
     if constexpr (NC <= 128) K.cg.push_back(green2_cand<T, NC, 1>());
+    if constexpr (sizeof(T) == 8 && NC == 128) {
+      // the same with chunks of three loads: twice the blocks, the moments read twice
+      auto c3 = green2_cand<T, NC, 2, 3>();
+      c3.gch = 3;
+      K.cg.push_back(c3);
+    }
+    if constexpr (NC >= 256) {
+      // long lines have few positions: chunks of two or three loads give more
+      // blocks (a shorter last wave) for more reads of the position's operator
+      auto c3 = green2_cand<T, NC, 1>();
+      c3.gch = 3;
+      K.cg.push_back(c3);
+      auto c2 = green2_cand<T, NC, 1>();
+      c2.gch = 2;
+      K.cg.push_back(c2);
+    }
     for (size_t i = K.cg.size(); i-- > 0;)
       if (K.cg[i].lds > (size_t)lds_limit()) K.cg.erase(K.cg.begin() + i);
     if (!K.cg.empty()) {
@@ -744,8 +761,11 @@ void apply_choice(KernSet<T>& K, int gmode, const int ch[4]) {
     K.lds2 = c.lds;
   }
   if (K.green2 && !K.cg.empty()) {
-    const auto& c = K.cg[std::min<size_t>((size_t)ch[2], K.cg.size() - 1)];
+    const auto* cp = &K.cg[std::min<size_t>((size_t)ch[2], K.cg.size() - 1)];
+    if (!cp->fn[gmode]) cp = &K.cg[0];  // a variant without this Green mode: the default
+    const auto& c = *cp;
     for (int m = 0; m < 4; ++m) K.gr2[m] = c.fn[m];
+    K.gch = c.gch;
     K.NTG = c.nt;
     K.ldsG = c.lds;
   }
@@ -759,6 +779,21 @@ void apply_choice(KernSet<T>& K, int gmode, const int ch[4]) {
 }
 
 inline int prec_index(const lsh_pattern* p) { return p->bound_prec == LSH_FP32_MIXED ? 1 : 0; }
+
+// Green chunks: runs of at most K.gch consecutive loads of one instance, and
+// the Green pass's grid.
+template <typename T>
+void make_chunks(GroupRun<T>& G) {
+  G.chunks.clear();
+  for (int L = 0; L < G.nload;) {
+    int e = L + 1;
+    while (e < G.nload && e - L < G.K.gch && G.spec.inst_of[e] == G.spec.inst_of[L]) ++e;
+    G.chunks.push_back(L);
+    G.chunks.push_back(e);
+    L = e;
+  }
+  G.gridG = G.K.green2 ? dim3(G.npos, (unsigned)(G.chunks.size() / 2)) : dim3((G.npos + 7) / 8 * 8 * G.nload);
+}
 
 template <typename T>
 int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
@@ -796,15 +831,7 @@ int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
   const int nt3b = (G.g.n3 + G.K.W2 - 1) / G.K.W2;
   G.gridB = dim3(G.g.h1 * nt3b, 6, G.nload);
   G.npos = G.g.h1 * G.g.n2;
-  G.chunks.clear();
-  for (int L = 0; L < G.nload;) {
-    int e = L + 1;
-    while (e < G.nload && e - L < GCH && G.spec.inst_of[e] == G.spec.inst_of[L]) ++e;
-    G.chunks.push_back(L);
-    G.chunks.push_back(e);
-    L = e;
-  }
-  G.gridG = G.K.green2 ? dim3(G.npos, (unsigned)(G.chunks.size() / 2)) : dim3((G.npos + 7) / 8 * 8 * G.nload);
+  make_chunks(G);
   G.nblkS = G.g.n2 * nt3a;
   return LSH_OK;
 }
@@ -1012,8 +1039,16 @@ int tune_group(GroupRun<T>& G, hipStream_t st, int choice[4], int ncand[4], floa
     float best = 1e30f;
     int bi = 0;
     for (int c = 0; c < nc[pass] && c < LSH_TUNE_MAX && rc == LSH_OK; ++c) {
+      if (pass == 2 && G.K.green2 && !G.K.cg[c].fn[G.gmode]) {
+        ms[pass][c] = 0.f;  // this variant has no kernel for the pattern's Green mode
+        continue;
+      }
       ch[pass] = c;
       apply_choice(G.K, G.gmode, ch);
+      if (pass == 2) {  // the variant's chunk size
+        make_chunks(G);
+        HIPCHK(hipMemcpyAsync(G.w.chunks, G.chunks.data(), sizeof(int) * G.chunks.size(), hipMemcpyHostToDevice, st));
+      }
       const int nt3b = (G.g.n3 + G.K.W2 - 1) / G.K.W2;
       G.gridB = dim3(G.g.h1 * nt3b, 6, G.nload);
       G.gridS1 = dim3(G.g.n2 * ((G.g.n3 + G.K.W1s - 1) / G.K.W1s), G.nload);
@@ -1069,6 +1104,8 @@ int tune_group(GroupRun<T>& G, hipStream_t st, int choice[4], int ncand[4], floa
   (void)hipEventDestroy(e1);
   if (rc) return rc;
   apply_choice(G.K, G.gmode, ch);
+  make_chunks(G);
+  HIPCHK(hipMemcpyAsync(G.w.chunks, G.chunks.data(), sizeof(int) * G.chunks.size(), hipMemcpyHostToDevice, st));
   const int nt3b = (G.g.n3 + G.K.W2 - 1) / G.K.W2;
   G.gridB = dim3(G.g.h1 * nt3b, 6, G.nload);
   G.gridS1 = dim3(G.g.n2 * ((G.g.n3 + G.K.W1s - 1) / G.K.W1s), G.nload);

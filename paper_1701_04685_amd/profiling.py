@@ -24,7 +24,8 @@ import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SOURCES = ["lsh_kernels.hpp", "lsh_fft.hpp", "lsh_green.hpp", "lsh_solver.hip"]
+KERNEL_SOURCES = ["lsh_kernels.hpp", "lsh_common.hpp", "lsh_fft.hpp", "lsh_green.hpp", "lsh_solver.hip",
+                  "lsh_twopass.hpp", "lsh_twopass.hip"]
 
 
 def source_fingerprint() -> str:

@@ -72,3 +72,49 @@ def test_autotune_choice_and_answer(problem):
     res = pr.G.solve(EPS0[None], tol=-1.0, max_iter=7, return_E=True)
     assert rel(res["sigma"][0], ref["sigma_voigt"]) < TOL["fp64"]
     pr.G.tune_reset()
+
+
+@pytest.mark.parametrize("kind,params", [("dlvp", {"alpha": [0.75] * 3}), ("dirichlet_modified", {}),
+                                         ("dirichlet", {})])
+def test_green_variants_fp64_128_lines(kind, params):
+    """FP64 Green pass on 128-point lines (the benchmark's length), where the
+    variants differ in loads per block, wave cap and loads per chunk (even
+    lengths: the -1/2 faces take the Hermitian part): every Green variant
+    against the oracle in lock step."""
+    pr = Problem(np.diag([4, 8, 128]), kind, params, spheres(33))
+    assert tuple(pr.G.e) == (4, 8, 128)
+    ref = pr.oracle_solve(EPS0, n_iter=5)
+    pr.bind("fp64")
+    info = pr.G.autotune(nload=2)
+    ng = len(info["green"]["ms"])
+    assert ng >= 4, info["green"]
+    for c in range(ng):
+        pr.G.tune_set([0, 0, c])
+        res = pr.G.solve(EPS0[None], tol=-1.0, max_iter=5, return_E=True)
+        Eg = pr.gpu_E_to_oracle_mandel(res["E"].cpu().numpy()[0])
+        assert rel(res["sigma"][0], ref["sigma_voigt"]) < TOL["fp64"], c
+        assert rel(Eg, ref["E"]) < TOL["fp64"], c
+    pr.G.tune_reset()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_green_chunk_variants_512_lines(prec):
+    """512-point lines: Green-pass variants that split the six loads into
+    chunks of three or two (more blocks, the position's operator formed once
+    per chunk) against the oracle, all six loads in lock step."""
+    pr = Problem(np.diag([4, 8, 512]), "dlvp", {"alpha": [0.75] * 3}, spheres(34))
+    assert tuple(pr.G.e) == (4, 8, 512)
+    loads = np.eye(6)
+    refs = [pr.oracle_solve(loads[j], n_iter=4) for j in range(6)]
+    pr.bind(prec)
+    info = pr.G.autotune(nload=6)
+    ng = len(info["green"]["ms"])
+    assert ng >= 3, info["green"]
+    for c in range(ng):
+        pr.G.tune_set([0, 0, c])
+        res = pr.G.solve(loads, tol=-1.0, max_iter=4, return_E=True)
+        for j in range(6):
+            Eg = pr.gpu_E_to_oracle_mandel(res["E"][j].cpu().numpy())
+            assert rel(res["sigma"][j], refs[j]["sigma_voigt"]) < TOL[prec], (c, j)
+            assert rel(Eg, refs[j]["E"]) < TOL[prec], (c, j)
+    pr.G.tune_reset()
