@@ -556,6 +556,43 @@ def bench_unet(args):
                       "cpu_baseline": None}), flush=True)
 
 
+def bench_grid(args):
+    """The Basic Scheme on a plain n^3 grid (dlVP alpha = 3/4, 20 % RSA spheres of
+    radii 6-12 grid steps, contrast 10, six unit loads) at either precision:
+    the iteration rate and the per-pass times, e.g. for lengths that take the
+    runtime-plan kernels (lengths outside the compile-time list)."""
+    import torch
+    from paper_1701_04685_amd import lsh
+    import lsh_inputs as li
+    n = args.n
+    P = lsh.Pattern(np.diag([n, n, n]))
+    Cp = np.stack([li.isotropic_voigt(1.0, 0.3), li.isotropic_voigt(10.0, 0.3)])
+    c, r = li.rsa_spheres(5, 1.0 / n, 0.2, max_attempts=200_000)
+    P.set_kernel("dlvp", {"alpha": [0.75] * 3})
+    P.set_stiffness(Cp, li.mean_reference(Cp), li.spheres_phase_grid(n, c, r))
+    P.bind(args.precision)
+    ws = torch.empty(P.workspace_bytes(6), dtype=torch.uint8, device="cuda")
+    loads = np.eye(6)
+    tuned = P.autotune(nload=6, workspace=ws)
+    lsh.profile_enable(True)
+    P.solve(loads, tol=-1.0, max_iter=max(2, args.warmup), workspace=ws)
+    ms, cnt = lsh.profile_read()
+    lsh.profile_enable(False)
+    per = {name: round(ms[i] / cnt[i], 5) for i, name in enumerate(KERNEL_NAMES) if cnt[i] > 0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.solve(loads, tol=-1.0, max_iter=args.steps, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"metric": METRIC, "value": 6 * P.m / dt, "unit": "voxel-iters/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32",
+                      "data": "synthetic",
+                      "config": {"workload": f"{n}^3 grid, dlVP alpha=3/4, RSA spheres f=0.2, contrast 10, 6 unit loads",
+                                 "snf": list(P.e), "precision": args.precision},
+                      "roofline": None, "cpu_baseline": None, "autotune": tuned, "per_kernel_ms": per}), flush=True)
+
+
 def bench_plane(args):
     """The two-dimensional study of Sec. 4 on the GPU: the relative effective
     error e_eff for the Dirichlet kernel, the Box spline with
@@ -855,17 +892,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the converged (time-to-tol) solve")
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "copy", "ve", "plane", "cg", "refine",
-                                                           "startcurve", "unet"],
+                                                           "startcurve", "unet", "grid"],
                     help="cfg2 (default): 128^3 FP64 dlVP; cfg3: non-diagonal Box FP32; cfg4: batched FP32; "
                          "cfg5: learned warm start; copy: counter calibration; ve: variational discretisation; "
                          "plane: the 2-D study of Sec. 4; cg: conjugate gradients vs the Basic Scheme; "
                          "refine: FP32 then FP64 to a tight tolerance; startcurve: iterations against the start's "
-                         "error shape; unet: U-Net inference rate")
+                         "error shape; unet: U-Net inference rate; grid: an n^3 grid at --precision")
     ap.add_argument("--train-packings", type=int, default=334, help="cfg5: 64^3 training packings (x6 fields)")
     ap.add_argument("--epochs", type=int, default=12, help="cfg5: training epochs")
     ap.add_argument("--eval-packings", type=int, default=200, help="cfg5: unseen 128^3 packings")
     ap.add_argument("--ablation-packings", type=int, default=10, help="cfg5: packings also run with the untrained net")
     ap.add_argument("--instances", type=int, default=256, help="cfg4: number of microstructures")
+    ap.add_argument("--n", type=int, default=100, help="grid: the side of the n^3 grid")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"], help="grid: precision")
     ap.add_argument("--no-extra", action="store_true",
                     help="default workload: leave out the batched and non-diagonal Box lines")
     args = ap.parse_args()
@@ -903,6 +942,8 @@ def main():
         return bench_startcurve(args)
     if args.workload == "unet":
         return bench_unet(args)
+    if args.workload == "grid":
+        return bench_grid(args)
 
     P, Cp, C0, phase = build_problem(lsh, li)
     nload = 6

@@ -203,8 +203,10 @@ __device__ __forceinline__ void fft_stage(typename cpx<T>::t* buf, int N, int L,
 }
 
 // Full FFT of L lines.  DIR = -1: forward, exp(-2 pi i ...); +1: inverse
-// (unnormalised).  All threads of the block must call it.
-template <typename T, int DIR, int MAXE>
+// (unnormalised).  All threads of the block must call it.  SMOOTH: the plan's
+// radices are 2, 3, 4, 5 and 8 only (the direct DFTs of 7, 11 and 13 are not
+// built, which keeps the kernel's register count down).
+template <typename T, int DIR, int MAXE, bool SMOOTH = false>
 __device__ void fft_lines(typename cpx<T>::t* buf, const FftPlan& pl, int L, int ls, int es, bool line_fast,
                           const typename cpx<T>::t* __restrict__ tw) {
   int Ns = 1;
@@ -215,11 +217,14 @@ __device__ void fft_lines(typename cpx<T>::t* buf, const FftPlan& pl, int L, int
       case 3: fft_stage<T, DIR, 3, MAXE>(buf, pl.N, L, Ns, ls, es, line_fast, tw); break;
       case 4: fft_stage<T, DIR, 4, MAXE>(buf, pl.N, L, Ns, ls, es, line_fast, tw); break;
       case 5: fft_stage<T, DIR, 5, MAXE>(buf, pl.N, L, Ns, ls, es, line_fast, tw); break;
-      case 7: fft_stage<T, DIR, 7, MAXE>(buf, pl.N, L, Ns, ls, es, line_fast, tw); break;
       case 8: fft_stage<T, DIR, 8, MAXE>(buf, pl.N, L, Ns, ls, es, line_fast, tw); break;
-      case 11: fft_stage<T, DIR, 11, MAXE>(buf, pl.N, L, Ns, ls, es, line_fast, tw); break;
-      case 13: fft_stage<T, DIR, 13, MAXE>(buf, pl.N, L, Ns, ls, es, line_fast, tw); break;
-      default: break;
+      default:
+        if constexpr (!SMOOTH) {
+          if (R == 7) fft_stage<T, DIR, 7, MAXE>(buf, pl.N, L, Ns, ls, es, line_fast, tw);
+          else if (R == 11) fft_stage<T, DIR, 11, MAXE>(buf, pl.N, L, Ns, ls, es, line_fast, tw);
+          else if (R == 13) fft_stage<T, DIR, 13, MAXE>(buf, pl.N, L, Ns, ls, es, line_fast, tw);
+        }
+        break;
     }
     Ns *= R;
   }
@@ -299,14 +304,15 @@ __device__ __forceinline__ void fft_static(typename cpx<T>::t* buf, int ls, int 
   }
 }
 
-// Dispatch: NC > 0 uses the compile-time path, NC == 0 the runtime plan.
+// Dispatch: NC > 0 uses the compile-time path, NC == 0 the runtime plan,
+// NC == -1 the runtime plan of a length whose radices are 2, 3, 4, 5, 8.
 template <typename T, int DIR, int NC, int L, bool LF, int NT>
 __device__ __forceinline__ void fft_any(typename cpx<T>::t* buf, const FftPlan& pl, int ls, int es,
                                         const typename cpx<T>::t* __restrict__ tw) {
   if constexpr (NC > 0) {
     fft_static<T, DIR, NC, L, LF, NT>(buf, ls, es, tw);
   } else {
-    fft_lines<T, DIR, 16>(buf, pl, L, ls, es, LF, tw);
+    fft_lines<T, DIR, 16, NC < 0>(buf, pl, L, ls, es, LF, tw);
   }
 }
 

@@ -67,6 +67,16 @@ bool plan_fits(const FftPlan& pl, int L, int nthr) {
   return true;
 }
 
+// A plan whose radices are all 2, 3, 4, 5 or 8: its runtime-plan kernels are
+// built without the direct DFTs of the larger primes (NC = -1).
+bool plan_smooth(const FftPlan& pl) {
+  for (int s = 0; s < pl.nst; ++s) {
+    const int r = pl.rad[s];
+    if (r != 2 && r != 3 && r != 4 && r != 5 && r != 8) return false;
+  }
+  return true;
+}
+
 int lds_limit() {
   static int lim = -1;
   if (lim < 0) {
@@ -206,14 +216,19 @@ bool choose_axis1(const Geo& g, const FftPlan& pl, KernSet<T>& K) {
   }
   if (!ok) {
     // runtime plan: widest tile (16, 4 or 1 columns) that fits
-    if (g.n3 >= 16 && plan_fits(pl, 48, 256) && (size_t)g.n1 * 48 * sizeof(C2<T>) <= 60 * 1024)
-      put_axis1<T, 0, 16>(K);
-    else if (g.n3 >= 4 && plan_fits(pl, 12, 256) && (size_t)g.n1 * 12 * sizeof(C2<T>) <= 60 * 1024)
-      put_axis1<T, 0, 4>(K);
-    else if (plan_fits(pl, 3, 256))
-      put_axis1<T, 0, 1>(K);
-    else
+    const bool sm = plan_smooth(pl);
+    if (g.n3 >= 16 && plan_fits(pl, 48, 256) && (size_t)g.n1 * 48 * sizeof(C2<T>) <= 60 * 1024) {
+      if (sm) put_axis1<T, -1, 16>(K);
+      else put_axis1<T, 0, 16>(K);
+    } else if (g.n3 >= 4 && plan_fits(pl, 12, 256) && (size_t)g.n1 * 12 * sizeof(C2<T>) <= 60 * 1024) {
+      if (sm) put_axis1<T, -1, 4>(K);
+      else put_axis1<T, 0, 4>(K);
+    } else if (plan_fits(pl, 3, 256)) {
+      if (sm) put_axis1<T, -1, 1>(K);
+      else put_axis1<T, 0, 1>(K);
+    } else {
       return false;
+    }
   }
   K.lds1 = sizeof(C2<T>) * ((size_t)g.n1 + (size_t)g.n1 * 3 * K.W1) + sizeof(T) * 36 * 16;
   if (K.c1.empty()) K.c1.push_back({K.a1[0], K.NT1, K.lds1, K.W1});
@@ -261,14 +276,19 @@ bool choose_axis2(const Geo& g, const FftPlan& pl, KernSet<T>& K) {
     default: break;
   }
   if (!ok) {
-    if (g.n3 >= 16 && plan_fits(pl, 16, 256) && (size_t)g.n2 * 16 * sizeof(C2<T>) <= 60 * 1024)
-      put_axis2<T, 0, 16>(K);
-    else if (g.n3 >= 4 && plan_fits(pl, 4, 256) && (size_t)g.n2 * 4 * sizeof(C2<T>) <= 60 * 1024)
-      put_axis2<T, 0, 4>(K);
-    else if (plan_fits(pl, 1, 256))
-      put_axis2<T, 0, 1>(K);
-    else
+    const bool sm = plan_smooth(pl);
+    if (g.n3 >= 16 && plan_fits(pl, 16, 256) && (size_t)g.n2 * 16 * sizeof(C2<T>) <= 60 * 1024) {
+      if (sm) put_axis2<T, -1, 16>(K);
+      else put_axis2<T, 0, 16>(K);
+    } else if (g.n3 >= 4 && plan_fits(pl, 4, 256) && (size_t)g.n2 * 4 * sizeof(C2<T>) <= 60 * 1024) {
+      if (sm) put_axis2<T, -1, 4>(K);
+      else put_axis2<T, 0, 4>(K);
+    } else if (plan_fits(pl, 1, 256)) {
+      if (sm) put_axis2<T, -1, 1>(K);
+      else put_axis2<T, 0, 1>(K);
+    } else {
       return false;
+    }
   }
   K.lds2 = sizeof(C2<T>) * ((size_t)g.n2 + (size_t)g.n2 * K.W2);
   K.c2.insert(K.c2.begin(), {K.a2[0], K.a2[1], K.W2, K.NT2, K.lds2});
@@ -352,6 +372,17 @@ void green_special(const Geo& g, KernSet<T>& K) {
   (void)g;
 }
 
+// Runtime-plan Green pass of a smooth length: one build per Green mode (the
+// branches of the other modes and the direct DFTs would otherwise set the
+// register count).
+template <typename T, int NT>
+void put_green_rt(KernSet<T>& K) {
+  K.gr2[GREEN_GENERAL] = k_green<T, -1, NT, GREEN_GENERAL>;
+  K.gr2[GREEN_TABLE] = k_green<T, -1, NT, GREEN_TABLE>;
+  K.gr2[GREEN_MOMENTS] = k_green<T, -1, NT, GREEN_MOMENTS>;
+  K.gr = K.gr2[GREEN_MOMENTS];
+}
+
 template <typename T>
 bool choose_green(const Geo& g, const FftPlan& pl, bool table, KernSet<T>& K) {
   bool ok = false;
@@ -368,11 +399,19 @@ bool choose_green(const Geo& g, const FftPlan& pl, bool table, KernSet<T>& K) {
     // long lines (e.g. 1024, 2048) need more threads for their butterflies
     while (nt < 1024 && !plan_fits(pl, 6, nt)) nt *= 2;
     if (!plan_fits(pl, 6, nt)) return false;
-    if (nt == 64) K.gr = k_green<T, 0, 64>;
-    else if (nt == 128) K.gr = k_green<T, 0, 128>;
-    else if (nt == 256) K.gr = k_green<T, 0, 256>;
-    else if (nt == 512) K.gr = k_green<T, 0, 512>;
-    else K.gr = k_green<T, 0, 1024>;
+    if (plan_smooth(pl)) {
+      if (nt == 64) put_green_rt<T, 64>(K);
+      else if (nt == 128) put_green_rt<T, 128>(K);
+      else if (nt == 256) put_green_rt<T, 256>(K);
+      else if (nt == 512) put_green_rt<T, 512>(K);
+      else put_green_rt<T, 1024>(K);
+    } else {
+      if (nt == 64) K.gr = k_green<T, 0, 64>;
+      else if (nt == 128) K.gr = k_green<T, 0, 128>;
+      else if (nt == 256) K.gr = k_green<T, 0, 256>;
+      else if (nt == 512) K.gr = k_green<T, 0, 512>;
+      else K.gr = k_green<T, 0, 1024>;
+    }
     K.NTG = nt;
   }
   (void)table;
