@@ -1248,17 +1248,56 @@ int run_groups(std::vector<GroupRun<T>>& groups, double tol, int max_iter, hipSt
   bool use_graph = graphs && !g_prof.on && st != nullptr;
   hipGraphExec_t gexec = nullptr;
   if (use_graph) {
-    hipGraph_t graph = nullptr;
-    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    // Each group's two iterations form a branch of its own (forked from and
+    // joined to `st` through events on side streams), so the groups of a batch
+    // are independent in the graph and the GPU may run one group's kernels
+    // beside another's instead of strictly after them.
+    const size_t ng = groups.size();
+    std::vector<hipStream_t> side(ng > 1 ? ng : 0, nullptr);
+    std::vector<hipEvent_t> join(side.size(), nullptr);
+    hipEvent_t fork = nullptr;
+    auto release = [&]() {
+      for (auto& x : side)
+        if (x) (void)hipStreamDestroy(x);
+      for (auto& x : join)
+        if (x) (void)hipEventDestroy(x);
+      if (fork) (void)hipEventDestroy(fork);
+    };
     int rc = LSH_OK;
-    for (int par = 0; par < 2 && rc == LSH_OK; ++par)
-      for (auto& G : groups) {
-        rc = group_iterate<T>(G, par, tol, fixed, st);
-        if (rc) break;
+    if (ng > 1) {
+      hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+      for (size_t i = 0; i < ng && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
       }
-    hipError_t e = hipStreamEndCapture(st, &graph);
+      if (e != hipSuccess) {
+        release();
+        return lsh_fail(LSH_EDEVICE, std::string("graph branches: ") + hipGetErrorString(e));
+      }
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      release();
+      return lsh_fail(LSH_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    if (ng > 1) {
+      e = hipEventRecord(fork, st);
+      for (size_t i = 0; i < ng && e == hipSuccess && rc == LSH_OK; ++i) {
+        e = hipStreamWaitEvent(side[i], fork, 0);
+        for (int par = 0; par < 2 && e == hipSuccess && rc == LSH_OK; ++par)
+          rc = group_iterate<T>(groups[i], par, tol, fixed, side[i]);
+        if (e == hipSuccess && rc == LSH_OK) e = hipEventRecord(join[i], side[i]);
+        if (e == hipSuccess && rc == LSH_OK) e = hipStreamWaitEvent(st, join[i], 0);
+      }
+    } else {
+      for (int par = 0; par < 2 && rc == LSH_OK; ++par) rc = group_iterate<T>(groups[0], par, tol, fixed, st);
+    }
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    release();
     if (rc) return rc;
-    if (e != hipSuccess) return lsh_fail(LSH_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    if (e != hipSuccess || ec != hipSuccess)
+      return lsh_fail(LSH_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : ec));
     e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return lsh_fail(LSH_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
