@@ -15,8 +15,14 @@ namespace {
 // One block: load L, coset r of axis 2 (i2 = r + P j, j < Q) and W consecutive
 // i3.  LDS: axis-1 twiddles [N1], w_Q^k [Q], w_n2^{r q} [Q], the tile
 // Z[k < N1][(pair, j, w)] (component pairs (0,1), (2,3), (4,5) share one complex
-// axis-1 line), then (C_p - C0) of the first NDL phases.  Blocks take r
-// fastest: neighbouring blocks' runs lie P n3 elements apart.
+// axis-1 line), then (C_p - C0) of the first NDL phases.
+//
+// Tile order: the chip hands blocks to its eight XCDs in turn, so block b of
+// a load runs on XCD b mod 8 (the grid's width is a multiple of 8 for every
+// variant built).  Each XCD's share of the tiles is one range of the (r, i3)
+// tiles with i3 fastest: the blocks one XCD runs side by side read and write
+// neighbouring W-element runs of one coset, which share 128-byte lines in that
+// XCD's L2 (a run is 32 or 64 bytes), as do the phase bytes they read.
 template <typename T, int N1, int Q, int W, int NT, int NDL = 16>
 __global__ void __launch_bounds__(NT) k_stress2(Geo g, const C2<T>* __restrict__ tw0, const C2<T>* __restrict__ tw1,
                                                 const C2<T>* __restrict__ X, C2<T>* __restrict__ Y,
@@ -39,8 +45,15 @@ __global__ void __launch_bounds__(NT) k_stress2(Geo g, const C2<T>* __restrict__
   const int L = blockIdx.y;
   if (*itp >= stop_iter[L]) return;
   const int P = g.n2 / Q;
-  const int r = blockIdx.x % P;
-  const int a30 = (blockIdx.x / P) * W;
+  const int nw = g.n3 / W;
+  int r, a30;
+  {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int x = b & 7, base = nb >> 3, extra = nb & 7;
+    const int t = x * base + (x < extra ? x : extra) + (b >> 3);
+    r = t / nw;
+    a30 = (t - r * nw) * W;
+  }
   const Inst& in = insts[inst_of[L]];
   const uint8_t* __restrict__ phase = in.phase;
   const T* __restrict__ dmat = reinterpret_cast<const T*>(in.dmat);
@@ -349,7 +362,8 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
 }
 
 // ------------------------------------------------------ state conversions ---
-// One thread per (load, comp, k1, r, i3); Q <= 8 values each.
+// One thread per (load, comp, k1, r, i3); Q <= QMAX values each.
+constexpr int QMAX = 16;
 template <typename T>
 __global__ void __launch_bounds__(256) k_to_split(Geo g, int Q, const C2<T>* __restrict__ tw1,
                                                   const C2<T>* __restrict__ X, C2<T>* __restrict__ Xs, int nload) {
@@ -365,7 +379,7 @@ __global__ void __launch_bounds__(256) k_to_split(Geo g, int Q, const C2<T>* __r
     const int k1 = (int)(rem / ((long long)g.n3 * P));
     const T2* src = X + lc * g.spec + (long long)k1 * g.n2 * g.n3 + i3;
     T2* dst = Xs + lc * g.spec + (long long)k1 * Q * P * g.n3 + (long long)r * g.n3 + i3;
-    T2 x[8];
+    T2 x[QMAX];
     for (int j = 0; j < Q; ++j) x[j] = src[(long long)(r + P * j) * g.n3];
     const T inv = (T)(1.0 / Q);
     for (int q = 0; q < Q; ++q) {
@@ -397,7 +411,7 @@ __global__ void __launch_bounds__(256) k_from_split(Geo g, int Q, const C2<T>* _
     const int k1 = (int)(rem / ((long long)g.n3 * P));
     const T2* src = Xs + lc * g.spec + (long long)k1 * Q * P * g.n3 + (long long)r * g.n3 + i3;
     T2* dst = X + lc * g.spec + (long long)k1 * g.n2 * g.n3 + i3;
-    T2 x[8];
+    T2 x[QMAX];
     for (int q = 0; q < Q; ++q) {
       T2 w = tw1[r * q];
       w.y = -w.y;
@@ -430,51 +444,59 @@ constexpr int green3_nt() {
   return nt > 1024 ? 1024 : nt;
 }
 
-template <typename T, int N, int Q, int W>
+// a variant for the SNF grid (N1, N2, N3) with N2 = Q P and stress tiles W wide
+template <typename T, int N1, int N2, int N3, int Q, int W>
 void add_cand(const Geo& g, TwoPass<T>* out, int maxn, int* n) {
-  constexpr int P = N / Q;
-  static_assert(P * Q == N, "Q divides the axis-2 length");
-  if (*n >= maxn || g.n2 % Q != 0 || g.n3 % W != 0) return;
+  constexpr int P = N2 / Q;
+  static_assert(P * Q == N2, "Q divides the axis-2 length");
+  static_assert(Q <= QMAX, "the state conversions hold Q values per thread");
+  static_assert(N3 % W == 0, "W divides the axis-3 length");
+  if (*n >= maxn || g.n1 != N1 || g.n2 != N2 || g.n3 != N3) return;
   TwoPass<T> c;
-  constexpr int NTS = stress2_nt<N, Q, W>();
-  constexpr int NTG = green3_nt<T, P, N>();
-  c.s2 = k_stress2<T, N, Q, W, NTS>;
-  c.g3[GREEN_TABLE] = k_green3<T, P, N, NTG, GREEN_TABLE>;
-  c.g3[GREEN_MOMENTS] = k_green3<T, P, N, NTG, GREEN_MOMENTS>;
+  constexpr int NTS = stress2_nt<N1, Q, W>();
+  constexpr int NTG = green3_nt<T, P, N3>();
+  c.s2 = k_stress2<T, N1, Q, W, NTS>;
+  c.g3[GREEN_TABLE] = k_green3<T, P, N3, NTG, GREEN_TABLE>;
+  c.g3[GREEN_MOMENTS] = k_green3<T, P, N3, NTG, GREEN_MOMENTS>;
   c.Q = Q;
   c.P = P;
   c.W = W;
   c.nts = NTS;
   c.ntg = NTG;
-  c.ldss = sizeof(C2<T>) * ((size_t)N + 2 * Q + (size_t)N * 3 * Q * W) + sizeof(T) * 36 * 16;
-  c.ldsg = sizeof(C2<T>) * ((size_t)N + P + (size_t)6 * P * (N + 1));
+  c.ldss = sizeof(C2<T>) * ((size_t)N1 + 2 * Q + (size_t)N1 * 3 * Q * W) + sizeof(T) * 36 * 16;
+  c.ldsg = sizeof(C2<T>) * ((size_t)N3 + P + (size_t)6 * P * (N3 + 1));
   out[(*n)++] = c;
+}
+
+template <typename T, int N, int Q, int W>
+void add_cubic(const Geo& g, TwoPass<T>* out, int maxn, int* n) {
+  add_cand<T, N, N, N, Q, W>(g, out, maxn, n);
 }
 
 template <typename T>
 int candidates_t(const Geo& g, TwoPass<T>* out, int maxn) {
   int n = 0;
-  // cubic SNF grids of the batched size classes and the 128^3 workloads;
-  // the first candidate of each is the default
+  // cubic SNF grids of the batched size classes; the first candidate of each
+  // is the default
   if (g.n1 != g.n2 || g.n2 != g.n3) return 0;
   if constexpr (sizeof(T) == 4) {
     switch (g.n1) {
       case 32:
-        add_cand<T, 32, 4, 8>(g, out, maxn, &n);
-        add_cand<T, 32, 2, 16>(g, out, maxn, &n);
+        add_cubic<T, 32, 4, 8>(g, out, maxn, &n);
+        add_cubic<T, 32, 2, 16>(g, out, maxn, &n);
         break;
       case 48:
-        add_cand<T, 48, 4, 8>(g, out, maxn, &n);
-        add_cand<T, 48, 3, 8>(g, out, maxn, &n);
+        add_cubic<T, 48, 4, 8>(g, out, maxn, &n);
+        add_cubic<T, 48, 3, 8>(g, out, maxn, &n);
         break;
       case 64:
-        add_cand<T, 64, 4, 8>(g, out, maxn, &n);
-        add_cand<T, 64, 8, 4>(g, out, maxn, &n);
+        add_cubic<T, 64, 4, 8>(g, out, maxn, &n);
+        add_cubic<T, 64, 8, 4>(g, out, maxn, &n);
         break;
       case 96:
-        add_cand<T, 96, 6, 8>(g, out, maxn, &n);
-        add_cand<T, 96, 6, 4>(g, out, maxn, &n);
-        add_cand<T, 96, 8, 4>(g, out, maxn, &n);
+        add_cubic<T, 96, 6, 8>(g, out, maxn, &n);
+        add_cubic<T, 96, 6, 4>(g, out, maxn, &n);
+        add_cubic<T, 96, 8, 4>(g, out, maxn, &n);
         break;
       default:
         break;
@@ -482,7 +504,7 @@ int candidates_t(const Geo& g, TwoPass<T>* out, int maxn) {
   } else {
     // FP64: the Green operator of two bins per thread does not fit the
     // registers beyond the smallest grid
-    if (g.n1 == 32) add_cand<T, 32, 4, 8>(g, out, maxn, &n);
+    if (g.n1 == 32) add_cubic<T, 32, 4, 8>(g, out, maxn, &n);
   }
   return n;
 }
