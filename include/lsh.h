@@ -161,9 +161,20 @@ int lsh_set_stiffness(lsh_pattern *p, int nphase, const double *C_voigt,
  *     ||z|| / ||E + z + eps0|| with z = -Gamma^p C (E + eps0).  Same solution
  *     as LSH_SCHEME_LS; lsh_solve only (lsh_solve_batch refuses it).
  *     lsh_solve returns LSH_EUNSUPPORTED for other kernels or even m.
+ *   LSH_SCHEME_LS_INC: the iterates of LSH_SCHEME_LS, computed from their
+ *     increments.  The scheme is affine in E, so past the first iteration
+ *       dE_{k+1} = -Gamma^p[(C - C0):dE_k],   E_{k+1} = E_k + dE_{k+1},
+ *     with dE_{k+1} = E_{k+1} - E_k (eps0 drops out); the first iteration is
+ *     the LS step.  In exact arithmetic the iterates, the residual history and
+ *     the answer are LSH_SCHEME_LS's.  In rounded arithmetic the transforms
+ *     act on the increment, so their rounding error scales with the increment
+ *     rather than with the field, and the Cauchy residual ||dE|| / ||E|| keeps
+ *     falling where the LS form levels off (about 1e-6 at contrast 100 in
+ *     LSH_FP32_MIXED).  Same memory and passes as LS (the Green pass also
+ *     writes the increment, one more field write per iteration).
  * LS and VE coincide for the Dirichlet kernel (Remark (constants)).  Changing
  * the scheme drops the device binding (call lsh_bind again).  Errors: LSH_EINVAL. */
-typedef enum { LSH_SCHEME_LS = 0, LSH_SCHEME_VE = 1, LSH_SCHEME_CG = 2 } lsh_scheme;
+typedef enum { LSH_SCHEME_LS = 0, LSH_SCHEME_VE = 1, LSH_SCHEME_CG = 2, LSH_SCHEME_LS_INC = 3 } lsh_scheme;
 int lsh_set_scheme(lsh_pattern *p, lsh_scheme scheme);
 
 /* ------------------------------------------------------------- device binding ---

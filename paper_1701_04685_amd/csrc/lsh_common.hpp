@@ -85,6 +85,37 @@ __device__ __forceinline__ void stress6(const T* D, const T E[6], T t[6]) {
   }
 }
 
+// How a Green pass turns its result v (its input transformed with
+// -Gamma^p / m) into the new state, given the previous state ov:
+//   UPD_LS   new = v (the input is the polarisation of the current iterate);
+//   UPD_VE   new = ov + v (the variational scheme: v is the correction);
+//   UPD_INC  iteration 0 as UPD_LS, with the increment v - ov written to dP;
+//            later iterations take the polarisation's increment as input, so
+//            new = ov + v and the increment is v itself.
+// *d2 = |new - ov|^2 in double; for UPD_INC past iteration 0 it is |v|^2,
+// taken from v rather than from the rounded difference of the states.
+enum { UPD_LS = 0, UPD_VE = 1, UPD_INC = 2 };
+
+template <typename T>
+__device__ __forceinline__ C2<T> green_update(C2<T> v, C2<T> ov, int upd, int it, C2<T>* __restrict__ dP,
+                                              long long gi, double* d2) {
+  C2<T> nv;
+  double dx, dy;
+  if (upd == UPD_INC && it > 0) {
+    nv = cadd(v, ov);
+    dP[gi] = v;
+    dx = (double)v.x;
+    dy = (double)v.y;
+  } else {
+    nv = upd == UPD_VE ? cadd(v, ov) : v;
+    if (upd == UPD_INC) dP[gi] = csub(v, ov);
+    dx = (double)nv.x - (double)ov.x;
+    dy = (double)nv.y - (double)ov.y;
+  }
+  *d2 = dx * dx + dy * dy;
+  return nv;
+}
+
 // Green operator forms (see k_green in lsh_kernels.hpp).
 enum { GREEN_ISO = 0, GREEN_GENERAL = 1, GREEN_TABLE = 2, GREEN_MOMENTS = 3 };
 

@@ -416,7 +416,7 @@ extern "C" int lsh_set_kernel(lsh_pattern* p, lsh_kernel kind, const double* par
 
 extern "C" int lsh_set_scheme(lsh_pattern* p, lsh_scheme scheme) {
   if (!p) return lsh_fail(LSH_EINVAL, "null pattern");
-  if (scheme != LSH_SCHEME_LS && scheme != LSH_SCHEME_VE && scheme != LSH_SCHEME_CG)
+  if (scheme != LSH_SCHEME_LS && scheme != LSH_SCHEME_VE && scheme != LSH_SCHEME_CG && scheme != LSH_SCHEME_LS_INC)
     return lsh_fail(LSH_EINVAL, "unknown scheme");
   if (p->scheme != (int)scheme) {
     p->scheme = (int)scheme;

@@ -324,6 +324,7 @@ __global__ void __launch_bounds__(NT) k_axis2(Geo g, FftPlan pl, const C2<T>* __
 // GM >= 0 fixes the Green mode at compile time (only that branch is built,
 // which keeps the register count of the table and moment paths low); -1
 // switches on the gmode argument.
+// upd (every Green pass): UPD_LS, UPD_VE or UPD_INC (lsh_common.hpp).
 template <typename T, int NC, int NT, int GM = -1>
 __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __restrict__ tw, GreenParams gp,
                                               const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
@@ -332,7 +333,7 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
                                               const int* __restrict__ chunks_unused,
                                               const int* __restrict__ stop_iter, const int* __restrict__ itp,
                                               int nload, int npos, double* __restrict__ partial, int ls, int gmode,
-                                              int ve) {
+                                              int upd, C2<T>* __restrict__ dP) {
   using T2 = C2<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n3 = NC > 0 ? NC : g.n3;
@@ -424,14 +425,14 @@ __global__ void __launch_bounds__(NT) k_green(Geo g, FftPlan pl, const C2<T>* __
   __syncthreads();
   fft_any<T, +1, NC, 6, false, NT>(lines, pl, ls, 1, twl);
   double acc[2] = {0.0, 0.0};
+  const int it = *itp;
   auto finish = [&](int idx, T2 ov) {
     const int c = idx / n3, k3 = idx - c * n3;
     const long long gi = ((long long)(L * 6 + c)) * g.spec + row + k3;
-    // variational scheme: the pass computes the correction, added to P_old
-    const T2 nv = ve ? cadd(lines[c * ls + k3], ov) : lines[c * ls + k3];
+    double dd;
+    const T2 nv = green_update<T>(lines[c * ls + k3], ov, upd, it, dP, gi, &dd);
     Pnew[gi] = nv;
-    const double dx = (double)nv.x - (double)ov.x, dy = (double)nv.y - (double)ov.y;
-    acc[0] += wk1 * (dx * dx + dy * dy);
+    acc[0] += wk1 * dd;
     acc[1] += wk1 * ((double)nv.x * (double)nv.x + (double)nv.y * (double)nv.y);
   };
   if constexpr (NC > 0) {
@@ -584,7 +585,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
                                                const Inst* __restrict__ insts, const int* __restrict__ inst_of,
                                                const int* __restrict__ chunks, const int* __restrict__ stop_iter,
                                                const int* __restrict__ itp, int nload, int npos,
-                                               double* __restrict__ partial, int ls_unused, int gmode, int ve) {
+                                               double* __restrict__ partial, int ls_unused, int gmode, int upd,
+                                               C2<T>* __restrict__ dP) {
   using T2 = C2<T>;
   static_assert(NL == 1 || NL == 2, "one or two loads at a time");
   (void)pl;
@@ -789,15 +791,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
         const int l = u / nbl, j = u % nbl;
         const int sl = l / 6, c = l % 6;
         if ((nu % NT == 0 || u < nu) && (sl == 0 ? act0 : act1)) {
-          T2* dstp = Pnew + ((long long)((L0 + sl) * 6 + c)) * g.spec + row + j;
+          const long long g0 = ((long long)((L0 + sl) * 6 + c)) * g.spec + row + j;
           double dd = 0.0, nn = 0.0;
 #pragma unroll
           for (int r = 0; r < R; ++r) {
-            // variational scheme: the pass computes the correction, added to P_old
-            const T2 ov = po[q][r], nv = ve ? cadd(v[q][r], ov) : v[q][r];
-            dstp[r * nbl] = nv;
-            const double dx = (double)nv.x - (double)ov.x, dy = (double)nv.y - (double)ov.y;
-            dd += dx * dx + dy * dy;
+            double d2;
+            const T2 nv = green_update<T>(v[q][r], po[q][r], upd, it, dP, g0 + r * nbl, &d2);
+            Pnew[g0 + r * nbl] = nv;
+            dd += d2;
             nn += (double)nv.x * (double)nv.x + (double)nv.y * (double)nv.y;
           }
           if (sl == 0) {
@@ -1055,6 +1056,35 @@ __global__ void __launch_bounds__(1024) k_finalize_resid(const double* __restric
 // runtime memset node)
 __global__ void __launch_bounds__(256) k_zero(unsigned long long* __restrict__ p, long long n) {
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) p[i] = 0ull;
+}
+
+// The increment scheme's start: eps0 added to the state's mean bins.  The
+// mean of a field sits in the first `count` elements of each (load,
+// component) block of `spec` elements (the k1 = 0 plane of the four-pass
+// state, the k1 = 0, q = 0 rows of the two-pass state), where the transforms'
+// normalisation gives a constant field c the value c.
+template <typename T>
+__global__ void __launch_bounds__(256) k_add_mean(C2<T>* __restrict__ X, long long spec, long long count,
+                                                  const double* __restrict__ eps0, int nload) {
+  const long long n = count * 6 * nload;
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
+    const long long lc = t / count;
+    X[lc * spec + t % count].x += (T)eps0[lc];
+  }
+}
+
+// dst <- the state each load's last iteration wrote: P1 if min(stop_iter[L],
+// it) is odd, else P0 (one (load, component) block of spec elements at a time).
+template <typename T>
+__global__ void __launch_bounds__(256) k_pick_parity(const C2<T>* __restrict__ P0, const C2<T>* __restrict__ P1,
+                                                     C2<T>* __restrict__ dst, long long spec, int nload,
+                                                     const int* __restrict__ stop_iter, const int* __restrict__ itp) {
+  const long long n = spec * 6 * nload;
+  const int it = *itp;
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
+    const int L = (int)(t / (spec * 6));
+    dst[t] = (min(stop_iter[L], it) & 1) ? P1[t] : P0[t];
+  }
 }
 
 // end of an iteration: advance the device-side iteration counter

@@ -96,7 +96,8 @@ struct KernSet {
                       const int*, const int*, const double* const*, const double*, double* const*, double*);
   using A2 = void (*)(Geo, FftPlan, const C2<T>*, const C2<T>*, C2<T>*, const int*, const int*, T);
   using GR = void (*)(Geo, FftPlan, const C2<T>*, GreenParams, const C2<T>*, const C2<T>*, C2<T>*, const T*,
-                      const Inst*, const int*, const int*, const int*, const int*, int, int, double*, int, int, int);
+                      const Inst*, const int*, const int*, const int*, const int*, int, int, double*, int, int, int,
+                      C2<T>*);
   A1 a1[3] = {nullptr, nullptr, nullptr};  // MODE_STRESS, MODE_FINAL, MODE_INIT
   A2 a2[2] = {nullptr, nullptr};           // forward, inverse
   GR gr = nullptr;
@@ -563,8 +564,10 @@ int bind_t(lsh_pattern* p, void* dev, size_t bytes, hipStream_t st) {
     double Cm[36];
     lsh_voigt_to_mandel(p->C_voigt.data() + 36 * q, Cm);
     for (int i = 0; i < 36; ++i) {
-      // stress-pass matrix: C_p - C0 (Lippmann-Schwinger), C_p (variational)
-      dm[36 * q + i] = (T)(p->scheme != LSH_SCHEME_LS ? Cm[i] : Cm[i] - C0m[i]);
+      // stress-pass matrix: C_p - C0 (Lippmann-Schwinger, either form), C_p
+      // (variational, conjugate gradients)
+      const bool ls = p->scheme == LSH_SCHEME_LS || p->scheme == LSH_SCHEME_LS_INC;
+      dm[36 * q + i] = (T)(ls ? Cm[i] - C0m[i] : Cm[i]);
       cm[36 * q + i] = Cm[i];
     }
   }
@@ -625,6 +628,7 @@ struct GroupWS {
   double* C0m;     // conjugate gradients: C0 (Mandel)
   double* partial;
   double* eps0;
+  double* eps0z;   // zeros: the stress pass's eps0 in the increment scheme
   double* e0sq;
   double* hist;
   double* sigma;
@@ -663,6 +667,7 @@ GroupWS group_layout(const Geo& g, int nload, int ninst, const KernSet<T>& K, ch
   const long long npart = std::max(std::max(nblkS * 6, nblkG * 2), cg ? nblkU * 3 : 0LL) * nload;
   w.partial = (double*)(base + off); off += lsh_align(sizeof(double) * npart);
   w.eps0 = (double*)(base + off); off += lsh_align(sizeof(double) * 6 * nload);
+  w.eps0z = (double*)(base + off); off += lsh_align(sizeof(double) * 6 * nload);
   w.e0sq = (double*)(base + off); off += lsh_align(sizeof(double) * nload);
   w.hist = (double*)(base + off); off += lsh_align(sizeof(double) * LSH_HIST * nload);
   w.sigma = (double*)(base + off); off += lsh_align(sizeof(double) * 6 * nload);
@@ -939,21 +944,46 @@ int group_init(GroupRun<T>& G, int max_iter, hipStream_t st) {
     if (!rc) rc = zero_async(G.w.P[0], fb, st);
     if (rc) return rc;
   }
+  if (p->scheme == LSH_SCHEME_LS_INC) {
+    // the increment scheme's X at iteration 0: the start state (in the layout
+    // its stress pass reads) with eps0 in the mean bins; its stress pass then
+    // takes eps0 = 0 throughout
+    int rc = zero_async(G.w.eps0z, sizeof(double) * 6 * nload, st);
+    if (rc) return rc;
+    long long count = (long long)G.g.n2 * G.g.n3;  // the k1 = 0 plane
+    if (G.K.tpi >= 0) {
+      HIPCHK(hipMemcpyAsync(G.w.X, G.w.P[0], fb, hipMemcpyDeviceToDevice, st));
+      count = (long long)(G.g.n2 / G.K.tp[G.K.tpi].Q) * G.g.n3;  // its q = 0 rows
+    }
+    const long long n = count * 6 * nload;
+    hipLaunchKernelGGL(k_add_mean<T>, dim3((unsigned)std::min<long long>((n + 255) / 256, 8192)), dim3(256), 0, st,
+                       (T2*)G.w.X, (long long)G.g.spec, count, (const double*)G.w.eps0, nload);
+    HIPCHK(hipGetLastError());
+  }
   G.ring.assign(LSH_HIST * nload, NAN);
   return LSH_OK;
 }
 
+// The Green pass's update rule for the pattern's scheme (UPD_*, lsh_common.hpp).
+inline int upd_of(const lsh_pattern* p) {
+  return p->scheme == LSH_SCHEME_VE ? UPD_VE : (p->scheme == LSH_SCHEME_LS_INC ? UPD_INC : UPD_LS);
+}
+
 // Enqueue one Basic Scheme iteration of the group; `cur` picks which P buffer
-// holds the previous iterate.
+// holds the previous iterate.  In the increment scheme (LSH_SCHEME_LS_INC) X
+// holds the increment of the state (at iteration 0 the start state with eps0
+// in its mean bins), the stress pass takes eps0 = 0, the Green pass writes the
+// increment into X, and the inverse axis-2 pass transforms it in place.
 // The passes of one iteration, launched one by one.
 template <typename T>
 void launch_stress(GroupRun<T>& G, hipStream_t st) {
   using T2 = C2<T>;
   const lsh_pattern* p = G.spec.rep;
   const T2* tw0 = (const T2*)(p->dev_persist + p->off_tw[0]);
+  const double* e0 = p->scheme == LSH_SCHEME_LS_INC ? G.w.eps0z : G.w.eps0;
   hipLaunchKernelGGL(G.K.a1s, G.gridS1, dim3(G.K.NT1s), G.K.lds1s, st, G.g, p->plan[0], tw0, (const T2*)G.w.X,
                      (T2*)G.w.TAU,
-                     (const Inst*)G.w.insts, (const int*)G.w.inst_of, G.w.eps0, (const int*)G.w.stop_iter,
+                     (const Inst*)G.w.insts, (const int*)G.w.inst_of, e0, (const int*)G.w.stop_iter,
                      (const int*)G.w.itp, (const double* const*)nullptr, (const double*)nullptr,
                      (double* const*)nullptr, (double*)nullptr);
 }
@@ -976,8 +1006,8 @@ void launch_green(GroupRun<T>& G, int cur, hipStream_t st) {
   hipLaunchKernelGGL(G.K.gr, G.gridG, dim3(G.K.NTG), G.K.ldsG, st, G.g, p->plan[2], tw2, G.gp, (const T2*)G.w.TAU,
                      (const T2*)G.w.P[cur], (T2*)G.w.P[1 - cur], table, (const Inst*)G.w.insts,
                      (const int*)G.w.inst_of, (const int*)G.w.chunks, (const int*)G.w.stop_iter,
-                     (const int*)G.w.itp, G.nload, G.npos, G.w.partial, G.K.lsG, G.gmode,
-                     G.spec.rep->scheme == LSH_SCHEME_VE ? 1 : 0);
+                     (const int*)G.w.itp, G.nload, G.npos, G.w.partial, G.K.lsG, G.gmode, upd_of(G.spec.rep),
+                     (T2*)G.w.X);
 }
 
 // The two passes of the two-pass schedule: P[cur] -> TAU -> P[1 - cur].
@@ -989,17 +1019,19 @@ void launch_twopass(GroupRun<T>& G, int cur, int which, hipStream_t st) {
   const T2* tw0 = (const T2*)(p->dev_persist + p->off_tw[0]);
   const T2* tw1 = (const T2*)(p->dev_persist + p->off_tw[1]);
   const T2* tw2 = (const T2*)(p->dev_persist + p->off_tw[2]);
+  const bool inc = p->scheme == LSH_SCHEME_LS_INC;  // the stress pass reads the increment in X
   if (which & 1)
     hipLaunchKernelGGL(c.s2, dim3(c.P * (G.g.n3 / c.W), G.nload), dim3(c.nts), c.ldss, st, G.g, tw0, tw1,
-                       (const T2*)G.w.P[cur], (T2*)G.w.TAU, (const Inst*)G.w.insts, (const int*)G.w.inst_of,
-                       (const double*)G.w.eps0, (const int*)G.w.stop_iter, (const int*)G.w.itp);
+                       (const T2*)(inc ? G.w.X : G.w.P[cur]), (T2*)G.w.TAU, (const Inst*)G.w.insts,
+                       (const int*)G.w.inst_of, (const double*)(inc ? G.w.eps0z : G.w.eps0),
+                       (const int*)G.w.stop_iter, (const int*)G.w.itp);
   if (which & 2) {
     const T* table = p->has_table ? (const T*)(p->dev_persist + p->off_table) : nullptr;
     hipLaunchKernelGGL(c.g3[G.gmode], dim3(G.g.h1 * c.Q, (unsigned)(G.chunks.size() / 2)), dim3(c.ntg), c.ldsg, st,
                        G.g, tw1, tw2, (const T2*)G.w.TAU, (const T2*)G.w.P[cur], (T2*)G.w.P[1 - cur], table,
                        (const Inst*)G.w.insts, (const int*)G.w.inst_of, (const int*)G.w.chunks,
-                       (const int*)G.w.stop_iter, (const int*)G.w.itp, G.g.h1 * c.Q, G.w.partial,
-                       p->scheme == LSH_SCHEME_VE ? 1 : 0);
+                       (const int*)G.w.stop_iter, (const int*)G.w.itp, G.g.h1 * c.Q, G.w.partial, upd_of(p),
+                       (T2*)G.w.X);
   }
 }
 
@@ -1044,7 +1076,8 @@ int group_iterate(GroupRun<T>& G, int cur, double tol, bool fixed, hipStream_t s
   }
   {
     Timer tm(4, st);
-    launch_axis2<T>(G, 1, (const T2*)G.w.P[1 - cur], (T2*)G.w.X, st);
+    const bool inc = G.spec.rep->scheme == LSH_SCHEME_LS_INC;
+    launch_axis2<T>(G, 1, (const T2*)(inc ? G.w.X : G.w.P[1 - cur]), (T2*)G.w.X, st);
   }
   {
     // residual, stop flags and the iteration counter's advance
@@ -1180,9 +1213,20 @@ int group_finish(GroupRun<T>& G, int done, double tol, bool fixed, double secs, 
   const T2* tw0 = (const T2*)(base + p->off_tw[0]);
   std::vector<int> nonfin(G.nload, 0);
   HIPCHK(hipMemcpyAsync(nonfin.data(), G.w.nonfinite, sizeof(int) * G.nload, hipMemcpyDeviceToHost, st));
-  if (G.K.tpi >= 0)  // back to the four-pass layout X, from the buffer each load's last iteration wrote
+  if (G.K.tpi >= 0) {  // back to the four-pass layout X, from the buffer each load's last iteration wrote
     twopass_from_split(G.g, G.K.tp[G.K.tpi].Q, (const T2*)(base + p->off_tw[1]), (const T2*)G.w.P[0],
                        (const T2*)G.w.P[1], (T2*)G.w.X, (const int*)G.w.stop_iter, (const int*)G.w.itp, G.nload, st);
+  } else if (p->scheme == LSH_SCHEME_LS_INC) {
+    // X holds the last increment; the state is the P buffer each load's last
+    // iteration wrote, back through the inverse axis-2 transform (every load)
+    const long long n = (long long)G.g.spec * 6 * G.nload;
+    hipLaunchKernelGGL(k_pick_parity<T>, dim3((unsigned)std::min<long long>((n + 255) / 256, 8192)), dim3(256), 0,
+                       st, (const T2*)G.w.P[0], (const T2*)G.w.P[1], (T2*)G.w.TAU, (long long)G.g.spec, G.nload,
+                       (const int*)G.w.stop_iter, (const int*)G.w.itp);
+    hipLaunchKernelGGL(G.K.a2[1], G.gridB, dim3(G.K.NT2), G.K.lds2, st, G.g, p->plan[1],
+                       (const T2*)(base + p->off_tw[1]), (const T2*)G.w.TAU, (T2*)G.w.X, (const int*)nullptr,
+                       (const int*)nullptr, (T)1);
+  }
   bool any_out = false;
   for (double* e : G.spec.eout) any_out = any_out || e != nullptr;
   if (any_out)

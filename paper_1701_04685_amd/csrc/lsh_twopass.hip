@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
                                                const Inst* __restrict__ insts, const int* __restrict__ inst_of,
                                                const int* __restrict__ chunks, const int* __restrict__ stop_iter,
                                                const int* __restrict__ itp, int npos, double* __restrict__ partial,
-                                               int ve) {
+                                               int upd, C2<T>* __restrict__ dP) {
   using T2 = C2<T>;
   static_assert(GM == GREEN_TABLE || GM == GREEN_MOMENTS, "tabled Green operators only");
   constexpr int LS = N3 + 1;  // odd line stride: the same entry of neighbouring lines in other banks
@@ -341,12 +341,10 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
         reg_fft<T, +1, P>(v, twP);
 #pragma unroll
         for (int rr = 0; rr < P; ++rr) {
-          const T2 po = Pold[g0 + rr * N3];
-          // variational scheme: the pass computes the correction, added to the old state
-          const T2 nv = ve ? cadd(v[rr], po) : v[rr];
+          double d2;
+          const T2 nv = green_update<T>(v[rr], Pold[g0 + rr * N3], upd, it, dP, g0 + rr * N3, &d2);
           Pnew[g0 + rr * N3] = nv;
-          const double dx = (double)nv.x - (double)po.x, dy = (double)nv.y - (double)po.y;
-          acc[0] += dx * dx + dy * dy;
+          acc[0] += d2;
           acc[1] += (double)nv.x * (double)nv.x + (double)nv.y * (double)nv.y;
         }
       }

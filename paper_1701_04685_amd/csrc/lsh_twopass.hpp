@@ -33,7 +33,7 @@ struct TwoPass {
   using S2 = void (*)(Geo, const C2<T>*, const C2<T>*, const C2<T>*, C2<T>*, const Inst*, const int*, const double*,
                       const int*, const int*);
   using G3 = void (*)(Geo, const C2<T>*, const C2<T>*, const C2<T>*, const C2<T>*, C2<T>*, const T*, const Inst*,
-                      const int*, const int*, const int*, const int*, int, double*, int);
+                      const int*, const int*, const int*, const int*, int, double*, int, C2<T>*);
   S2 s2 = nullptr;
   G3 g3[4] = {nullptr, nullptr, nullptr, nullptr};  // per Green mode (GREEN_TABLE, GREEN_MOMENTS built)
   int Q = 0, P = 0, W = 0;  // axis-2 split and the stress tile's width along i3

@@ -173,7 +173,7 @@ class Pattern:
     and fields carry 3 components).  Kernels: 'dirichlet',
     'dirichlet_modified', 'dlvp' ({"alpha": [d values]}) and 'box'
     ({"Xi": d x s directions, "R": alias radius, "tail": add the aliases
-    beyond R along slow axes}).  Schemes (set_scheme): 'ls', 've', 'cg'.
+    beyond R along slow axes}).  Schemes (set_scheme): 'ls', 've', 'cg', 'ls_inc'.
     """
 
     def __init__(self, M):
@@ -240,9 +240,10 @@ class Pattern:
         self._prec = None
 
     def set_scheme(self, scheme):
-        """'ls' (Lippmann-Schwinger, default), 've' (variational) or 'cg' (conjugate
-        gradients, Dirichlet kernel, odd m); rebind afterwards."""
-        _check(_lib.lsh_set_scheme(self._h, {"ls": 0, "ve": 1, "cg": 2}[scheme]))
+        """'ls' (Lippmann-Schwinger, default), 've' (variational), 'cg' (conjugate
+        gradients, Dirichlet kernel, odd m) or 'ls_inc' (the Lippmann-Schwinger
+        iterates computed from their increments); rebind afterwards."""
+        _check(_lib.lsh_set_scheme(self._h, {"ls": 0, "ve": 1, "cg": 2, "ls_inc": 3}[scheme]))
         self._prec = None
 
     def bind(self, precision="fp64"):
