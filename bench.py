@@ -456,7 +456,7 @@ def bench_cfg5(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_startcurve(args):
+def measure_startcurve(npk):
     """Iterations of the Basic Scheme to the Cauchy residual 1e-6 against the
     shape of the start's error, on the learned-start workload (128^3 RSA
     packings, f = 0.3, radii 6-12 grid steps, contrast 100, Dirichlet, FP64,
@@ -470,7 +470,6 @@ def bench_startcurve(args):
     eps = np.eye(6)[0].reshape(1, 6)
     nrng = np.random.Generator(np.random.PCG64(9))
     rows = {}
-    npk = max(1, args.eval_packings)
     for k in range(npk):
         ph = wst.packing(60000 + k, n)
         P = wst.grid_pattern(n, ph, 100.0, precision="fp64")
@@ -509,6 +508,13 @@ def bench_startcurve(args):
         for name, E0 in starts.items():
             rows.setdefault(name, []).append(iters_from(E0))
         del ws, Es
+    return rows
+
+
+def bench_startcurve(args):
+    """The start curve (measure_startcurve) on --eval-packings packings."""
+    npk = max(1, args.eval_packings)
+    rows = measure_startcurve(npk)
     out = {"metric": "Basic Scheme iterations to residual 1e-6 by start", "value": float(np.mean(rows["zero"])),
            "unit": "iterations (zero start)", "n_gpus": 1, "steps": npk, "warmup": 0, "ms_per_step": None,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -807,6 +813,19 @@ def bench_refine(args):
     t0 = time.perf_counter()
     c = pats["fp32"].solve(loads, tol=1e-6, max_iter=3000, workspace=ws, allow_notconverged=True)
     t32 = time.perf_counter() - t0
+    # the FP32 path in the increment form (LSH_SCHEME_LS_INC): the same iterates,
+    # with the transforms' rounding scaled by the increment
+    Pi = lsh.Pattern(np.diag([n, n, n]))
+    Pi.set_kernel("dirichlet")
+    Pi.set_stiffness(Cp, li.mean_reference(Cp), ph)
+    Pi.set_scheme("ls_inc")
+    Pi.bind("fp32")
+    Pi.solve(loads, tol=-1.0, max_iter=3, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d = Pi.solve(loads, tol=1e-6, max_iter=3000, workspace=ws, allow_notconverged=True)
+    tinc = time.perf_counter() - t0
+    d8 = Pi.solve(loads, tol=1e-8, max_iter=5000, workspace=ws, allow_notconverged=True)
     C64, Cmix = ref["sigma"].T, b["sigma"].T
     line = {"metric": "time to Cauchy residual 1e-6, FP64 alone / FP32 then FP64", "value": t64 / tmix, "unit": "x",
             "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": tmix * 1e3, "higher_is_better": True,
@@ -820,7 +839,15 @@ def bench_refine(args):
             "C_eff_rel_diff_vs_fp64_alone": float(np.linalg.norm(Cmix - C64) / np.linalg.norm(C64)),
             "fp32_alone_to_1e-6": {"seconds": round(t32, 4), "iterations": [int(v) for v in c["iterations"]],
                                    "converged": [bool(v) for v in c["converged"]],
-                                   "last_residual": [float(v) for v in c["residual"]]}}
+                                   "last_residual": [float(v) for v in c["residual"]]},
+            "fp32_increment_form_to_1e-6": {
+                "seconds": round(tinc, 4), "iterations": [int(v) for v in d["iterations"]],
+                "converged": [bool(v) for v in d["converged"]],
+                "speedup_vs_fp64_alone": round(t64 / tinc, 3),
+                "C_eff_rel_diff_vs_fp64": float(np.linalg.norm(d["sigma"].T - C64) / np.linalg.norm(C64))},
+            "fp32_increment_form_to_1e-8": {
+                "iterations": [int(v) for v in d8["iterations"]], "converged": [bool(v) for v in d8["converged"]],
+                "last_residual": [float(v) for v in d8["residual"]]}}
     print(json.dumps(line), flush=True)
 
 
@@ -1039,6 +1066,12 @@ def main():
         m3 = measure_cfg3(args, 100)
         m3.pop("_P")
         extra["nondiagonal_box_fp32"] = m3
+        torch.cuda.empty_cache()
+        # what a start field saves: iterations to 1e-6 on an unseen 128^3 packing
+        # of the learned-start workload from starts of known error shape
+        extra["warm_start_curve"] = {"iterations_to_1e-6_by_start": measure_startcurve(1),
+                                     "workload": "RSA packing 128^3 (seed 60000), f=0.3, radii 6-12, contrast 100, "
+                                                 "Dirichlet, FP64, load e11; starts from the field converged to 1e-10"}
         torch.cuda.empty_cache()
 
     cpu = None
