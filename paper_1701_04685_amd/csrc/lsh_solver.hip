@@ -852,7 +852,8 @@ int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
   }
   if (G.K.tpi >= 0) {
     rc = allow_lds(G.K.tp[G.K.tpi].s2, G.K.tp[G.K.tpi].ldss);
-    if (!rc) rc = allow_lds(G.K.tp[G.K.tpi].g3[G.gmode], G.K.tp[G.K.tpi].ldsg);
+    const bool inc = G.spec.rep->scheme == LSH_SCHEME_LS_INC;
+    if (!rc) rc = allow_lds(G.K.tp[G.K.tpi].green(G.gmode, inc), G.K.tp[G.K.tpi].ldsg);
     if (rc) return rc;
   }
   rc = allow_lds(G.K.gr, G.K.ldsG);
@@ -1027,7 +1028,8 @@ void launch_twopass(GroupRun<T>& G, int cur, int which, hipStream_t st) {
                        (const int*)G.w.stop_iter, (const int*)G.w.itp);
   if (which & 2) {
     const T* table = p->has_table ? (const T*)(p->dev_persist + p->off_table) : nullptr;
-    hipLaunchKernelGGL(c.g3[G.gmode], dim3(G.g.h1 * c.Q, (unsigned)(G.chunks.size() / 2)), dim3(c.ntg), c.ldsg, st,
+    hipLaunchKernelGGL(c.green(G.gmode, inc), dim3(G.g.h1 * c.Q, (unsigned)(G.chunks.size() / 2)), dim3(c.ntg),
+                       c.ldsg, st,
                        G.g, tw1, tw2, (const T2*)G.w.TAU, (const T2*)G.w.P[cur], (T2*)G.w.P[1 - cur], table,
                        (const Inst*)G.w.insts, (const int*)G.w.inst_of, (const int*)G.w.chunks,
                        (const int*)G.w.stop_iter, (const int*)G.w.itp, G.g.h1 * c.Q, G.w.partial, upd_of(p),
@@ -1132,7 +1134,8 @@ int tune_group(GroupRun<T>& G, hipStream_t st, int choice[4], int ncand[4], floa
       if (pass == 2) rc = allow_lds(G.K.gr, G.K.ldsG);
       if (pass == 3 && G.K.tpi >= 0) {
         rc = allow_lds(G.K.tp[G.K.tpi].s2, G.K.tp[G.K.tpi].ldss);
-        if (!rc) rc = allow_lds(G.K.tp[G.K.tpi].g3[G.gmode], G.K.tp[G.K.tpi].ldsg);
+        const bool inc = G.spec.rep->scheme == LSH_SCHEME_LS_INC;
+        if (!rc) rc = allow_lds(G.K.tp[G.K.tpi].green(G.gmode, inc), G.K.tp[G.K.tpi].ldsg);
       }
       if (rc) break;
       auto run = [&]() {

@@ -204,7 +204,12 @@ __global__ void __launch_bounds__(NT) k_stress2(Geo g, const C2<T>* __restrict__
 // transforms run in LDS, and the values go out through the inverse
 // transforms, the inverse P-point DFT again in registers, with the Cauchy
 // residual's partial sums (double).
-template <typename T, int P, int N3, int NT, int GM>
+// PF: fetch the next load's values while the current one is transformed (else
+// each load's values are fetched when its turn comes, which frees the
+// registers that hold them through the rest of the loop).  INC: the build for
+// the increment scheme (upd = UPD_INC); the other build serves UPD_LS and
+// UPD_VE, whose output stage then carries no increment store.
+template <typename T, int P, int N3, int NT, int GM, bool PF = true, bool INC = false>
 __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ tw1, const C2<T>* __restrict__ tw2,
                                                const C2<T>* __restrict__ tau, const C2<T>* __restrict__ Pold,
                                                C2<T>* __restrict__ Pnew, const T* __restrict__ table,
@@ -256,7 +261,7 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
     return L;
   };
   int L = next_active(Lbeg);
-  fetch(L);  // in flight while the Green operator is formed
+  if (PF) fetch(L);  // in flight while the Green operator is formed
 
   stage_twiddles<T>(tw3, tw2, N3);
   for (int i = tid; i < P; i += NT) twP[i] = tw1[i * Q];
@@ -282,6 +287,7 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
   __syncthreads();
 
   while (L < Lend) {
+    if (!PF) fetch(L);
     // P-point DFT over r on the way in (item (c, i3), consecutive items
     // consecutive i3), then the next active load's values are fetched
 #pragma unroll
@@ -298,7 +304,7 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
       }
     }
     const int Lnext = next_active(L + 1);
-    if (Lnext < Lend) fetch(Lnext);
+    if (PF && Lnext < Lend) fetch(Lnext);
     __syncthreads();
     fft_static<T, -1, N3, NLN, false, NT>(lines, LS, 1, tw3);
 
@@ -342,7 +348,16 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
 #pragma unroll
         for (int rr = 0; rr < P; ++rr) {
           double d2;
-          const T2 nv = green_update<T>(v[rr], Pold[g0 + rr * N3], upd, it, dP, g0 + rr * N3, &d2);
+          T2 nv;
+          if constexpr (INC) {
+            nv = green_update<T>(v[rr], Pold[g0 + rr * N3], UPD_INC, it, dP, g0 + rr * N3, &d2);
+          } else {
+            // variational scheme: the pass computes the correction, added to the old state
+            const T2 po = Pold[g0 + rr * N3];
+            nv = upd == UPD_VE ? cadd(v[rr], po) : v[rr];
+            const double dx = (double)nv.x - (double)po.x, dy = (double)nv.y - (double)po.y;
+            d2 = dx * dx + dy * dy;
+          }
           Pnew[g0 + rr * N3] = nv;
           acc[0] += d2;
           acc[1] += (double)nv.x * (double)nv.x + (double)nv.y * (double)nv.y;
@@ -442,8 +457,9 @@ constexpr int green3_nt() {
   return nt > 1024 ? 1024 : nt;
 }
 
-// a variant for the SNF grid (N1, N2, N3) with N2 = Q P and stress tiles W wide
-template <typename T, int N1, int N2, int N3, int Q, int W>
+// a variant for the SNF grid (N1, N2, N3) with N2 = Q P, stress tiles W wide,
+// and the Green pass with or without the next load's prefetch
+template <typename T, int N1, int N2, int N3, int Q, int W, bool PF = true>
 void add_cand(const Geo& g, TwoPass<T>* out, int maxn, int* n) {
   constexpr int P = N2 / Q;
   static_assert(P * Q == N2, "Q divides the axis-2 length");
@@ -454,8 +470,10 @@ void add_cand(const Geo& g, TwoPass<T>* out, int maxn, int* n) {
   constexpr int NTS = stress2_nt<N1, Q, W>();
   constexpr int NTG = green3_nt<T, P, N3>();
   c.s2 = k_stress2<T, N1, Q, W, NTS>;
-  c.g3[GREEN_TABLE] = k_green3<T, P, N3, NTG, GREEN_TABLE>;
-  c.g3[GREEN_MOMENTS] = k_green3<T, P, N3, NTG, GREEN_MOMENTS>;
+  c.g3[GREEN_TABLE] = k_green3<T, P, N3, NTG, GREEN_TABLE, PF>;
+  c.g3[GREEN_MOMENTS] = k_green3<T, P, N3, NTG, GREEN_MOMENTS, PF>;
+  c.g3inc[GREEN_TABLE] = k_green3<T, P, N3, NTG, GREEN_TABLE, PF, true>;
+  c.g3inc[GREEN_MOMENTS] = k_green3<T, P, N3, NTG, GREEN_MOMENTS, PF, true>;
   c.Q = Q;
   c.P = P;
   c.W = W;
@@ -466,9 +484,9 @@ void add_cand(const Geo& g, TwoPass<T>* out, int maxn, int* n) {
   out[(*n)++] = c;
 }
 
-template <typename T, int N, int Q, int W>
+template <typename T, int N, int Q, int W, bool PF = true>
 void add_cubic(const Geo& g, TwoPass<T>* out, int maxn, int* n) {
-  add_cand<T, N, N, N, Q, W>(g, out, maxn, n);
+  add_cand<T, N, N, N, Q, W, PF>(g, out, maxn, n);
 }
 
 template <typename T>
@@ -482,19 +500,26 @@ int candidates_t(const Geo& g, TwoPass<T>* out, int maxn) {
       case 32:
         add_cubic<T, 32, 4, 8>(g, out, maxn, &n);
         add_cubic<T, 32, 2, 16>(g, out, maxn, &n);
+        add_cubic<T, 32, 4, 8, false>(g, out, maxn, &n);
         break;
       case 48:
         add_cubic<T, 48, 4, 8>(g, out, maxn, &n);
         add_cubic<T, 48, 3, 8>(g, out, maxn, &n);
+        add_cubic<T, 48, 3, 8, false>(g, out, maxn, &n);
         break;
       case 64:
         add_cubic<T, 64, 4, 8>(g, out, maxn, &n);
         add_cubic<T, 64, 8, 4>(g, out, maxn, &n);
+        add_cubic<T, 64, 4, 8, false>(g, out, maxn, &n);
         break;
       case 96:
         add_cubic<T, 96, 6, 8>(g, out, maxn, &n);
         add_cubic<T, 96, 6, 4>(g, out, maxn, &n);
         add_cubic<T, 96, 8, 4>(g, out, maxn, &n);
+        // without the Green pass's prefetch (fewer registers live across the
+        // load loop: at 96 points the prefetching build spills)
+        add_cubic<T, 96, 6, 4, false>(g, out, maxn, &n);
+        add_cubic<T, 96, 8, 4, false>(g, out, maxn, &n);
         break;
       default:
         break;

@@ -35,7 +35,9 @@ struct TwoPass {
   using G3 = void (*)(Geo, const C2<T>*, const C2<T>*, const C2<T>*, const C2<T>*, C2<T>*, const T*, const Inst*,
                       const int*, const int*, const int*, const int*, int, double*, int, C2<T>*);
   S2 s2 = nullptr;
-  G3 g3[4] = {nullptr, nullptr, nullptr, nullptr};  // per Green mode (GREEN_TABLE, GREEN_MOMENTS built)
+  G3 g3[4] = {nullptr, nullptr, nullptr, nullptr};     // per Green mode (GREEN_TABLE, GREEN_MOMENTS built)
+  G3 g3inc[4] = {nullptr, nullptr, nullptr, nullptr};  // the same for the increment scheme
+  G3 green(int gmode, bool inc) const { return inc ? g3inc[gmode] : g3[gmode]; }
   int Q = 0, P = 0, W = 0;  // axis-2 split and the stress tile's width along i3
   int nts = 0, ntg = 0;     // threads per block of each pass
   size_t ldss = 0, ldsg = 0;
