@@ -207,5 +207,8 @@ def test_box_tail_and_scheme_arguments(lib):
     with pytest.raises(lib.LshError) as e:
         lib._check(lib._lib.lsh_set_scheme(P._h, 7))
     assert e.value.status == -1
-    for sc in ("ls", "ve", "cg"):
+    for sc in ("ls", "ve", "cg", "ls_inc"):
         P.set_scheme(sc)
+    for bad in (-1, 4):
+        with pytest.raises(lib.LshError):
+            lib._check(lib._lib.lsh_set_scheme(P._h, bad))
