@@ -183,21 +183,34 @@ __global__ void k_mask_relu(u16* __restrict__ g, int g_cs, int g_off, const u16*
   if (!(bf2f(act[p * a_cs + a_off + ch]) > 0.0f)) g[p * g_cs + g_off + ch] = 0;
 }
 
-// 2x2x2 average pooling (forward), output (D/2)^3
+// 2x2x2 average pooling (forward), output (D/2)^3.  One thread per 8 channels
+// of an output voxel (16-byte loads and stores): C, the offsets and the row
+// strides are multiples of 8 at every call.
 __global__ void k_pool(const u16* __restrict__ in, int in_cs, int in_off, u16* __restrict__ out, int out_cs,
                        int out_off, int C, int D, int H, int W) {
-  const int d = D / 2, h = H / 2, w = W / 2;
+  const int d = D / 2, h = H / 2, w = W / 2, C8 = C / 8;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)d * h * w * C) return;
-  const int ch = (int)(i % C);
-  const long long q = i / C;
+  if (i >= (long long)d * h * w * C8) return;
+  const int ch = 8 * (int)(i % C8);
+  const long long q = i / C8;
   const int x = (int)(q % w), y = (int)((q / w) % h), z = (int)(q / ((long long)w * h));
-  float s = 0.0f;
+  float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
-      for (int e = 0; e < 2; ++e)
-        s += bf2f(in[(((long long)(2 * z + a) * H + 2 * y + b) * W + 2 * x + e) * in_cs + in_off + ch]);
-  out[q * out_cs + out_off + ch] = f2bf(0.125f * s);
+      for (int e = 0; e < 2; ++e) {
+        const uint4 v = *reinterpret_cast<const uint4*>(
+            in + (((long long)(2 * z + a) * H + 2 * y + b) * W + 2 * x + e) * in_cs + in_off + ch);
+        const unsigned u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          s[2 * k] += bf2f((u16)(u[k] & 0xFFFFu));
+          s[2 * k + 1] += bf2f((u16)(u[k] >> 16));
+        }
+      }
+  unsigned o[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o[k] = (unsigned)f2bf(0.125f * s[2 * k]) | ((unsigned)f2bf(0.125f * s[2 * k + 1]) << 16);
+  *reinterpret_cast<uint4*>(out + q * out_cs + out_off + ch) = uint4{o[0], o[1], o[2], o[3]};
 }
 
 // pooling backward: dIn[child] += dOut[parent] / 8
@@ -213,17 +226,20 @@ __global__ void k_pool_bwd(const u16* __restrict__ dout, int do_cs, int do_off, 
   din[p * di_cs + di_off + ch] = f2bf(v);
 }
 
-// nearest upsampling x2 (forward): out (2D)^3 from in D^3
+// nearest upsampling x2 (forward): out (2D)^3 from in D^3; one thread per 8
+// channels of an output voxel (16-byte copies; C, offsets and strides are
+// multiples of 8 at every call)
 __global__ void k_up(const u16* __restrict__ in, int in_cs, int in_off, u16* __restrict__ out, int out_cs, int out_off,
                      int C, int D, int H, int W) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int D2 = 2 * D, H2 = 2 * H, W2 = 2 * W;
-  if (i >= (long long)D2 * H2 * W2 * C) return;
-  const int ch = (int)(i % C);
-  const long long p = i / C;
+  const int D2 = 2 * D, H2 = 2 * H, W2 = 2 * W, C8 = C / 8;
+  if (i >= (long long)D2 * H2 * W2 * C8) return;
+  const int ch = 8 * (int)(i % C8);
+  const long long p = i / C8;
   const int x = (int)(p % W2), y = (int)((p / W2) % H2), z = (int)(p / ((long long)W2 * H2));
   const long long q = ((long long)(z / 2) * H + y / 2) * W + x / 2;
-  out[p * out_cs + out_off + ch] = in[q * in_cs + in_off + ch];
+  *reinterpret_cast<uint4*>(out + p * out_cs + out_off + ch) =
+      *reinterpret_cast<const uint4*>(in + q * in_cs + in_off + ch);
 }
 
 // upsampling backward: dIn[q] = sum of the 8 children of q
@@ -243,13 +259,14 @@ __global__ void k_up_bwd(const u16* __restrict__ dout, int do_cs, int do_off, u1
   din[q * di_cs + di_off + ch] = f2bf(s);
 }
 
-// input: channel 0 = phase indicator, channels 1..31 = 0
+// input: channel 0 = phase indicator, channels 1..31 = 0; one thread per 8
+// channels of a voxel (16-byte stores)
 __global__ void k_pack_input(const uint8_t* __restrict__ phase, long long V, u16* __restrict__ x) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= V * 32) return;
-  const long long p = i / 32;
-  const int ch = (int)(i % 32);
-  x[i] = ch == 0 ? f2bf(phase[p] ? 1.0f : 0.0f) : (u16)0;
+  if (i >= V * 4) return;
+  const long long p = i / 4;
+  const unsigned c0 = (i % 4) == 0 ? (unsigned)f2bf(phase[p] ? 1.0f : 0.0f) : 0u;
+  *reinterpret_cast<uint4*>(x + 8 * i) = uint4{c0, 0u, 0u, 0u};
 }
 
 // mean squared error over 36 channels: dy = 2 (y - T) / (V 36) (bf16, 64 channels), loss partial sums
@@ -304,17 +321,34 @@ __global__ void k_cast_weights(const float* __restrict__ w, int ntap, int cout, 
   wb[((long long)t * cin + ci) * cout + co] = h;
 }
 
-// E_out[L][c][p] = (c < 3 ? 1 : sqrt2) sum_j eps0[L][j] y[p][6 j + c]
-__global__ void k_contract(const float* __restrict__ y, long long V, const double* __restrict__ eps0, int nload,
-                           double* __restrict__ E) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= V * 6 * nload) return;
-  const long long p = i % V;
-  const int c = (int)((i / V) % 6);
-  const int L = (int)(i / (V * 6));
-  double s = 0.0;
-  for (int j = 0; j < 6; ++j) s += eps0[6 * L + j] * (double)y[p * 64 + 6 * j + c];
-  E[i] = s * (c < 3 ? 1.0 : 1.41421356237309504880);
+// E_out[L][c][p] = (c < 3 ? 1 : sqrt2) sum_j eps0[L][j] y[p][6 j + c].  A block
+// takes 64 voxels: their rows of y (64 channels, 16 KB) come in with coalesced
+// 16-byte loads into LDS (rows padded to 65 words, so that a wave reading one
+// column of 64 rows hits 64 banks), and the outputs leave voxel-fastest.
+__global__ void __launch_bounds__(256) k_contract(const float* __restrict__ y, long long V,
+                                                  const double* __restrict__ eps0, int nload,
+                                                  double* __restrict__ E) {
+  __shared__ float ys[64][65];
+  const long long p0 = (long long)blockIdx.x * 64;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 64 * 16; i += 256) {
+    const int row = i >> 4, q = i & 15;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (p0 + row < V) v = reinterpret_cast<const float4*>(y + (p0 + row) * 64)[q];
+    ys[row][4 * q] = v.x;
+    ys[row][4 * q + 1] = v.y;
+    ys[row][4 * q + 2] = v.z;
+    ys[row][4 * q + 3] = v.w;
+  }
+  __syncthreads();
+  for (int i = tid; i < nload * 6 * 64; i += 256) {
+    const int pv = i & 63, lc = i >> 6;
+    const int L = lc / 6, c = lc - 6 * L;
+    if (p0 + pv >= V) continue;
+    double s = 0.0;
+    for (int j = 0; j < 6; ++j) s += eps0[6 * L + j] * (double)ys[pv][6 * j + c];
+    E[(long long)lc * V + p0 + pv] = s * (c < 3 ? 1.0 : 1.41421356237309504880);
+  }
 }
 
 // T[p][6 j + c] = E6[j][c][p] (Voigt -> Mandel)
@@ -455,22 +489,22 @@ void mask(u16* g, int g_cs, int g_off, const u16* act, int a_cs, int a_off, int 
 void forward(lsh_unet* net, const Acts& a, const uint8_t* phase, int n, hipStream_t st) {
   const int n1 = n / 2, n2 = n / 4;
   const long long V0 = (long long)n * n * n;
-  hipLaunchKernelGGL(k_pack_input, dim3(blocks(V0 * 32, 256)), dim3(256), 0, st, phase, V0, a.x0);
+  hipLaunchKernelGGL(k_pack_input, dim3(blocks(V0 * 4, 256)), dim3(256), 0, st, phase, V0, a.x0);
   conv_fwd(net, E1A, a.x0, 32, 0, a.e1a, nullptr, 32, 0, 1, n, st);
   conv_fwd(net, E1B, a.e1a, 32, 0, a.cat1, nullptr, 96, 64, 1, n, st);
-  hipLaunchKernelGGL(k_pool, dim3(blocks((long long)n1 * n1 * n1 * 32, 256)), dim3(256), 0, st, (const u16*)a.cat1, 96,
+  hipLaunchKernelGGL(k_pool, dim3(blocks((long long)n1 * n1 * n1 * 4, 256)), dim3(256), 0, st, (const u16*)a.cat1, 96,
                      64, a.p1, 32, 0, 32, n, n, n);
   conv_fwd(net, E2A, a.p1, 32, 0, a.e2a, nullptr, 64, 0, 1, n1, st);
   conv_fwd(net, E2B, a.e2a, 64, 0, a.cat2, nullptr, 192, 128, 1, n1, st);
-  hipLaunchKernelGGL(k_pool, dim3(blocks((long long)n2 * n2 * n2 * 64, 256)), dim3(256), 0, st, (const u16*)a.cat2,
+  hipLaunchKernelGGL(k_pool, dim3(blocks((long long)n2 * n2 * n2 * 8, 256)), dim3(256), 0, st, (const u16*)a.cat2,
                      192, 128, a.p2, 64, 0, 64, n1, n1, n1);
   conv_fwd(net, E3A, a.p2, 64, 0, a.e3a, nullptr, 128, 0, 1, n2, st);
   conv_fwd(net, E3B, a.e3a, 128, 0, a.e3b, nullptr, 128, 0, 1, n2, st);
-  hipLaunchKernelGGL(k_up, dim3(blocks((long long)n1 * n1 * n1 * 128, 256)), dim3(256), 0, st, (const u16*)a.e3b, 128,
+  hipLaunchKernelGGL(k_up, dim3(blocks((long long)n1 * n1 * n1 * 16, 256)), dim3(256), 0, st, (const u16*)a.e3b, 128,
                      0, a.cat2, 192, 0, 128, n2, n2, n2);
   conv_fwd(net, D2A, a.cat2, 192, 0, a.d2a, nullptr, 64, 0, 1, n1, st);
   conv_fwd(net, D2B, a.d2a, 64, 0, a.d2b, nullptr, 64, 0, 1, n1, st);
-  hipLaunchKernelGGL(k_up, dim3(blocks(V0 * 64, 256)), dim3(256), 0, st, (const u16*)a.d2b, 64, 0, a.cat1, 96, 0, 64,
+  hipLaunchKernelGGL(k_up, dim3(blocks(V0 * 8, 256)), dim3(256), 0, st, (const u16*)a.d2b, 64, 0, a.cat1, 96, 0, 64,
                      n1, n1, n1);
   conv_fwd(net, D1A, a.cat1, 96, 0, a.d1a, nullptr, 32, 0, 1, n, st);
   conv_fwd(net, D1B, a.d1a, 32, 0, a.d1b, nullptr, 32, 0, 1, n, st);
@@ -662,7 +696,7 @@ extern "C" int lsh_unet_predict(lsh_unet* net, const uint8_t* phase, int n, cons
   const long long V0 = (long long)n * n * n;
   forward(net, a, phase, n, st);
   UCHK(hipMemcpyAsync(a.eps, eps0_voigt, sizeof(double) * 6 * nload, hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_contract, dim3(blocks(V0 * 6 * nload, 256)), dim3(256), 0, st, (const float*)a.y, V0,
+  hipLaunchKernelGGL(k_contract, dim3(blocks(V0, 64)), dim3(256), 0, st, (const float*)a.y, V0,
                      (const double*)a.eps, nload, dev_E_out);
   UCHK(hipGetLastError());
   UCHK(hipStreamSynchronize(st));
