@@ -41,6 +41,7 @@ k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
                                               double* __restrict__ partial) {
   using T2 = C2<T>;
   constexpr int W3 = 3 * W;
+  constexpr bool NTS = sizeof(T) == 4;  // nontemporal state and polarisation (measured: pays in FP32 only)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n1 = NC > 0 ? NC : g.n1;
   const int h1 = n1 / 2 + 1;
@@ -107,8 +108,8 @@ k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
         ra[i] = T2{0, 0};
         rb[i] = T2{0, 0};
         if ((npairs % NT == 0 || idx < npairs) && a30 + idx % W < g.n3) {
-          ra[i] = X[addr(idx, 0)];
-          rb[i] = X[addr(idx, 1)];
+          ra[i] = ld_st<NTS>(X + addr(idx, 0));
+          rb[i] = ld_st<NTS>(X + addr(idx, 1));
         }
       }
 #pragma unroll
@@ -120,8 +121,8 @@ k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
       for (int idx = tid; idx < npairs; idx += NT) {
         T2 a = T2{0, 0}, b = T2{0, 0};
         if (a30 + idx % W < g.n3) {
-          a = X[addr(idx, 0)];
-          b = X[addr(idx, 1)];
+          a = ld_st<NTS>(X + addr(idx, 0));
+          b = ld_st<NTS>(X + addr(idx, 1));
         }
         put(idx, a, b);
       }
@@ -228,8 +229,8 @@ k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
     const T2 zn = Z[((n1 - k) % n1) * W3 + col];
     const T hf = (T)0.5;
     const long long off = (long long)k * n23 + colbase + w;
-    Y[((long long)(L * 6 + 2 * q)) * g.spec + off] = T2{hf * (zk.x + zn.x), hf * (zk.y - zn.y)};
-    Y[((long long)(L * 6 + 2 * q + 1)) * g.spec + off] = T2{hf * (zk.y + zn.y), hf * (zn.x - zk.x)};
+    st_st<NTS>(Y + ((long long)(L * 6 + 2 * q)) * g.spec + off, T2{hf * (zk.x + zn.x), hf * (zk.y - zn.y)});
+    st_st<NTS>(Y + ((long long)(L * 6 + 2 * q + 1)) * g.spec + off, T2{hf * (zk.y + zn.y), hf * (zn.x - zk.x)});
   };
   if constexpr (NC > 0) {
 #pragma unroll
@@ -641,7 +642,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
       const bool ok = (nu0 % NT == 0 || u < nu0) && (sl == 0 ? a0 : a1);
       const T2* src = tau + ((long long)((Lb + sl) * 6 + c)) * g.spec + row + j;
 #pragma unroll
-      for (int r = 0; r < R0; ++r) pf[q][r] = ok ? src[r * nbl0] : T2{0, 0};
+      for (int r = 0; r < R0; ++r) pf[q][r] = ok ? ld_nt(src + r * nbl0) : T2{0, 0};
     }
   };
   load0(Lbeg);  // in flight while the Green operator is formed
@@ -711,7 +712,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
       const bool ok = (nuL % NT == 0 || u < nuL) && (sl == 0 ? act0 : act1);
       const T2* src = Pold + ((long long)((L0 + sl) * 6 + c)) * g.spec + row + j;
 #pragma unroll
-      for (int r = 0; r < RL; ++r) po[q][r] = ok ? src[r * nblL] : T2{0, 0};
+      for (int r = 0; r < RL; ++r) po[q][r] = ok ? ld_nt(src + r * nblL) : T2{0, 0};
     }
     g2_fwd_rest<T, N, NLN, NT, 1, RH.r[0]>(lines, twl);
 
@@ -797,7 +798,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
           for (int r = 0; r < R; ++r) {
             double d2;
             const T2 nv = green_update<T>(v[q][r], po[q][r], upd, it, dP, g0 + r * nbl, &d2);
-            Pnew[g0 + r * nbl] = nv;
+            st_nt(Pnew + g0 + r * nbl, nv);
             dd += d2;
             nn += (double)nv.x * (double)nv.x + (double)nv.y * (double)nv.y;
           }
