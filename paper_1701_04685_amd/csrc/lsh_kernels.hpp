@@ -108,8 +108,8 @@ k_axis1(Geo g, FftPlan pl, const C2<T>* __restrict__ tw,
         ra[i] = T2{0, 0};
         rb[i] = T2{0, 0};
         if ((npairs % NT == 0 || idx < npairs) && a30 + idx % W < g.n3) {
-          ra[i] = ld_st<NTS>(X + addr(idx, 0));
-          rb[i] = ld_st<NTS>(X + addr(idx, 1));
+          ra[i] = ld_nt(X + addr(idx, 0));
+          rb[i] = ld_nt(X + addr(idx, 1));
         }
       }
 #pragma unroll
@@ -289,7 +289,8 @@ __global__ void __launch_bounds__(NT) k_axis2(Geo g, FftPlan pl, const C2<T>* __
     for (int i = 0; i < ET; ++i) {
       const int idx = tid + i * NT;
       r[i] = T2{0, 0};
-      if (((NC * W) % NT == 0 || idx < ne) && a30 + idx % W < g.n3) r[i] = src[base + (long long)(idx / W) * g.n3 + idx % W];
+      if (((NC * W) % NT == 0 || idx < ne) && a30 + idx % W < g.n3)
+        r[i] = ld_st<(DIR > 0)>(src + base + (long long)(idx / W) * g.n3 + idx % W);
     }
 #pragma unroll
     for (int i = 0; i < ET; ++i) {
