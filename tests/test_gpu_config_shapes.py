@@ -109,18 +109,45 @@ def test_cfg3_grid_lockstep(kind, prec, tol):
 _BOX512 = {}
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
-def test_box_512_lines_lockstep(prec, tol):
-    """Box {e1,e2,e3,e1+e2} (R = 1) on M = [[128,32,0],[0,128,0],[0,0,4]], SNF
-    (4, 32, 512): the tabled Green pass on 512-point lines, all six loads."""
+def box512_problem():
     if "pr" not in _BOX512:
         Cp, C0 = two_phase(1.0, 100.0)
         _BOX512["pr"] = Problem([[128, 32, 0], [0, 128, 0], [0, 0, 4]], "box", {"Xi": BOX_CFG3["Xi"], "R": 1},
                                 rsa_phase(5, 0.3, rmin=2.0, rmax=4.0), Cp, C0)
     pr = _BOX512["pr"]
     assert tuple(pr.G.e) == (4, 32, 512)
+    return pr
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_box_512_lines_lockstep(prec, tol):
+    """Box {e1,e2,e3,e1+e2} (R = 1) on M = [[128,32,0],[0,128,0],[0,0,4]], SNF
+    (4, 32, 512): the tabled Green pass on 512-point lines, all six loads."""
+    pr = box512_problem()
     res = lockstep_six_loads(pr, prec, 4)
     check_against(pr, res, oracle_runs("box512", pr, range(6), 4), tol)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_box_512_lines_every_green_variant(prec, tol):
+    """The same problem with each Green-pass variant built for the table form
+    forced in turn (one load per block in chunks of six, three or two loads),
+    all six loads, 4 iterations, against the oracle."""
+    import torch
+    pr = box512_problem()
+    pr.G.bind(prec)
+    ws = torch.empty(pr.G.workspace_bytes(6), dtype=torch.uint8, device="cuda")
+    info = pr.G.autotune(nload=6, workspace=ws)
+    ms = info["green"]["ms"]
+    built = [c for c in range(len(ms)) if ms[c] > 0]
+    assert len(built) >= 3, ms
+    refs = oracle_runs("box512", pr, range(6), 4)
+    for c in built:
+        print(f"Green variant {c} {prec}", flush=True)
+        pr.G.tune_set([info["stress"]["choice"], info["axis2"]["choice"], c, 0])
+        res = pr.G.solve(LOADS, tol=-1.0, max_iter=4, return_E=True, workspace=ws, history=True)
+        check_against(pr, res, refs, tol)
+    pr.G.tune_reset()
 
 
 @pytest.mark.parametrize("prec,atol", [("fp64", 5e-12), ("fp32", 2e-7)])
