@@ -110,6 +110,117 @@ __global__ void __launch_bounds__(256) k_conv(const u16* __restrict__ in, int in
     }
 }
 
+// The same convolution with the input staged in LDS.  Block: an 8 x 4 x 4
+// (x, y, z) tile of output voxels and 16 NTL output channels; per chunk of 32
+// input channels its 10 x 6 x 6 halo (periodic) comes into LDS once, and the
+// 27 taps read their A fragments there instead of from the cache hierarchy
+// (the global version re-reads every input row once per tap).  Wave w takes
+// the tile's voxels 32 w .. 32 w + 31 (two 16-voxel row tiles: 8 x 2 at one
+// z) against the block's channels.  Needs W % 8 == 0, H % 4 == 0, D % 4 == 0.
+constexpr int HX = 10, HY = 6, HZ = 6, HV = HX * HY * HZ;
+constexpr int HROW = 40;  // u16 per halo voxel: 32 channels + 8 pad (bank spread)
+template <int NTL>
+__global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, int in_cs, int in_off, int K,
+                                                  const u16* __restrict__ wt, int N, const float* __restrict__ bias,
+                                                  int ks, int flip, u16* __restrict__ out_bf,
+                                                  float* __restrict__ out_f, int out_cs, int out_off, int relu, int D,
+                                                  int H, int W) {
+  __shared__ __align__(16) u16 halo[HV * HROW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tx = W / 8, ty = H / 4;
+  const int bx = blockIdx.x % tx, by = (blockIdx.x / tx) % ty, bz = blockIdx.x / (tx * ty);
+  const int x0 = 8 * bx, y0 = 4 * by, z0 = 4 * bz;
+  const int n0 = blockIdx.y * 16 * NTL;
+  const int r = lane & 15, g = lane >> 4;
+  // this lane's voxel in each of the wave's two row tiles (v = x + 8 y + 32 z)
+  int vx[2], vy[2], vz[2];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi) {
+    const int v = 32 * wave + 16 * mi + r;
+    vx[mi] = v & 7;
+    vy[mi] = (v >> 3) & 3;
+    vz[mi] = v >> 5;
+  }
+  f4 acc[2][NTL];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < NTL; ++nj) acc[mi][nj] = f4{0, 0, 0, 0};
+  const int ntap = ks * ks * ks;
+  const int c = ks / 2;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    // halo voxel h = hx + HX (hy + HY hz) <- input voxel (x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz), periodic
+    for (int sgm = tid; sgm < HV * 4; sgm += 256) {
+      const int h = sgm >> 2, part = sgm & 3;
+      const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+      const int q = (wrap(z0 - 1 + hz, D) * H + wrap(y0 - 1 + hy, H)) * W + wrap(x0 - 1 + hx, W);
+      *reinterpret_cast<uint4*>(halo + h * HROW + 8 * part) =
+          *reinterpret_cast<const uint4*>(in + (long long)q * in_cs + in_off + k0 + 8 * part);
+    }
+    __syncthreads();
+    for (int t = 0; t < ntap; ++t) {
+      int dz = t / (ks * ks) - c, dy = (t / ks) % ks - c, dx = t % ks - c;
+      if (flip) {
+        dz = -dz;
+        dy = -dy;
+        dx = -dx;
+      }
+      bf16x8 a[2], b[NTL];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) {
+        const int h = (vx[mi] + 1 + dx) + HX * ((vy[mi] + 1 + dy) + HY * (vz[mi] + 1 + dz));
+        a[mi] = ld8(halo + h * HROW + 8 * g);
+      }
+      const u16* wb = wt + ((long long)t * N + n0 + r) * K + k0 + 8 * g;
+#pragma unroll
+      for (int nj = 0; nj < NTL; ++nj) b[nj] = ld8(wb + (long long)16 * nj * K);
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < NTL; ++nj)
+          acc[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mi], b[nj], acc[mi][nj], 0, 0, 0);
+    }
+    __syncthreads();  // the next chunk overwrites the halo
+  }
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < NTL; ++nj) {
+      const int ch = n0 + 16 * nj + r;
+      const float bv = bias ? bias[ch] : 0.0f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // row 4 g + i of the row tile: the voxel the lane with r = 4 g + i holds
+        const int v = 32 * wave + 16 * mi + 4 * g + i;
+        const long long p = ((long long)(z0 + (v >> 5)) * H + y0 + ((v >> 3) & 3)) * W + x0 + (v & 7);
+        float val = acc[mi][nj][i] + bv;
+        if (relu) val = fmaxf(val, 0.0f);
+        if (out_f)
+          out_f[p * out_cs + out_off + ch] = val;
+        else
+          out_bf[p * out_cs + out_off + ch] = f2bf(val);
+      }
+    }
+}
+
+// Both convolutions behind one call: the LDS-staged one where the grid tiles
+// into 8 x 4 x 4 blocks (64 output channels per block when N allows, so the
+// halo is staged once for them), the global one elsewhere (the coarsest
+// levels of small grids).
+void launch_conv(const u16* in, int in_cs, int in_off, int K, const u16* wt, int N, const float* bias, int ks,
+                 int flip, u16* out_bf, float* out_f, int out_cs, int out_off, int relu, int n, hipStream_t st) {
+  const long long V = (long long)n * n * n;
+  if (n % 8 == 0 && N % 64 == 0)
+    hipLaunchKernelGGL(k_conv_lds<4>, dim3((unsigned)(V / 128), N / 64), dim3(256), 0, st, in, in_cs, in_off, K, wt,
+                       N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
+  else if (n % 8 == 0)
+    hipLaunchKernelGGL(k_conv_lds<2>, dim3((unsigned)(V / 128), N / 32), dim3(256), 0, st, in, in_cs, in_off, K, wt,
+                       N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
+  else
+    hipLaunchKernelGGL(k_conv, dim3((unsigned)((V + 127) / 128), N / 32), dim3(256), 0, st, in, in_cs, in_off, K, wt,
+                       N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
+}
+
 // -------------------------------------------------------- weight gradient ---
 // dW[t][co][ci] += sum_p dout[p][co] * in[p + d_t][ci]; block tile 32 co x 32 ci,
 // a chunk of voxels per block (atomics across chunks).  Voxel tiles of 32 are
@@ -457,11 +568,9 @@ Acts act_layout(int n, bool training, char* base) {
 void conv_fwd(lsh_unet* net, int l, const u16* in, int in_cs, int in_off, u16* out_bf, float* out_f, int out_cs,
               int out_off, int relu, int n, hipStream_t st) {
   const LayerDesc& d = net->L[l];
-  const long long V = (long long)n * n * n;
   const long long wofs = d.w_off;
-  hipLaunchKernelGGL(k_conv, dim3(blocks(V, 128), d.cout / 32), dim3(256), 0, st, in, in_cs, in_off, d.cin,
-                     (const u16*)(net->wf + wofs), d.cout, (const float*)(net->w + d.b_off), d.ks, 0, out_bf, out_f,
-                     out_cs, out_off, relu, n, n, n);
+  launch_conv(in, in_cs, in_off, d.cin, (const u16*)(net->wf + wofs), d.cout, (const float*)(net->w + d.b_off), d.ks,
+              0, out_bf, out_f, out_cs, out_off, relu, n, st);
 }
 
 // backward of layer l given dPre (already masked): weight/bias grads and (if din) input grads
@@ -476,9 +585,8 @@ void conv_bwd(lsh_unet* net, int l, const u16* in, int in_cs, int in_off, const 
   hipLaunchKernelGGL(k_bias_grad, dim3(std::min<long long>(blocks(V, 4), 512), blocks(d.cout, 64)), dim3(256), 0, st,
                      dpre, dp_cs, dp_off, d.cout, (int)V, net->g + d.b_off);
   if (din)
-    hipLaunchKernelGGL(k_conv, dim3(blocks(V, 128), d.cin / 32), dim3(256), 0, st, dpre, dp_cs, dp_off, d.cout,
-                       (const u16*)(net->wb + d.w_off), d.cin, (const float*)nullptr, d.ks, 1, din, (float*)nullptr,
-                       di_cs, di_off, 0, n, n, n);
+    launch_conv(dpre, dp_cs, dp_off, d.cout, (const u16*)(net->wb + d.w_off), d.cin, (const float*)nullptr, d.ks, 1,
+                din, (float*)nullptr, di_cs, di_off, 0, n, st);
 }
 
 void mask(u16* g, int g_cs, int g_off, const u16* act, int a_cs, int a_off, int C, int n, hipStream_t st) {
