@@ -110,40 +110,41 @@ __global__ void __launch_bounds__(256) k_conv(const u16* __restrict__ in, int in
     }
 }
 
-// The same convolution with the input staged in LDS.  Block: an 8 x 4 x 4
+// The same convolution with the input staged in LDS.  Block: an 8 x 2MT x 4
 // (x, y, z) tile of output voxels and 16 NTL output channels; per chunk of 32
-// input channels its 10 x 6 x 6 halo (periodic) comes into LDS once, and the
-// 27 taps read their A fragments there instead of from the cache hierarchy
-// (the global version re-reads every input row once per tap).  Wave w takes
-// the tile's voxels 32 w .. 32 w + 31 (two 16-voxel row tiles: 8 x 2 at one
-// z) against the block's channels.  Needs W % 8 == 0, H % 4 == 0, D % 4 == 0.
-constexpr int HX = 10, HY = 6, HZ = 6, HV = HX * HY * HZ;
+// input channels its 10 x (2MT + 2) x 6 halo (periodic) comes into LDS once,
+// and the 27 taps read their A fragments there instead of from the cache
+// hierarchy (the global version re-reads every input row once per tap).
+// Wave w takes the tile's voxels v = x + 8 y + 16 MT z in [16 MT w, 16 MT (w
+// + 1)): MT row tiles of 16 (8 x 2 at one z) against the block's channels.
+// Needs W % 8 == 0, H % (2 MT) == 0, D % 4 == 0.
 constexpr int HROW = 40;  // u16 per halo voxel: 32 channels + 8 pad (bank spread)
-template <int NTL>
+template <int MT, int NTL>
 __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, int in_cs, int in_off, int K,
                                                   const u16* __restrict__ wt, int N, const float* __restrict__ bias,
                                                   int ks, int flip, u16* __restrict__ out_bf,
                                                   float* __restrict__ out_f, int out_cs, int out_off, int relu, int D,
                                                   int H, int W) {
+  constexpr int TY = 2 * MT, HX = 10, HY = TY + 2, HZ = 6, HV = HX * HY * HZ;
   __shared__ __align__(16) u16 halo[HV * HROW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tx = W / 8, ty = H / 4;
+  const int tx = W / 8, ty = H / TY;
   const int bx = blockIdx.x % tx, by = (blockIdx.x / tx) % ty, bz = blockIdx.x / (tx * ty);
-  const int x0 = 8 * bx, y0 = 4 * by, z0 = 4 * bz;
+  const int x0 = 8 * bx, y0 = TY * by, z0 = 4 * bz;
   const int n0 = blockIdx.y * 16 * NTL;
   const int r = lane & 15, g = lane >> 4;
-  // this lane's voxel in each of the wave's two row tiles (v = x + 8 y + 32 z)
-  int vx[2], vy[2], vz[2];
+  // this lane's voxel in each of the wave's row tiles
+  int vx[MT], vy[MT], vz[MT];
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi) {
-    const int v = 32 * wave + 16 * mi + r;
+  for (int mi = 0; mi < MT; ++mi) {
+    const int v = 16 * MT * wave + 16 * mi + r;
     vx[mi] = v & 7;
-    vy[mi] = (v >> 3) & 3;
-    vz[mi] = v >> 5;
+    vy[mi] = (v >> 3) % TY;
+    vz[mi] = v / (8 * TY);
   }
-  f4 acc[2][NTL];
+  f4 acc[MT][NTL];
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
     for (int nj = 0; nj < NTL; ++nj) acc[mi][nj] = f4{0, 0, 0, 0};
   const int ntap = ks * ks * ks;
@@ -165,9 +166,9 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
         dy = -dy;
         dx = -dx;
       }
-      bf16x8 a[2], b[NTL];
+      bf16x8 a[MT], b[NTL];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi) {
+      for (int mi = 0; mi < MT; ++mi) {
         const int h = (vx[mi] + 1 + dx) + HX * ((vy[mi] + 1 + dy) + HY * (vz[mi] + 1 + dz));
         a[mi] = ld8(halo + h * HROW + 8 * g);
       }
@@ -175,7 +176,7 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
 #pragma unroll
       for (int nj = 0; nj < NTL; ++nj) b[nj] = ld8(wb + (long long)16 * nj * K);
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
         for (int nj = 0; nj < NTL; ++nj)
           acc[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mi], b[nj], acc[mi][nj], 0, 0, 0);
@@ -183,7 +184,7 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
     __syncthreads();  // the next chunk overwrites the halo
   }
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
     for (int nj = 0; nj < NTL; ++nj) {
       const int ch = n0 + 16 * nj + r;
@@ -191,8 +192,8 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         // row 4 g + i of the row tile: the voxel the lane with r = 4 g + i holds
-        const int v = 32 * wave + 16 * mi + 4 * g + i;
-        const long long p = ((long long)(z0 + (v >> 5)) * H + y0 + ((v >> 3) & 3)) * W + x0 + (v & 7);
+        const int v = 16 * MT * wave + 16 * mi + 4 * g + i;
+        const long long p = ((long long)(z0 + v / (8 * TY)) * H + y0 + (v >> 3) % TY) * W + x0 + (v & 7);
         float val = acc[mi][nj][i] + bv;
         if (relu) val = fmaxf(val, 0.0f);
         if (out_f)
@@ -204,18 +205,18 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
 }
 
 // Both convolutions behind one call: the LDS-staged one where the grid tiles
-// into 8 x 4 x 4 blocks (64 output channels per block when N allows, so the
-// halo is staged once for them), the global one elsewhere (the coarsest
-// levels of small grids).
+// into its blocks (8 x 8 x 4 voxels, 64 output channels per block when N
+// allows, so the halo is staged once for them), the global one elsewhere
+// (the coarsest levels of small grids).
 void launch_conv(const u16* in, int in_cs, int in_off, int K, const u16* wt, int N, const float* bias, int ks,
                  int flip, u16* out_bf, float* out_f, int out_cs, int out_off, int relu, int n, hipStream_t st) {
   const long long V = (long long)n * n * n;
   if (n % 8 == 0 && N % 64 == 0)
-    hipLaunchKernelGGL(k_conv_lds<4>, dim3((unsigned)(V / 128), N / 64), dim3(256), 0, st, in, in_cs, in_off, K, wt,
-                       N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
+    hipLaunchKernelGGL((k_conv_lds<4, 4>), dim3((unsigned)(V / 256), N / 64), dim3(256), 0, st, in, in_cs, in_off, K,
+                       wt, N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
   else if (n % 8 == 0)
-    hipLaunchKernelGGL(k_conv_lds<2>, dim3((unsigned)(V / 128), N / 32), dim3(256), 0, st, in, in_cs, in_off, K, wt,
-                       N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
+    hipLaunchKernelGGL((k_conv_lds<4, 2>), dim3((unsigned)(V / 256), N / 32), dim3(256), 0, st, in, in_cs, in_off, K,
+                       wt, N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
   else
     hipLaunchKernelGGL(k_conv, dim3((unsigned)((V + 127) / 128), N / 32), dim3(256), 0, st, in, in_cs, in_off, K, wt,
                        N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
