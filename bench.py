@@ -779,11 +779,12 @@ def bench_cg(args):
 
 
 def bench_refine(args):
-    """FP32 then FP64: the FP32 path's Cauchy residual levels off near 1e-6 at
-    contrast 100, so a tight tolerance needs FP64.  Solving in FP32 to 1e-5 and
-    continuing in FP64 from that field (the start-field input) reaches 1e-6
-    with most iterations at FP32 cost.  128^3 Dirichlet, RSA spheres f = 0.3
-    with radii 6-12 grid steps, contrast 100, six unit loads."""
+    """Reaching 1e-6 at contrast 100, where the plain FP32 iteration's Cauchy
+    residual levels off near the tolerance: FP64 alone; FP32 to 1e-5 continued
+    in FP64 from that field (the start-field input); FP32 alone; and FP32 in the
+    increment form (LSH_SCHEME_LS_INC), whose residual keeps falling (also taken
+    to 1e-8).  128^3 Dirichlet, RSA spheres f = 0.3 with radii 6-12 grid steps,
+    contrast 100, six unit loads."""
     import torch
     from paper_1701_04685_amd import lsh, warmstart as wst
     import lsh_inputs as li
