@@ -205,13 +205,14 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
 }
 
 // Both convolutions behind one call: the LDS-staged one where the grid tiles
-// into its blocks (8 x 8 x 4 voxels, 64 output channels per block when N
-// allows, so the halo is staged once for them), the global one elsewhere
-// (the coarsest levels of small grids).
+// into its blocks (8 x 8 x 4 voxels; 64 output channels per block when N
+// allows and the layer still has 2048 blocks, so the halo is staged once for
+// them, else 32), the global one elsewhere (the coarsest levels of small
+// grids).
 void launch_conv(const u16* in, int in_cs, int in_off, int K, const u16* wt, int N, const float* bias, int ks,
                  int flip, u16* out_bf, float* out_f, int out_cs, int out_off, int relu, int n, hipStream_t st) {
   const long long V = (long long)n * n * n;
-  if (n % 8 == 0 && N % 64 == 0)
+  if (n % 8 == 0 && N % 64 == 0 && (V / 256) * (N / 64) >= 2048)
     hipLaunchKernelGGL((k_conv_lds<4, 4>), dim3((unsigned)(V / 256), N / 64), dim3(256), 0, st, in, in_cs, in_off, K,
                        wt, N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
   else if (n % 8 == 0)
