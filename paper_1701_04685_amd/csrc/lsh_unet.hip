@@ -119,10 +119,10 @@ __global__ void __launch_bounds__(256) k_conv(const u16* __restrict__ in, int in
 // + 1)): MT row tiles of 16 (8 x 2 at one z) against the block's channels.
 // Needs W % 8 == 0, H % (2 MT) == 0, D % 4 == 0.
 constexpr int HROW = 40;  // u16 per halo voxel: 32 channels + 8 pad (bank spread)
-template <int MT, int NTL>
+template <int MT, int NTL, int KS>
 __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, int in_cs, int in_off, int K,
                                                   const u16* __restrict__ wt, int N, const float* __restrict__ bias,
-                                                  int ks, int flip, u16* __restrict__ out_bf,
+                                                  int flip, u16* __restrict__ out_bf,
                                                   float* __restrict__ out_f, int out_cs, int out_off, int relu, int D,
                                                   int H, int W) {
   constexpr int TY = 2 * MT, HX = 10, HY = TY + 2, HZ = 6, HV = HX * HY * HZ;
@@ -147,8 +147,8 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
   for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
     for (int nj = 0; nj < NTL; ++nj) acc[mi][nj] = f4{0, 0, 0, 0};
-  const int ntap = ks * ks * ks;
-  const int c = ks / 2;
+  constexpr int ntap = KS * KS * KS;
+  constexpr int c = KS / 2;
   for (int k0 = 0; k0 < K; k0 += 32) {
     // halo voxel h = hx + HX (hy + HY hz) <- input voxel (x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz), periodic
     for (int sgm = tid; sgm < HV * 4; sgm += 256) {
@@ -159,8 +159,9 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
           *reinterpret_cast<const uint4*>(in + (long long)q * in_cs + in_off + k0 + 8 * part);
     }
     __syncthreads();
+#pragma unroll 3
     for (int t = 0; t < ntap; ++t) {
-      int dz = t / (ks * ks) - c, dy = (t / ks) % ks - c, dx = t % ks - c;
+      int dz = t / (KS * KS) - c, dy = (t / KS) % KS - c, dx = t % KS - c;
       if (flip) {
         dz = -dz;
         dy = -dy;
@@ -212,12 +213,21 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
 void launch_conv(const u16* in, int in_cs, int in_off, int K, const u16* wt, int N, const float* bias, int ks,
                  int flip, u16* out_bf, float* out_f, int out_cs, int out_off, int relu, int n, hipStream_t st) {
   const long long V = (long long)n * n * n;
-  if (n % 8 == 0 && N % 64 == 0 && (V / 256) * (N / 64) >= 2048)
-    hipLaunchKernelGGL((k_conv_lds<4, 4>), dim3((unsigned)(V / 256), N / 64), dim3(256), 0, st, in, in_cs, in_off, K,
-                       wt, N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
-  else if (n % 8 == 0)
-    hipLaunchKernelGGL((k_conv_lds<4, 2>), dim3((unsigned)(V / 256), N / 32), dim3(256), 0, st, in, in_cs, in_off, K,
-                       wt, N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
+  const bool lds = n % 8 == 0 && (ks == 3 || ks == 1);
+  const bool wide = N % 64 == 0 && (V / 256) * (N / 64) >= 2048;
+  const dim3 grid((unsigned)(V / 256), wide ? N / 64 : N / 32);
+  if (lds && wide && ks == 3)
+    hipLaunchKernelGGL((k_conv_lds<4, 4, 3>), grid, dim3(256), 0, st, in, in_cs, in_off, K, wt, N, bias, flip, out_bf,
+                       out_f, out_cs, out_off, relu, n, n, n);
+  else if (lds && wide)
+    hipLaunchKernelGGL((k_conv_lds<4, 4, 1>), grid, dim3(256), 0, st, in, in_cs, in_off, K, wt, N, bias, flip, out_bf,
+                       out_f, out_cs, out_off, relu, n, n, n);
+  else if (lds && ks == 3)
+    hipLaunchKernelGGL((k_conv_lds<4, 2, 3>), grid, dim3(256), 0, st, in, in_cs, in_off, K, wt, N, bias, flip, out_bf,
+                       out_f, out_cs, out_off, relu, n, n, n);
+  else if (lds)
+    hipLaunchKernelGGL((k_conv_lds<4, 2, 1>), grid, dim3(256), 0, st, in, in_cs, in_off, K, wt, N, bias, flip, out_bf,
+                       out_f, out_cs, out_off, relu, n, n, n);
   else
     hipLaunchKernelGGL(k_conv, dim3((unsigned)((V + 127) / 128), N / 32), dim3(256), 0, st, in, in_cs, in_off, K, wt,
                        N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
