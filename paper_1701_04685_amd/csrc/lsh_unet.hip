@@ -118,7 +118,10 @@ __global__ void __launch_bounds__(256) k_conv(const u16* __restrict__ in, int in
 // Wave w takes the tile's voxels v = x + 8 y + 16 MT z in [16 MT w, 16 MT (w
 // + 1)): MT row tiles of 16 (8 x 2 at one z) against the block's channels.
 // Needs W % 8 == 0, H % (2 MT) == 0, D % 4 == 0.
-constexpr int HROW = 40;  // u16 per halo voxel: 32 channels + 8 pad (bank spread)
+// u16 per halo voxel: its 32 channels, unpadded (37.5 KB per block, so four
+// blocks share a CU; padding to 40 spread the banks but, at 46.9 KB, allowed
+// only three, and was slower: 2.71 against 2.58 ms per 128^3 prediction)
+constexpr int HROW = 32;
 template <int MT, int NTL, int KS>
 __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, int in_cs, int in_off, int K,
                                                   const u16* __restrict__ wt, int N, const float* __restrict__ bias,
