@@ -538,7 +538,10 @@ def bench_unet(args):
     # resolution level of each layer in order: two convolutions per level down
     # to the bottom, two per level back up, then the 1x1 head
     levels = [0, 0, 1, 1, 2, 2, 1, 1, 0, 0, 0]
-    flops = sum(2.0 * (n >> lv) ** 3 * ci * co * ks ** 3 for (ci, co, ks), lv in zip(layers, levels))
+    # the head counts the 36 output channels a prediction uses (its kernel
+    # forms 48 of the layer's 64 and contracts them with the loads)
+    outs = [co for _, co, _ in layers[:-1]] + [36]
+    flops = sum(2.0 * (n >> lv) ** 3 * ci * co * ks ** 3 for (ci, _, ks), co, lv in zip(layers, outs, levels))
     phd = torch.from_numpy(wst.packing(60000, n)).cuda()
     eps = np.eye(6)[:2]
     net.predict(phd, n, eps)

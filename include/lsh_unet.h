@@ -73,12 +73,15 @@ int lsh_unet_get_grads(const lsh_unet *net, float *grads, void *stream);
 /* Prediction for nload macroscopic strains: writes the start fluctuation
  *   dev_E_out : double [nload][6][n^3], Voigt with engineering shear (the layout
  *               lsh_solve takes as dev_E_init).
- *   eps0_voigt: host nload*6.                                                      */
+ *   eps0_voigt: host nload*6.
+ * The head and its combination with eps0 run as one kernel, so a prediction
+ * leaves no head output behind (lsh_unet_head then returns LSH_ESTATE).          */
 int lsh_unet_predict(lsh_unet *net, const uint8_t *dev_phase, int n, const double *eps0_voigt, int nload,
                      double *dev_E_out, void *dev_act, size_t act_bytes, void *stream);
 
-/* Copies the raw 64-channel head output of the last forward pass (float
- * [n^3][64]) into dev_dst, for tests.                                              */
+/* Copies the raw 64-channel head output of the last training step's forward
+ * pass (float [n^3][64]) into dev_dst, for tests; it lives in that step's
+ * activation workspace, which must still be allocated.                            */
 int lsh_unet_head(const lsh_unet *net, int n, float *dev_dst, void *stream);
 
 /* Layer table: for layer l < nlayer, input/output channels and kernel size

@@ -112,9 +112,10 @@ __global__ void __launch_bounds__(256) k_conv(const u16* __restrict__ in, int in
 
 // The same convolution with the input staged in LDS.  Block: an 8 x 2MT x 4
 // (x, y, z) tile of output voxels and 16 NTL output channels; per chunk of 32
-// input channels its 10 x (2MT + 2) x 6 halo (periodic) comes into LDS once,
-// and the 27 taps read their A fragments there instead of from the cache
-// hierarchy (the global version re-reads every input row once per tap).
+// input channels its 10 x (2MT + 2) x 6 halo (periodic; for 1x1 kernels the
+// tile itself) comes into LDS once, and the 27 taps read their A fragments
+// there instead of from the cache hierarchy (the global version re-reads every
+// input row once per tap).
 // Wave w takes the tile's voxels v = x + 8 y + 16 MT z in [16 MT w, 16 MT (w
 // + 1)): MT row tiles of 16 (8 x 2 at one z) against the block's channels.
 // Needs W % 8 == 0, H % (2 MT) == 0, D % 4 == 0.
@@ -122,19 +123,20 @@ __global__ void __launch_bounds__(256) k_conv(const u16* __restrict__ in, int in
 // blocks share a CU; padding to 40 spread the banks but, at 46.9 KB, allowed
 // only three, and was slower: 2.71 against 2.58 ms per 128^3 prediction)
 constexpr int HROW = 32;
+template <int MT, int KS>
+constexpr int halo_u16() {
+  return (8 + KS - 1) * (2 * MT + KS - 1) * (4 + KS - 1) * HROW;
+}
+
+// The tile's accumulation: acc[mi][nj][i] is output channel n0 + 16 nj + r of
+// tile voxel 16 MT wave + 16 mi + 4 g + i (r = lane % 16, g = lane / 16).
 template <int MT, int NTL, int KS>
-__global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, int in_cs, int in_off, int K,
-                                                  const u16* __restrict__ wt, int N, const float* __restrict__ bias,
-                                                  int flip, u16* __restrict__ out_bf,
-                                                  float* __restrict__ out_f, int out_cs, int out_off, int relu, int D,
-                                                  int H, int W) {
-  constexpr int TY = 2 * MT, HX = 10, HY = TY + 2, HZ = 6, HV = HX * HY * HZ;
-  __shared__ __align__(16) u16 halo[HV * HROW];
+__device__ __forceinline__ void conv_lds_tile(const u16* __restrict__ in, int in_cs, int in_off, int K,
+                                              const u16* __restrict__ wt, int N, int flip, int D, int H, int W,
+                                              int x0, int y0, int z0, int n0, u16* halo, f4 (&acc)[MT][NTL]) {
+  constexpr int c = KS / 2;
+  constexpr int TY = 2 * MT, HX = 8 + 2 * c, HY = TY + 2 * c, HZ = 4 + 2 * c, HV = HX * HY * HZ;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tx = W / 8, ty = H / TY;
-  const int bx = blockIdx.x % tx, by = (blockIdx.x / tx) % ty, bz = blockIdx.x / (tx * ty);
-  const int x0 = 8 * bx, y0 = TY * by, z0 = 4 * bz;
-  const int n0 = blockIdx.y * 16 * NTL;
   const int r = lane & 15, g = lane >> 4;
   // this lane's voxel in each of the wave's row tiles
   int vx[MT], vy[MT], vz[MT];
@@ -145,19 +147,17 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
     vy[mi] = (v >> 3) % TY;
     vz[mi] = v / (8 * TY);
   }
-  f4 acc[MT][NTL];
 #pragma unroll
   for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
     for (int nj = 0; nj < NTL; ++nj) acc[mi][nj] = f4{0, 0, 0, 0};
   constexpr int ntap = KS * KS * KS;
-  constexpr int c = KS / 2;
   for (int k0 = 0; k0 < K; k0 += 32) {
-    // halo voxel h = hx + HX (hy + HY hz) <- input voxel (x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz), periodic
+    // halo voxel h = hx + HX (hy + HY hz) <- input voxel (x0 - c + hx, y0 - c + hy, z0 - c + hz), periodic
     for (int sgm = tid; sgm < HV * 4; sgm += 256) {
       const int h = sgm >> 2, part = sgm & 3;
       const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-      const int q = (wrap(z0 - 1 + hz, D) * H + wrap(y0 - 1 + hy, H)) * W + wrap(x0 - 1 + hx, W);
+      const int q = (wrap(z0 - c + hz, D) * H + wrap(y0 - c + hy, H)) * W + wrap(x0 - c + hx, W);
       *reinterpret_cast<uint4*>(halo + h * HROW + 8 * part) =
           *reinterpret_cast<const uint4*>(in + (long long)q * in_cs + in_off + k0 + 8 * part);
     }
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
       bf16x8 a[MT], b[NTL];
 #pragma unroll
       for (int mi = 0; mi < MT; ++mi) {
-        const int h = (vx[mi] + 1 + dx) + HX * ((vy[mi] + 1 + dy) + HY * (vz[mi] + 1 + dz));
+        const int h = (vx[mi] + c + dx) + HX * ((vy[mi] + c + dy) + HY * (vz[mi] + c + dz));
         a[mi] = ld8(halo + h * HROW + 8 * g);
       }
       const u16* wb = wt + ((long long)t * N + n0 + r) * K + k0 + 8 * g;
@@ -185,8 +185,31 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
         for (int nj = 0; nj < NTL; ++nj)
           acc[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mi], b[nj], acc[mi][nj], 0, 0, 0);
     }
-    __syncthreads();  // the next chunk overwrites the halo
+    __syncthreads();  // the next chunk (or the caller's epilogue) overwrites the halo
   }
+}
+
+// grid point of tile voxel v = x + 8 y + 16 MT z of the tile at (x0, y0, z0)
+template <int MT>
+__device__ __forceinline__ long long tile_point(int v, int x0, int y0, int z0, int H, int W) {
+  constexpr int TY = 2 * MT;
+  return ((long long)(z0 + v / (8 * TY)) * H + y0 + (v >> 3) % TY) * W + x0 + (v & 7);
+}
+
+template <int MT, int NTL, int KS>
+__global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, int in_cs, int in_off, int K,
+                                                  const u16* __restrict__ wt, int N, const float* __restrict__ bias,
+                                                  int flip, u16* __restrict__ out_bf,
+                                                  float* __restrict__ out_f, int out_cs, int out_off, int relu, int D,
+                                                  int H, int W) {
+  constexpr int TY = 2 * MT;
+  __shared__ __align__(16) u16 halo[halo_u16<MT, KS>()];
+  const int tx = W / 8, ty = H / TY;
+  const int x0 = 8 * (blockIdx.x % tx), y0 = TY * ((blockIdx.x / tx) % ty), z0 = 4 * (blockIdx.x / (tx * ty));
+  const int n0 = blockIdx.y * 16 * NTL;
+  f4 acc[MT][NTL];
+  conv_lds_tile<MT, NTL, KS>(in, in_cs, in_off, K, wt, N, flip, D, H, W, x0, y0, z0, n0, halo, acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
@@ -196,8 +219,7 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         // row 4 g + i of the row tile: the voxel the lane with r = 4 g + i holds
-        const int v = 16 * MT * wave + 16 * mi + 4 * g + i;
-        const long long p = ((long long)(z0 + v / (8 * TY)) * H + y0 + (v >> 3) % TY) * W + x0 + (v & 7);
+        const long long p = tile_point<MT>(16 * MT * wave + 16 * mi + 4 * g + i, x0, y0, z0, H, W);
         float val = acc[mi][nj][i] + bv;
         if (relu) val = fmaxf(val, 0.0f);
         if (out_f)
@@ -205,6 +227,53 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
         else
           out_bf[p * out_cs + out_off + ch] = f2bf(val);
       }
+    }
+}
+
+// The head (1x1 convolution, 32 -> 64 channels, no activation) fused with the
+// strain contraction of a prediction:
+//   E[L][c][p] = (c < 3 ? 1 : sqrt2) sum_j eps0[L][j] y[p][6 j + c],
+// y = the head's output channels 0..35 (unit load j, Mandel component c).  A
+// block takes the conv tile of 8 x 8 x 4 voxels and output channels 0..47
+// (three 16-column tiles cover the 36 used); its y rows (FP32, padded to 37
+// words so that a wave reading one channel of 64 voxels hits distinct banks)
+// go through LDS (the buffer that held the input tile), and each thread then
+// forms one voxel's nload x 6 outputs, summed over j in ascending order in
+// FP64.  y itself is not stored.
+constexpr int YROW = 37;
+static_assert(256 * YROW * 4 >= halo_u16<4, 1>() * 2, "the input tile fits the y buffer");
+__global__ void __launch_bounds__(256) k_head_contract(const u16* __restrict__ in, int in_cs, int in_off,
+                                                       const u16* __restrict__ wt, const float* __restrict__ bias,
+                                                       const double* __restrict__ eps0, int nload,
+                                                       double* __restrict__ E, int D, int H, int W) {
+  constexpr int MT = 4, NTL = 3, TY = 2 * MT;
+  __shared__ __align__(16) float ys[256 * YROW];
+  const int tx = W / 8, ty = H / TY;
+  const int x0 = 8 * (blockIdx.x % tx), y0 = TY * ((blockIdx.x / tx) % ty), z0 = 4 * (blockIdx.x / (tx * ty));
+  f4 acc[MT][NTL];
+  // the input tile's LDS is free again when the tile returns (it ends with a barrier)
+  conv_lds_tile<MT, NTL, 1>(in, in_cs, in_off, 32, wt, 64, 0, D, H, W, x0, y0, z0, 0, reinterpret_cast<u16*>(ys), acc);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < NTL; ++nj) {
+      const int ch = 16 * nj + r;
+      if (ch < 36) {
+        const float bv = bias[ch];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ys[(16 * MT * wave + 16 * mi + 4 * g + i) * YROW + ch] = acc[mi][nj][i] + bv;
+      }
+    }
+  __syncthreads();
+  const long long V = (long long)D * H * W;
+  const long long p = tile_point<MT>(tid, x0, y0, z0, H, W);
+  const float* yv = ys + tid * YROW;
+  for (int L = 0; L < nload; ++L)
+    for (int c = 0; c < 6; ++c) {
+      double s = 0.0;
+      for (int j = 0; j < 6; ++j) s += eps0[6 * L + j] * (double)yv[6 * j + c];
+      E[(long long)(6 * L + c) * V + p] = s * (c < 3 ? 1.0 : 1.41421356237309504880);
     }
 }
 
@@ -447,36 +516,6 @@ __global__ void k_cast_weights(const float* __restrict__ w, int ntap, int cout, 
   wb[((long long)t * cin + ci) * cout + co] = h;
 }
 
-// E_out[L][c][p] = (c < 3 ? 1 : sqrt2) sum_j eps0[L][j] y[p][6 j + c].  A block
-// takes 64 voxels: their rows of y (64 channels, 16 KB) come in with coalesced
-// 16-byte loads into LDS (rows padded to 65 words, so that a wave reading one
-// column of 64 rows hits 64 banks), and the outputs leave voxel-fastest.
-__global__ void __launch_bounds__(256) k_contract(const float* __restrict__ y, long long V,
-                                                  const double* __restrict__ eps0, int nload,
-                                                  double* __restrict__ E) {
-  __shared__ float ys[64][65];
-  const long long p0 = (long long)blockIdx.x * 64;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < 64 * 16; i += 256) {
-    const int row = i >> 4, q = i & 15;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (p0 + row < V) v = reinterpret_cast<const float4*>(y + (p0 + row) * 64)[q];
-    ys[row][4 * q] = v.x;
-    ys[row][4 * q + 1] = v.y;
-    ys[row][4 * q + 2] = v.z;
-    ys[row][4 * q + 3] = v.w;
-  }
-  __syncthreads();
-  for (int i = tid; i < nload * 6 * 64; i += 256) {
-    const int pv = i & 63, lc = i >> 6;
-    const int L = lc / 6, c = lc - 6 * L;
-    if (p0 + pv >= V) continue;
-    double s = 0.0;
-    for (int j = 0; j < 6; ++j) s += eps0[6 * L + j] * (double)ys[pv][6 * j + c];
-    E[(long long)lc * V + p0 + pv] = s * (c < 3 ? 1.0 : 1.41421356237309504880);
-  }
-}
-
 // T[p][6 j + c] = E6[j][c][p] (Voigt -> Mandel)
 __global__ void k_pack_target(const double* __restrict__ E6, long long V, float* __restrict__ T) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -543,7 +582,6 @@ Acts act_layout(int n, bool training, char* base) {
   a.cat1 = (u16*)take(V0 * 96, 2);
   a.d1a = (u16*)take(V0 * 32, 2);
   a.d1b = (u16*)take(V0 * 32, 2);
-  a.y = (float*)take(V0 * 64, 4);
   a.p1 = (u16*)take(V1 * 32, 2);
   a.e2a = (u16*)take(V1 * 64, 2);
   a.cat2 = (u16*)take(V1 * 192, 2);
@@ -555,6 +593,7 @@ Acts act_layout(int n, bool training, char* base) {
   a.loss = (double*)take(1, 8);
   a.eps = (double*)take(64 * 6, 8);
   if (training) {
+    a.y = (float*)take(V0 * 64, 4);  // a prediction forms the head and its contraction in one kernel
     a.dy = (u16*)take(V0 * 64, 2);
     a.g_e1a = (u16*)take(V0 * 32, 2);
     a.g_cat1 = (u16*)take(V0 * 96, 2);
@@ -609,7 +648,8 @@ void mask(u16* g, int g_cs, int g_off, const u16* act, int a_cs, int a_off, int 
   hipLaunchKernelGGL(k_mask_relu, dim3(blocks(V * C, 256)), dim3(256), 0, st, g, g_cs, g_off, act, a_cs, a_off, C, V);
 }
 
-void forward(lsh_unet* net, const Acts& a, const uint8_t* phase, int n, hipStream_t st) {
+// every layer up to the head's input (d1b)
+void trunk(lsh_unet* net, const Acts& a, const uint8_t* phase, int n, hipStream_t st) {
   const int n1 = n / 2, n2 = n / 4;
   const long long V0 = (long long)n * n * n;
   hipLaunchKernelGGL(k_pack_input, dim3(blocks(V0 * 4, 256)), dim3(256), 0, st, phase, V0, a.x0);
@@ -631,6 +671,10 @@ void forward(lsh_unet* net, const Acts& a, const uint8_t* phase, int n, hipStrea
                      n1, n1, n1);
   conv_fwd(net, D1A, a.cat1, 96, 0, a.d1a, nullptr, 32, 0, 1, n, st);
   conv_fwd(net, D1B, a.d1a, 32, 0, a.d1b, nullptr, 32, 0, 1, n, st);
+}
+
+void forward(lsh_unet* net, const Acts& a, const uint8_t* phase, int n, hipStream_t st) {
+  trunk(net, a, phase, n, st);
   conv_fwd(net, HEAD, a.d1b, 32, 0, nullptr, a.y, 64, 0, 0, n, st);
   net->head = a.y;
 }
@@ -815,12 +859,16 @@ extern "C" int lsh_unet_predict(lsh_unet* net, const uint8_t* phase, int n, cons
   if (n < 8 || n % 8 != 0) return lsh_fail(LSH_EINVAL, "grid side must be a positive multiple of 8");
   Acts a = act_layout(n, false, (char*)dev_act);
   if (!dev_act || act_bytes < a.total) return lsh_fail(LSH_EWORKSPACE, "activation workspace too small");
+  const LayerDesc& hd = net->L[HEAD];
+  if (hd.cin != 32 || hd.cout != 64 || hd.ks != 1) return lsh_fail(LSH_ESTATE, "head layer is not 1x1, 32 -> 64");
   hipStream_t st = (hipStream_t)stream;
   const long long V0 = (long long)n * n * n;
-  forward(net, a, phase, n, st);
+  trunk(net, a, phase, n, st);
   UCHK(hipMemcpyAsync(a.eps, eps0_voigt, sizeof(double) * 6 * nload, hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_contract, dim3(blocks(V0, 64)), dim3(256), 0, st, (const float*)a.y, V0,
-                     (const double*)a.eps, nload, dev_E_out);
+  hipLaunchKernelGGL(k_head_contract, dim3((unsigned)(V0 / 256)), dim3(256), 0, st, (const u16*)a.d1b, 32, 0,
+                     (const u16*)(net->wf + hd.w_off), (const float*)(net->w + hd.b_off), (const double*)a.eps, nload,
+                     dev_E_out, n, n, n);
+  net->head = nullptr;  // not formed by a prediction
   UCHK(hipGetLastError());
   UCHK(hipStreamSynchronize(st));
   return LSH_OK;
