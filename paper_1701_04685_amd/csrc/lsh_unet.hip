@@ -128,10 +128,29 @@ constexpr int halo_u16() {
   return (8 + KS - 1) * (2 * MT + KS - 1) * (4 + KS - 1) * HROW;
 }
 
+// Where an LDS-staged convolution reads its input.  Channel k of voxel p is
+// in[p cs + off + k], except that
+//   phase != null: the network's packed input (channel 0 the phase
+//                  indicator 0/1, channels 1..31 zero), formed from the phase
+//                  map as it is staged;
+//   k < up_C:      the channel comes from the grid of half the side at p's
+//                  parent, up[parent up_cs + k] (nearest upsampling, read in
+//                  place instead of being copied out first).
+struct ConvIn {
+  const u16* in;
+  int cs, off;
+  const u16* up;
+  int up_cs, up_C;
+  const uint8_t* phase;
+};
+__host__ __device__ inline ConvIn plain_in(const u16* in, int cs, int off) {
+  return ConvIn{in, cs, off, nullptr, 0, 0, nullptr};
+}
+
 // The tile's accumulation: acc[mi][nj][i] is output channel n0 + 16 nj + r of
 // tile voxel 16 MT wave + 16 mi + 4 g + i (r = lane % 16, g = lane / 16).
 template <int MT, int NTL, int KS>
-__device__ __forceinline__ void conv_lds_tile(const u16* __restrict__ in, int in_cs, int in_off, int K,
+__device__ __forceinline__ void conv_lds_tile(const ConvIn& src, int K,
                                               const u16* __restrict__ wt, int N, int flip, int D, int H, int W,
                                               int x0, int y0, int z0, int n0, u16* halo, f4 (&acc)[MT][NTL]) {
   constexpr int c = KS / 2;
@@ -157,9 +176,18 @@ __device__ __forceinline__ void conv_lds_tile(const u16* __restrict__ in, int in
     for (int sgm = tid; sgm < HV * 4; sgm += 256) {
       const int h = sgm >> 2, part = sgm & 3;
       const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-      const int q = (wrap(z0 - c + hz, D) * H + wrap(y0 - c + hy, H)) * W + wrap(x0 - c + hx, W);
-      *reinterpret_cast<uint4*>(halo + h * HROW + 8 * part) =
-          *reinterpret_cast<const uint4*>(in + (long long)q * in_cs + in_off + k0 + 8 * part);
+      const int zf = wrap(z0 - c + hz, D), yf = wrap(y0 - c + hy, H), xf = wrap(x0 - c + hx, W);
+      const int q = (zf * H + yf) * W + xf;
+      uint4 val;
+      if (src.phase) {
+        val = uint4{part == 0 && src.phase[q] ? 0x3F80u : 0u, 0u, 0u, 0u};  // bf16 1.0 in channel 0
+      } else if (k0 < src.up_C) {
+        const int qc = ((zf >> 1) * (H >> 1) + (yf >> 1)) * (W >> 1) + (xf >> 1);
+        val = *reinterpret_cast<const uint4*>(src.up + (long long)qc * src.up_cs + k0 + 8 * part);
+      } else {
+        val = *reinterpret_cast<const uint4*>(src.in + (long long)q * src.cs + src.off + k0 + 8 * part);
+      }
+      *reinterpret_cast<uint4*>(halo + h * HROW + 8 * part) = val;
     }
     __syncthreads();
 #pragma unroll 3
@@ -197,7 +225,7 @@ __device__ __forceinline__ long long tile_point(int v, int x0, int y0, int z0, i
 }
 
 template <int MT, int NTL, int KS>
-__global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, int in_cs, int in_off, int K,
+__global__ void __launch_bounds__(256) k_conv_lds(ConvIn src, int K,
                                                   const u16* __restrict__ wt, int N, const float* __restrict__ bias,
                                                   int flip, u16* __restrict__ out_bf,
                                                   float* __restrict__ out_f, int out_cs, int out_off, int relu, int D,
@@ -208,7 +236,7 @@ __global__ void __launch_bounds__(256) k_conv_lds(const u16* __restrict__ in, in
   const int x0 = 8 * (blockIdx.x % tx), y0 = TY * ((blockIdx.x / tx) % ty), z0 = 4 * (blockIdx.x / (tx * ty));
   const int n0 = blockIdx.y * 16 * NTL;
   f4 acc[MT][NTL];
-  conv_lds_tile<MT, NTL, KS>(in, in_cs, in_off, K, wt, N, flip, D, H, W, x0, y0, z0, n0, halo, acc);
+  conv_lds_tile<MT, NTL, KS>(src, K, wt, N, flip, D, H, W, x0, y0, z0, n0, halo, acc);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int mi = 0; mi < MT; ++mi)
@@ -252,7 +280,8 @@ __global__ void __launch_bounds__(256) k_head_contract(const u16* __restrict__ i
   const int x0 = 8 * (blockIdx.x % tx), y0 = TY * ((blockIdx.x / tx) % ty), z0 = 4 * (blockIdx.x / (tx * ty));
   f4 acc[MT][NTL];
   // the input tile's LDS is free again when the tile returns (it ends with a barrier)
-  conv_lds_tile<MT, NTL, 1>(in, in_cs, in_off, 32, wt, 64, 0, D, H, W, x0, y0, z0, 0, reinterpret_cast<u16*>(ys), acc);
+  conv_lds_tile<MT, NTL, 1>(plain_in(in, in_cs, in_off), 32, wt, 64, 0, D, H, W, x0, y0, z0, 0,
+                            reinterpret_cast<u16*>(ys), acc);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int mi = 0; mi < MT; ++mi)
@@ -277,32 +306,35 @@ __global__ void __launch_bounds__(256) k_head_contract(const u16* __restrict__ i
     }
 }
 
-// Both convolutions behind one call: the LDS-staged one where the grid tiles
-// into its blocks (8 x 8 x 4 voxels; 64 output channels per block when N
-// allows and the layer still has 2048 blocks, so the halo is staged once for
-// them, else 32), the global one elsewhere (the coarsest levels of small
-// grids).
-void launch_conv(const u16* in, int in_cs, int in_off, int K, const u16* wt, int N, const float* bias, int ks,
-                 int flip, u16* out_bf, float* out_f, int out_cs, int out_off, int relu, int n, hipStream_t st) {
+// Whether a convolution on an n^3 grid with ks^3 taps runs LDS-staged (the
+// grid tiles into its 8 x 8 x 4 voxel blocks).
+bool lds_conv(int n, int ks) { return n % 8 == 0 && (ks == 3 || ks == 1); }
+
+// Both convolutions behind one call: the LDS-staged one where lds_conv holds
+// (64 output channels per block when N allows and the layer still has 2048
+// blocks, so the halo is staged once for them, else 32), the global one
+// elsewhere (the coarsest levels of small grids), which reads plain inputs only.
+void launch_conv(const ConvIn& src, int K, const u16* wt, int N, const float* bias, int ks, int flip, u16* out_bf,
+                 float* out_f, int out_cs, int out_off, int relu, int n, hipStream_t st) {
   const long long V = (long long)n * n * n;
-  const bool lds = n % 8 == 0 && (ks == 3 || ks == 1);
+  const bool lds = lds_conv(n, ks);
   const bool wide = N % 64 == 0 && (V / 256) * (N / 64) >= 2048;
   const dim3 grid((unsigned)(V / 256), wide ? N / 64 : N / 32);
   if (lds && wide && ks == 3)
-    hipLaunchKernelGGL((k_conv_lds<4, 4, 3>), grid, dim3(256), 0, st, in, in_cs, in_off, K, wt, N, bias, flip, out_bf,
-                       out_f, out_cs, out_off, relu, n, n, n);
+    hipLaunchKernelGGL((k_conv_lds<4, 4, 3>), grid, dim3(256), 0, st, src, K, wt, N, bias, flip, out_bf, out_f, out_cs,
+                       out_off, relu, n, n, n);
   else if (lds && wide)
-    hipLaunchKernelGGL((k_conv_lds<4, 4, 1>), grid, dim3(256), 0, st, in, in_cs, in_off, K, wt, N, bias, flip, out_bf,
-                       out_f, out_cs, out_off, relu, n, n, n);
+    hipLaunchKernelGGL((k_conv_lds<4, 4, 1>), grid, dim3(256), 0, st, src, K, wt, N, bias, flip, out_bf, out_f, out_cs,
+                       out_off, relu, n, n, n);
   else if (lds && ks == 3)
-    hipLaunchKernelGGL((k_conv_lds<4, 2, 3>), grid, dim3(256), 0, st, in, in_cs, in_off, K, wt, N, bias, flip, out_bf,
-                       out_f, out_cs, out_off, relu, n, n, n);
+    hipLaunchKernelGGL((k_conv_lds<4, 2, 3>), grid, dim3(256), 0, st, src, K, wt, N, bias, flip, out_bf, out_f, out_cs,
+                       out_off, relu, n, n, n);
   else if (lds)
-    hipLaunchKernelGGL((k_conv_lds<4, 2, 1>), grid, dim3(256), 0, st, in, in_cs, in_off, K, wt, N, bias, flip, out_bf,
-                       out_f, out_cs, out_off, relu, n, n, n);
+    hipLaunchKernelGGL((k_conv_lds<4, 2, 1>), grid, dim3(256), 0, st, src, K, wt, N, bias, flip, out_bf, out_f, out_cs,
+                       out_off, relu, n, n, n);
   else
-    hipLaunchKernelGGL(k_conv, dim3((unsigned)((V + 127) / 128), N / 32), dim3(256), 0, st, in, in_cs, in_off, K, wt,
-                       N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
+    hipLaunchKernelGGL(k_conv, dim3((unsigned)((V + 127) / 128), N / 32), dim3(256), 0, st, src.in, src.cs, src.off, K,
+                       wt, N, bias, ks, flip, out_bf, out_f, out_cs, out_off, relu, n, n, n);
 }
 
 // -------------------------------------------------------- weight gradient ---
@@ -619,12 +651,11 @@ Acts act_layout(int n, bool training, char* base) {
   } while (0)
 
 // forward convolution of layer l
-void conv_fwd(lsh_unet* net, int l, const u16* in, int in_cs, int in_off, u16* out_bf, float* out_f, int out_cs,
-              int out_off, int relu, int n, hipStream_t st) {
+void conv_fwd(lsh_unet* net, int l, const ConvIn& src, u16* out_bf, float* out_f, int out_cs, int out_off, int relu,
+              int n, hipStream_t st) {
   const LayerDesc& d = net->L[l];
-  const long long wofs = d.w_off;
-  launch_conv(in, in_cs, in_off, d.cin, (const u16*)(net->wf + wofs), d.cout, (const float*)(net->w + d.b_off), d.ks,
-              0, out_bf, out_f, out_cs, out_off, relu, n, st);
+  launch_conv(src, d.cin, (const u16*)(net->wf + d.w_off), d.cout, (const float*)(net->w + d.b_off), d.ks, 0, out_bf,
+              out_f, out_cs, out_off, relu, n, st);
 }
 
 // backward of layer l given dPre (already masked): weight/bias grads and (if din) input grads
@@ -639,8 +670,8 @@ void conv_bwd(lsh_unet* net, int l, const u16* in, int in_cs, int in_off, const 
   hipLaunchKernelGGL(k_bias_grad, dim3(std::min<long long>(blocks(V, 4), 512), blocks(d.cout, 64)), dim3(256), 0, st,
                      dpre, dp_cs, dp_off, d.cout, (int)V, net->g + d.b_off);
   if (din)
-    launch_conv(dpre, dp_cs, dp_off, d.cout, (const u16*)(net->wb + d.w_off), d.cin, (const float*)nullptr, d.ks, 1,
-                din, (float*)nullptr, di_cs, di_off, 0, n, st);
+    launch_conv(plain_in(dpre, dp_cs, dp_off), d.cout, (const u16*)(net->wb + d.w_off), d.cin, (const float*)nullptr,
+                d.ks, 1, din, (float*)nullptr, di_cs, di_off, 0, n, st);
 }
 
 void mask(u16* g, int g_cs, int g_off, const u16* act, int a_cs, int a_off, int C, int n, hipStream_t st) {
@@ -648,34 +679,52 @@ void mask(u16* g, int g_cs, int g_off, const u16* act, int a_cs, int a_off, int 
   hipLaunchKernelGGL(k_mask_relu, dim3(blocks(V * C, 256)), dim3(256), 0, st, g, g_cs, g_off, act, a_cs, a_off, C, V);
 }
 
-// every layer up to the head's input (d1b)
-void trunk(lsh_unet* net, const Acts& a, const uint8_t* phase, int n, hipStream_t st) {
+// every layer up to the head's input (d1b).  in_place: the first layer forms
+// its packed input from the phase map and the decoder's first convolutions
+// read the upsampled channels from the coarser grid as they stage their
+// halos, where those convolutions run LDS-staged (a prediction; training
+// keeps the packed input and the concatenations, which its weight gradients
+// read).
+void trunk(lsh_unet* net, const Acts& a, const uint8_t* phase, int n, bool in_place, hipStream_t st) {
   const int n1 = n / 2, n2 = n / 4;
   const long long V0 = (long long)n * n * n;
-  hipLaunchKernelGGL(k_pack_input, dim3(blocks(V0 * 4, 256)), dim3(256), 0, st, phase, V0, a.x0);
-  conv_fwd(net, E1A, a.x0, 32, 0, a.e1a, nullptr, 32, 0, 1, n, st);
-  conv_fwd(net, E1B, a.e1a, 32, 0, a.cat1, nullptr, 96, 64, 1, n, st);
+  const bool f0 = in_place && lds_conv(n, 3), f1 = in_place && lds_conv(n1, 3);
+  if (f0) {
+    conv_fwd(net, E1A, ConvIn{nullptr, 0, 0, nullptr, 0, 0, phase}, a.e1a, nullptr, 32, 0, 1, n, st);
+  } else {
+    hipLaunchKernelGGL(k_pack_input, dim3(blocks(V0 * 4, 256)), dim3(256), 0, st, phase, V0, a.x0);
+    conv_fwd(net, E1A, plain_in(a.x0, 32, 0), a.e1a, nullptr, 32, 0, 1, n, st);
+  }
+  conv_fwd(net, E1B, plain_in(a.e1a, 32, 0), a.cat1, nullptr, 96, 64, 1, n, st);
   hipLaunchKernelGGL(k_pool, dim3(blocks((long long)n1 * n1 * n1 * 4, 256)), dim3(256), 0, st, (const u16*)a.cat1, 96,
                      64, a.p1, 32, 0, 32, n, n, n);
-  conv_fwd(net, E2A, a.p1, 32, 0, a.e2a, nullptr, 64, 0, 1, n1, st);
-  conv_fwd(net, E2B, a.e2a, 64, 0, a.cat2, nullptr, 192, 128, 1, n1, st);
+  conv_fwd(net, E2A, plain_in(a.p1, 32, 0), a.e2a, nullptr, 64, 0, 1, n1, st);
+  conv_fwd(net, E2B, plain_in(a.e2a, 64, 0), a.cat2, nullptr, 192, 128, 1, n1, st);
   hipLaunchKernelGGL(k_pool, dim3(blocks((long long)n2 * n2 * n2 * 8, 256)), dim3(256), 0, st, (const u16*)a.cat2,
                      192, 128, a.p2, 64, 0, 64, n1, n1, n1);
-  conv_fwd(net, E3A, a.p2, 64, 0, a.e3a, nullptr, 128, 0, 1, n2, st);
-  conv_fwd(net, E3B, a.e3a, 128, 0, a.e3b, nullptr, 128, 0, 1, n2, st);
-  hipLaunchKernelGGL(k_up, dim3(blocks((long long)n1 * n1 * n1 * 16, 256)), dim3(256), 0, st, (const u16*)a.e3b, 128,
-                     0, a.cat2, 192, 0, 128, n2, n2, n2);
-  conv_fwd(net, D2A, a.cat2, 192, 0, a.d2a, nullptr, 64, 0, 1, n1, st);
-  conv_fwd(net, D2B, a.d2a, 64, 0, a.d2b, nullptr, 64, 0, 1, n1, st);
-  hipLaunchKernelGGL(k_up, dim3(blocks(V0 * 8, 256)), dim3(256), 0, st, (const u16*)a.d2b, 64, 0, a.cat1, 96, 0, 64,
-                     n1, n1, n1);
-  conv_fwd(net, D1A, a.cat1, 96, 0, a.d1a, nullptr, 32, 0, 1, n, st);
-  conv_fwd(net, D1B, a.d1a, 32, 0, a.d1b, nullptr, 32, 0, 1, n, st);
+  conv_fwd(net, E3A, plain_in(a.p2, 64, 0), a.e3a, nullptr, 128, 0, 1, n2, st);
+  conv_fwd(net, E3B, plain_in(a.e3a, 128, 0), a.e3b, nullptr, 128, 0, 1, n2, st);
+  if (f1) {
+    conv_fwd(net, D2A, ConvIn{a.cat2, 192, 0, a.e3b, 128, 128, nullptr}, a.d2a, nullptr, 64, 0, 1, n1, st);
+  } else {
+    hipLaunchKernelGGL(k_up, dim3(blocks((long long)n1 * n1 * n1 * 16, 256)), dim3(256), 0, st, (const u16*)a.e3b,
+                       128, 0, a.cat2, 192, 0, 128, n2, n2, n2);
+    conv_fwd(net, D2A, plain_in(a.cat2, 192, 0), a.d2a, nullptr, 64, 0, 1, n1, st);
+  }
+  conv_fwd(net, D2B, plain_in(a.d2a, 64, 0), a.d2b, nullptr, 64, 0, 1, n1, st);
+  if (f0) {
+    conv_fwd(net, D1A, ConvIn{a.cat1, 96, 0, a.d2b, 64, 64, nullptr}, a.d1a, nullptr, 32, 0, 1, n, st);
+  } else {
+    hipLaunchKernelGGL(k_up, dim3(blocks(V0 * 8, 256)), dim3(256), 0, st, (const u16*)a.d2b, 64, 0, a.cat1, 96, 0, 64,
+                       n1, n1, n1);
+    conv_fwd(net, D1A, plain_in(a.cat1, 96, 0), a.d1a, nullptr, 32, 0, 1, n, st);
+  }
+  conv_fwd(net, D1B, plain_in(a.d1a, 32, 0), a.d1b, nullptr, 32, 0, 1, n, st);
 }
 
 void forward(lsh_unet* net, const Acts& a, const uint8_t* phase, int n, hipStream_t st) {
-  trunk(net, a, phase, n, st);
-  conv_fwd(net, HEAD, a.d1b, 32, 0, nullptr, a.y, 64, 0, 0, n, st);
+  trunk(net, a, phase, n, false, st);
+  conv_fwd(net, HEAD, plain_in(a.d1b, 32, 0), nullptr, a.y, 64, 0, 0, n, st);
   net->head = a.y;
 }
 
@@ -863,7 +912,7 @@ extern "C" int lsh_unet_predict(lsh_unet* net, const uint8_t* phase, int n, cons
   if (hd.cin != 32 || hd.cout != 64 || hd.ks != 1) return lsh_fail(LSH_ESTATE, "head layer is not 1x1, 32 -> 64");
   hipStream_t st = (hipStream_t)stream;
   const long long V0 = (long long)n * n * n;
-  trunk(net, a, phase, n, st);
+  trunk(net, a, phase, n, true, st);
   UCHK(hipMemcpyAsync(a.eps, eps0_voigt, sizeof(double) * 6 * nload, hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_head_contract, dim3((unsigned)(V0 / 256)), dim3(256), 0, st, (const u16*)a.d1b, 32, 0,
                      (const u16*)(net->wf + hd.w_off), (const float*)(net->w + hd.b_off), (const double*)a.eps, nload,
