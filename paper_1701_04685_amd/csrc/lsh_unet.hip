@@ -560,6 +560,19 @@ __global__ void k_pack_target(const double* __restrict__ E6, long long V, float*
 
 int blocks(long long n, int t) { return (int)((n + t - 1) / t); }
 
+// clears n 4-byte words (a kernel rather than a memset node, so that a caller
+// may capture the entry points that clear buffers into a HIP graph)
+__global__ void k_zero_words(unsigned* __restrict__ p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+void zero_words(void* p, size_t bytes, hipStream_t st) {
+  const long long n = (long long)(bytes / 4);
+  if (n > 0)
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<long long>(blocks(n, 256), 4096)), dim3(256), 0, st,
+                       (unsigned*)p, n);
+}
+
 }  // namespace
 
 // ================================================================ network ===
@@ -832,7 +845,8 @@ extern "C" int lsh_unet_bind(lsh_unet* net, void* dev, size_t bytes, const float
   net->wf = (u16*)(b + 4 * fb);
   net->wb = (u16*)(b + 4 * fb + lsh_align(sizeof(u16) * net->nw));
   UCHK(hipMemcpyAsync(net->w, params, sizeof(float) * net->nparam, hipMemcpyHostToDevice, st));
-  UCHK(hipMemsetAsync(net->g, 0, 3 * fb, st));
+  zero_words(net->g, 3 * fb, st);
+  UCHK(hipGetLastError());
   net->step = 0;
   int rc = refresh_bf16(net, st);
   if (rc) return rc;
@@ -858,7 +872,8 @@ extern "C" int lsh_unet_get_grads(const lsh_unet* net, float* grads, void* strea
 
 extern "C" int lsh_unet_zero_grad(lsh_unet* net, void* stream) {
   if (!net || !net->g) return lsh_fail(LSH_ESTATE, "network not bound");
-  UCHK(hipMemsetAsync(net->g, 0, sizeof(float) * net->nparam, (hipStream_t)stream));
+  zero_words(net->g, sizeof(float) * net->nparam, (hipStream_t)stream);
+  UCHK(hipGetLastError());
   return LSH_OK;
 }
 
@@ -878,7 +893,7 @@ extern "C" int lsh_unet_train_step(lsh_unet* net, const uint8_t* phase, const fl
   hipStream_t st = (hipStream_t)stream;
   const long long V0 = (long long)n * n * n;
   forward(net, a, phase, n, st);
-  UCHK(hipMemsetAsync(a.loss, 0, sizeof(double), st));
+  zero_words(a.loss, sizeof(double), st);
   // gradient slices that are accumulated into (pool backward) start from the
   // conv backward-data results; the concat buffers are fully overwritten
   hipLaunchKernelGGL(k_mse, dim3(blocks(V0 * 64, 256)), dim3(256), 0, st, (const float*)a.y, target, V0, a.dy, a.loss);
@@ -892,7 +907,7 @@ extern "C" int lsh_unet_train_step(lsh_unet* net, const uint8_t* phase, const fl
                        net->v, net->nparam, lr, b1c, b2c);
     int rc = refresh_bf16(net, st);
     if (rc) return rc;
-    UCHK(hipMemsetAsync(net->g, 0, sizeof(float) * net->nparam, st));
+    zero_words(net->g, sizeof(float) * net->nparam, st);
   }
   if (loss_out) {
     UCHK(hipMemcpyAsync(loss_out, a.loss, sizeof(double), hipMemcpyDeviceToHost, st));
