@@ -345,6 +345,17 @@ def bench_cfg5(args):
     zero start.  The evaluation solves run the FP64 path: the FP32 path's
     residual floor at this contrast lies near 1e-6, so some FP32 solves
     stall just above the tolerance whatever their start."""
+    m = measure_cfg5(args.train_packings, args.epochs, args.eval_packings, args.ablation_packings, sensitivity=True)
+    out = {"metric": METRIC, "value": m["value"], "unit": m["unit"],
+           "n_gpus": 1, "steps": m["steps"], "warmup": 1, "ms_per_step": m["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (U-Net) / f64 (solver)", "data": "synthetic",
+           "config": m["config"], "roofline": None, "cpu_baseline": None, "warm_start": m["warm_start"]}
+    print(json.dumps(out), flush=True)
+
+
+def measure_cfg5(train_packings, epochs, eval_packings, ablation_packings, sensitivity):
+    """The learned-start workload (see bench_cfg5); sensitivity adds the
+    iterations from the exact field scaled or with noise of a given RMS."""
     import torch
     from paper_1701_04685_amd import lsh, warmstart as wst
     import lsh_inputs as li
@@ -354,20 +365,20 @@ def bench_cfg5(args):
 
     n_train, n_eval = 64, 128
     t0 = time.perf_counter()
-    data, its = wst.make_dataset([50000 + i for i in range(args.train_packings)], n_train, 100.0, tol=1e-6, log=log)
+    data, its = wst.make_dataset([50000 + i for i in range(train_packings)], n_train, 100.0, tol=1e-6, log=log)
     t_data = time.perf_counter() - t0
     layers = lsh.UNet.layers()
     net = lsh.UNet(li.unet_init_params(1, layers))
     untrained = lsh.UNet(li.unet_init_params(1, layers))
     t0 = time.perf_counter()
-    losses = wst.train(net, data, n_train, args.epochs, lr=3e-4, lr_final=3e-5, log=log)
+    losses = wst.train(net, data, n_train, epochs, lr=3e-4, lr_final=3e-5, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del data
     rng = np.random.Generator(np.random.PCG64(7))
     ws = None
     rows = []
-    for k in range(args.eval_packings):
+    for k in range(eval_packings):
         ph = wst.packing(60000 + k, n_eval)
         P = wst.grid_pattern(n_eval, ph, 100.0, precision="fp64")
         if k == 0:
@@ -384,14 +395,14 @@ def bench_cfg5(args):
                    learned_it=b["iterations"], fell_back=b["fell_back"],
                    dsig=float(np.abs(a["sigma"] - b["sigma"]).max() / np.abs(a["sigma"]).max()),
                    converged=a["converged"] and b["converged"])
-        if k < args.ablation_packings:
+        if k < ablation_packings:
             c = wst.solve_learned(P, untrained, phd, n_eval, eps, workspace=ws, max_iter=20000)
             row["untrained_s"], row["untrained_it"] = c["seconds"], c["iterations"]
         rows.append(row)
         if not row["converged"]:
             log(f"eval packing {60000 + k}: not converged (plain {a['iterations']}, learned {b['iterations']})")
         if (k + 1) % 20 == 0:
-            log(f"eval {k + 1}/{args.eval_packings}")
+            log(f"eval {k + 1}/{eval_packings}")
     nconv = sum(not r["converged"] for r in rows)
     rows = [r for r in rows if r["converged"]]   # the ratio is taken over solves that reached tol
     ratio = np.array([r["plain_s"] / r["learned_s"] for r in rows])
@@ -408,52 +419,51 @@ def bench_cfg5(args):
     torch.cuda.synchronize()
     t_inf = (time.perf_counter() - t0) / 5
     abl = [r for r in rows if "untrained_s" in r]
-    # how the iteration count reacts to the start's error: exact field (FP64,
-    # tol 1e-9) scaled, or plus white noise of a given RMS, on the first packing
-    ph = wst.packing(60000, n_eval)
-    P = wst.grid_pattern(n_eval, ph, 100.0, precision="fp64")
-    eps = np.eye(6)[0].reshape(1, 6)
-    Es = P.solve(eps, tol=1e-9, max_iter=6000, return_E=True)["E"]
-    rms = Es.norm().item() / np.sqrt(Es.numel())
-    nrng = np.random.Generator(np.random.PCG64(8))
+    sens = None
+    if sensitivity:
+        # how the iteration count reacts to the start's error: exact field
+        # (FP64, tol 1e-9) scaled, or plus white noise of a given RMS, on the
+        # first packing
+        ph = wst.packing(60000, n_eval)
+        P = wst.grid_pattern(n_eval, ph, 100.0, precision="fp64")
+        eps = np.eye(6)[0].reshape(1, 6)
+        Es = P.solve(eps, tol=1e-9, max_iter=6000, return_E=True)["E"]
+        rms = Es.norm().item() / np.sqrt(Es.numel())
+        nrng = np.random.Generator(np.random.PCG64(8))
 
-    def iters_from(E0):
-        o = P.solve(eps, tol=1e-6, max_iter=20000, E_init=E0, workspace=ws, allow_notconverged=True)
-        return int(o["iterations"][0]) if o["converged"][0] else None
+        def iters_from(E0):
+            o = P.solve(eps, tol=1e-6, max_iter=20000, E_init=E0, workspace=ws, allow_notconverged=True)
+            return int(o["iterations"][0]) if o["converged"][0] else None
 
-    sens = {"zero": iters_from(None), "0.9*exact": iters_from((0.9 * Es).contiguous())}
-    for sg in (1e-1, 1e-2, 1e-3):
-        noise = torch.from_numpy(nrng.standard_normal(tuple(Es.shape)) * (sg * rms)).cuda()
-        sens[f"exact+{sg:g}rms_noise"] = iters_from((Es + noise).contiguous())
-    Ep = net.predict(torch.from_numpy(ph).cuda(), n_eval, eps)
-    sens["learned"] = iters_from(Ep)
-    sens["learned_start_rel_error"] = float(((Ep - Es).norm() / Es.norm()).item())
-    out = {"metric": METRIC, "value": float(np.median(ratio)), "unit": "x (t_plain / t_learned, median)",
-           "n_gpus": 1, "steps": len(rows), "warmup": 1,
-           "ms_per_step": float(np.median([r["learned_s"] for r in rows]) * 1e3), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (U-Net) / f64 (solver)", "data": "synthetic",
-           "config": {"workload": f"learned warm start: U-Net trained on {len(its) * 6} fields "
-                                  f"({len(its)} RSA packings 64^3, 6 unit loads), evaluated on {len(rows)} unseen "
-                                  f"128^3 packings, f=0.3, radii 6-12, contrast 100, Dirichlet, FP64 solver, tol 1e-6",
-                      "epochs": args.epochs, "train_steps": args.epochs * len(its)},
-           "roofline": None, "cpu_baseline": None,
-           "warm_start": {
-               "ratio_min_median_max": [float(ratio.min()), float(np.median(ratio)), float(ratio.max())],
-               "ratio_mean": float(ratio.mean()),
-               "plain_ms_median": float(np.median([r["plain_s"] for r in rows]) * 1e3),
-               "learned_ms_median": float(np.median([r["learned_s"] for r in rows]) * 1e3),
-               "plain_iterations_median": float(np.median(pit)), "learned_iterations_median": float(np.median(lit)),
-               "fallback_fraction": float(np.mean([r["fell_back"] for r in rows])),
-               "not_converged_packings": int(nconv),
-               "plain_iterations_min_max": [int(pit.min()), int(pit.max())],
-               "sigma_rel_diff_max": float(max(r["dsig"] for r in rows)),
-               "inference_ms_128": round(t_inf * 1e3, 3),
-               "untrained_ratio_median": (float(np.median([r["plain_s"] / r["untrained_s"] for r in abl]))
-                                          if abl else None),
-               "start_sensitivity_iterations": sens,
-               "dataset_s": round(t_data, 1), "dataset_iterations_median": float(np.median(its)),
-               "train_s": round(t_train, 1), "train_loss_first_last_epoch": [float(losses[0]), float(losses[-1])]}}
-    print(json.dumps(out), flush=True)
+        sens = {"zero": iters_from(None), "0.9*exact": iters_from((0.9 * Es).contiguous())}
+        for sg in (1e-1, 1e-2, 1e-3):
+            noise = torch.from_numpy(nrng.standard_normal(tuple(Es.shape)) * (sg * rms)).cuda()
+            sens[f"exact+{sg:g}rms_noise"] = iters_from((Es + noise).contiguous())
+        Ep = net.predict(torch.from_numpy(ph).cuda(), n_eval, eps)
+        sens["learned"] = iters_from(Ep)
+        sens["learned_start_rel_error"] = float(((Ep - Es).norm() / Es.norm()).item())
+    return {"value": float(np.median(ratio)), "unit": "x (t_plain / t_learned, median)", "steps": len(rows),
+            "ms_per_step": float(np.median([r["learned_s"] for r in rows]) * 1e3),
+            "config": {"workload": f"learned warm start: U-Net trained on {len(its) * 6} fields "
+                                   f"({len(its)} RSA packings 64^3, 6 unit loads), evaluated on {len(rows)} unseen "
+                                   f"128^3 packings, f=0.3, radii 6-12, contrast 100, Dirichlet, FP64 solver, tol 1e-6",
+                       "epochs": epochs, "train_steps": epochs * len(its)},
+            "warm_start": {
+                "ratio_min_median_max": [float(ratio.min()), float(np.median(ratio)), float(ratio.max())],
+                "ratio_mean": float(ratio.mean()),
+                "plain_ms_median": float(np.median([r["plain_s"] for r in rows]) * 1e3),
+                "learned_ms_median": float(np.median([r["learned_s"] for r in rows]) * 1e3),
+                "plain_iterations_median": float(np.median(pit)), "learned_iterations_median": float(np.median(lit)),
+                "fallback_fraction": float(np.mean([r["fell_back"] for r in rows])),
+                "not_converged_packings": int(nconv),
+                "plain_iterations_min_max": [int(pit.min()), int(pit.max())],
+                "sigma_rel_diff_max": float(max(r["dsig"] for r in rows)),
+                "inference_ms_128": round(t_inf * 1e3, 3),
+                "untrained_ratio_median": (float(np.median([r["plain_s"] / r["untrained_s"] for r in abl]))
+                                           if abl else None),
+                "start_sensitivity_iterations": sens,
+                "dataset_s": round(t_data, 1), "dataset_iterations_median": float(np.median(its)),
+                "train_s": round(t_train, 1), "train_loss_first_last_epoch": [float(losses[0]), float(losses[-1])]}}
 
 
 def measure_startcurve(npk):
@@ -937,7 +947,8 @@ def main():
     ap.add_argument("--n", type=int, default=100, help="grid: the side of the n^3 grid")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"], help="grid: precision")
     ap.add_argument("--no-extra", action="store_true",
-                    help="default workload: leave out the batched and non-diagonal Box lines")
+                    help="default workload: leave out the batched, non-diagonal Box, start-curve and "
+                         "learned-start entries")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -1076,6 +1087,11 @@ def main():
         extra["warm_start_curve"] = {"iterations_to_1e-6_by_start": measure_startcurve(1),
                                      "workload": "RSA packing 128^3 (seed 60000), f=0.3, radii 6-12, contrast 100, "
                                                  "Dirichlet, FP64, load e11; starts from the field converged to 1e-10"}
+        torch.cuda.empty_cache()
+        # the metric's second half: time to 1e-6 from the learned start against
+        # the zero start (the network trained as in --workload cfg5, evaluated
+        # on the first 20 of its 200 unseen packings)
+        extra["learned_start"] = measure_cfg5(args.train_packings, args.epochs, 20, 0, sensitivity=False)
         torch.cuda.empty_cache()
 
     cpu = None
