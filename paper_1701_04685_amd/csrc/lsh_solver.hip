@@ -499,6 +499,21 @@ int green_mode(const lsh_pattern* p) {
   return GREEN_TABLE;
 }
 
+// The two-pass Green pass's operator form: with the Dirichlet kernel on
+// M = diag(n, n, n) (SNF factors the identity, so the grid index is the
+// frequency) and an isotropic C0 it applies Gamma0 in closed form and reads no
+// table; otherwise the pattern's form.
+int twopass_green_mode(const lsh_pattern* p, int gmode) {
+  if (gmode != GREEN_MOMENTS || p->kind != LSH_DIRICHLET) return gmode;
+  const int64_t* M = p->M;
+  bool diag = M[0] > 0 && M[0] == M[4] && M[4] == M[8];
+  for (int i = 0; i < 9; ++i) {
+    if (i % 4 != 0 && M[i] != 0) diag = false;
+    if (p->V[i] != (i % 4 == 0 ? 1 : 0)) diag = false;
+  }
+  return diag ? GREEN_ISO : gmode;
+}
+
 bool kind_has_table(const lsh_pattern* p) {
   // the table slot (21 rows per bin) holds Gamma^p rows (GREEN_TABLE) or the
   // 15 fourth alias moments (GREEN_MOMENTS); before the stiffness is known,
@@ -775,6 +790,7 @@ struct GroupRun {
   Geo g;
   GreenParams gp;
   int gmode;
+  int gmode3;  // the two-pass Green pass's operator form (twopass_green_mode)
   GroupWS w;
   int nload;
   dim3 gridS, gridS1, gridB, gridG;  // gridS1: the stress pass (its own tile width)
@@ -845,6 +861,7 @@ int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
   int rc = make_kernels<T>(p, p->has_table, &G.K);
   if (rc) return rc;
   G.gmode = green_mode(p);
+  G.gmode3 = twopass_green_mode(p, G.gmode);
   {
     const int pi = prec_index(p);
     const int zero[4] = {0, 0, 0, 0};
@@ -853,7 +870,7 @@ int group_prepare(GroupRun<T>& G, char* base, size_t avail, size_t* used) {
   if (G.K.tpi >= 0) {
     rc = allow_lds(G.K.tp[G.K.tpi].s2, G.K.tp[G.K.tpi].ldss);
     const bool inc = G.spec.rep->scheme == LSH_SCHEME_LS_INC;
-    if (!rc) rc = allow_lds(G.K.tp[G.K.tpi].green(G.gmode, inc), G.K.tp[G.K.tpi].ldsg);
+    if (!rc) rc = allow_lds(G.K.tp[G.K.tpi].green(G.gmode3, inc), G.K.tp[G.K.tpi].ldsg);
     if (rc) return rc;
   }
   rc = allow_lds(G.K.gr, G.K.ldsG);
@@ -1028,7 +1045,7 @@ void launch_twopass(GroupRun<T>& G, int cur, int which, hipStream_t st) {
                        (const int*)G.w.stop_iter, (const int*)G.w.itp);
   if (which & 2) {
     const T* table = p->has_table ? (const T*)(p->dev_persist + p->off_table) : nullptr;
-    hipLaunchKernelGGL(c.green(G.gmode, inc), dim3(G.g.h1 * c.Q, (unsigned)(G.chunks.size() / 2)), dim3(c.ntg),
+    hipLaunchKernelGGL(c.green(G.gmode3, inc), dim3(G.g.h1 * c.Q, (unsigned)(G.chunks.size() / 2)), dim3(c.ntg),
                        c.ldsg, st,
                        G.g, tw1, tw2, (const T2*)G.w.TAU, (const T2*)G.w.P[cur], (T2*)G.w.P[1 - cur], table,
                        (const Inst*)G.w.insts, (const int*)G.w.inst_of, (const int*)G.w.chunks,
@@ -1104,7 +1121,7 @@ int tune_group(GroupRun<T>& G, hipStream_t st, int choice[4], int ncand[4], floa
   // "pass" 3 is the schedule: a whole four-pass iteration with the variants
   // chosen before, against each two-pass variant's iteration
   int ntp = 0;
-  for (const auto& c : G.K.tp) ntp += c.g3[G.gmode] ? 1 : 0;
+  for (const auto& c : G.K.tp) ntp += c.g3[G.gmode3] ? 1 : 0;
   const int nc[4] = {(int)G.K.c1.size(), (int)G.K.c2.size(), G.K.green2 ? (int)G.K.cg.size() : 1,
                      1 + (ntp == (int)G.K.tp.size() ? ntp : 0)};
   int rc = LSH_OK;
@@ -1135,7 +1152,7 @@ int tune_group(GroupRun<T>& G, hipStream_t st, int choice[4], int ncand[4], floa
       if (pass == 3 && G.K.tpi >= 0) {
         rc = allow_lds(G.K.tp[G.K.tpi].s2, G.K.tp[G.K.tpi].ldss);
         const bool inc = G.spec.rep->scheme == LSH_SCHEME_LS_INC;
-        if (!rc) rc = allow_lds(G.K.tp[G.K.tpi].green(G.gmode, inc), G.K.tp[G.K.tpi].ldsg);
+        if (!rc) rc = allow_lds(G.K.tp[G.K.tpi].green(G.gmode3, inc), G.K.tp[G.K.tpi].ldsg);
       }
       if (rc) break;
       auto run = [&]() {

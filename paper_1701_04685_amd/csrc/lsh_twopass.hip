@@ -193,6 +193,56 @@ __global__ void __launch_bounds__(NT) k_stress2(Geo g, const C2<T>* __restrict__
   }
 }
 
+// -Gamma^p_h/m applied to the Mandel 6-vector v at the integer frequency h of
+// the pattern diag(n, n, n) with the Dirichlet kernel and an isotropic C0
+// (Lame lambda0, mu0):  Gamma0_k tau = sym(u (x) tau u)/mu0 - r (u . tau u)
+// u (x) u, u = k/|k|, r = (lambda0 + mu0)/(mu0 (lambda0 + 2 mu0)), so that no
+// table is read and no operator is held; on the -n/2 faces the Hermitian part
+// averages it with the direction whose face coordinates are negated (the
+// representative of -h).  h = 0 gives 0.
+template <typename T>
+__device__ __forceinline__ void iso_dirichlet_apply(C2<T> v[6], int h0, int h1, int h2, int n, T imu, T r, T scale) {
+  using T2 = C2<T>;
+  const T RS2 = (T)0.70710678118654752440, SQ2 = (T)1.41421356237309504880;
+  if (h0 == 0 && h1 == 0 && h2 == 0) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = T2{0, 0};
+    return;
+  }
+  // tau from Mandel: diagonal, then (12, 02, 01) with the 1/sqrt2 of the shear entries
+  const T2 t00 = v[0], t11 = v[1], t22 = v[2];
+  const T2 t12 = T2{v[3].x * RS2, v[3].y * RS2}, t02 = T2{v[4].x * RS2, v[4].y * RS2},
+           t01 = T2{v[5].x * RS2, v[5].y * RS2};
+  const bool f0 = 2 * h0 == -n, f1 = 2 * h1 == -n, f2 = 2 * h2 == -n;
+  const int nd = (f0 || f1 || f2) ? 2 : 1;
+  T2 R[6] = {T2{0, 0}, T2{0, 0}, T2{0, 0}, T2{0, 0}, T2{0, 0}, T2{0, 0}};  // 00 11 22 12 02 01
+  for (int d = 0; d < nd; ++d) {
+    const T k0 = (T)((d && f0) ? -h0 : h0), k1 = (T)((d && f1) ? -h1 : h1), k2 = (T)((d && f2) ? -h2 : h2);
+    const T inv = (T)1 / sqrt(k0 * k0 + k1 * k1 + k2 * k2);
+    const T u0 = k0 * inv, u1 = k1 * inv, u2 = k2 * inv;
+    T2 w[3];
+    w[0] = T2{t00.x * u0 + t01.x * u1 + t02.x * u2, t00.y * u0 + t01.y * u1 + t02.y * u2};
+    w[1] = T2{t01.x * u0 + t11.x * u1 + t12.x * u2, t01.y * u0 + t11.y * u1 + t12.y * u2};
+    w[2] = T2{t02.x * u0 + t12.x * u1 + t22.x * u2, t02.y * u0 + t12.y * u1 + t22.y * u2};
+    const T2 sd = T2{u0 * w[0].x + u1 * w[1].x + u2 * w[2].x, u0 * w[0].y + u1 * w[1].y + u2 * w[2].y};
+    const T u[3] = {u0, u1, u2};
+    const int pa[6] = {0, 1, 2, 1, 0, 0}, pb[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+    for (int I = 0; I < 6; ++I) {
+      const int a = pa[I], b = pb[I];
+      const T hs = (T)0.5 * imu, ruu = r * u[a] * u[b];
+      R[I].x += hs * (u[a] * w[b].x + u[b] * w[a].x) - ruu * sd.x;
+      R[I].y += hs * (u[a] * w[b].y + u[b] * w[a].y) - ruu * sd.y;
+    }
+  }
+  const T f = nd == 2 ? (T)0.5 * scale : scale;
+#pragma unroll
+  for (int I = 0; I < 6; ++I) {
+    const T c = I < 3 ? f : f * SQ2;
+    v[I] = T2{R[I].x * c, R[I].y * c};
+  }
+}
+
 // -------------------------------------------------------------- Green pass ---
 // One block: position (k1, q) and a chunk of up to six loads of one instance,
 // one load at a time.  LDS: axis-3 twiddles [N3], w_P^k [P], lines
@@ -218,7 +268,8 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
                                                const int* __restrict__ itp, int npos, double* __restrict__ partial,
                                                int upd, C2<T>* __restrict__ dP) {
   using T2 = C2<T>;
-  static_assert(GM == GREEN_TABLE || GM == GREEN_MOMENTS, "tabled Green operators only");
+  static_assert(GM == GREEN_TABLE || GM == GREEN_MOMENTS || GM == GREEN_ISO,
+                "tabled Green operators or the Dirichlet closed form");
   constexpr int LS = N3 + 1;  // odd line stride: the same entry of neighbouring lines in other banks
   constexpr int NLN = 6 * P;  // lines (s, comp)
   constexpr int NI = 6 * N3;  // items (comp, i3) of the P-point stages
@@ -266,10 +317,10 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
   stage_twiddles<T>(tw3, tw2, N3);
   for (int i = tid; i < P; i += NT) twP[i] = tw1[i * Q];
   // -Gamma^p_h / m at this thread's bins (k1, k2 = q + Q s, k3), b = tid + k NT
-  T Gr[NB2][21];
-  {
+  T Gr[GM == GREEN_ISO ? 1 : NB2][21];  // the closed form (GREEN_ISO) holds no operator
+  const double mu0 = insts[inst_of[Lbeg]].mu0, riso = insts[inst_of[Lbeg]].riso;
+  if constexpr (GM != GREEN_ISO) {
     const double scale = -1.0 / (double)g.m;
-    const double mu0 = insts[inst_of[Lbeg]].mu0, riso = insts[inst_of[Lbeg]].riso;
 #pragma unroll
     for (int k = 0; k < NB2; ++k) {
       const int b = tid + k * NT;
@@ -316,16 +367,27 @@ __global__ void __launch_bounds__(NT) k_green3(Geo g, const C2<T>* __restrict__ 
         T2 v[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) v[c] = lines[(s * 6 + c) * LS + k3];
+        if constexpr (GM == GREEN_ISO) {
+          // signed frequency of each index: [-n/2, n/2)
+          const int f[3] = {k1, q + Q * s, k3};
+          int h[3];
 #pragma unroll
-        for (int I = 0; I < 6; ++I) {
-          T2 y = T2{0, 0};
+          for (int i = 0; i < 3; ++i) h[i] = 2 * f[i] >= N3 ? f[i] - N3 : f[i];
+          iso_dirichlet_apply<T>(v, h[0], h[1], h[2], N3, (T)(1.0 / mu0), (T)riso, (T)(-1.0 / (double)g.m));
 #pragma unroll
-          for (int J = 0; J < 6; ++J) {
-            const T gij = Gr[k][I <= J ? tri_idx(I, J) : tri_idx(J, I)];
-            y.x += gij * v[J].x;
-            y.y += gij * v[J].y;
+          for (int I = 0; I < 6; ++I) lines[(s * 6 + I) * LS + k3] = v[I];
+        } else {
+#pragma unroll
+          for (int I = 0; I < 6; ++I) {
+            T2 y = T2{0, 0};
+#pragma unroll
+            for (int J = 0; J < 6; ++J) {
+              const T gij = Gr[k][I <= J ? tri_idx(I, J) : tri_idx(J, I)];
+              y.x += gij * v[J].x;
+              y.y += gij * v[J].y;
+            }
+            lines[(s * 6 + I) * LS + k3] = y;
           }
-          lines[(s * 6 + I) * LS + k3] = y;
         }
       }
     }
@@ -474,6 +536,8 @@ void add_cand(const Geo& g, TwoPass<T>* out, int maxn, int* n) {
   c.g3[GREEN_MOMENTS] = k_green3<T, P, N3, NTG, GREEN_MOMENTS, PF>;
   c.g3inc[GREEN_TABLE] = k_green3<T, P, N3, NTG, GREEN_TABLE, PF, true>;
   c.g3inc[GREEN_MOMENTS] = k_green3<T, P, N3, NTG, GREEN_MOMENTS, PF, true>;
+  c.g3[GREEN_ISO] = k_green3<T, P, N3, NTG, GREEN_ISO, PF>;
+  c.g3inc[GREEN_ISO] = k_green3<T, P, N3, NTG, GREEN_ISO, PF, true>;
   c.Q = Q;
   c.P = P;
   c.W = W;
