@@ -248,7 +248,10 @@ __device__ __forceinline__ void iso_dirichlet_apply(C2<T> v[6], int h0, int h1, 
 // one load at a time.  LDS: axis-3 twiddles [N3], w_P^k [P], lines
 // [(s, comp)][LS] along axis 3.  The Green operator -Gamma^p/m of the tile's
 // bins (k1, q + Q s, k3) is formed once per chunk into registers (each thread
-// keeps the NB2 bins it multiplies).  Per load: the tile's P n3 values of
+// keeps the NB2 bins it multiplies) from the table or the alias moments (GM =
+// GREEN_TABLE, GREEN_MOMENTS), or applied in closed form per bin for the
+// Dirichlet kernel on diag(n, n, n) (GM = GREEN_ISO, iso_dirichlet_apply).
+// Per load: the tile's P n3 values of
 // each component come in with the P-point DFT over r done in registers (the
 // next load's values are fetched while this one is transformed), the axis-3
 // transforms run in LDS, and the values go out through the inverse
