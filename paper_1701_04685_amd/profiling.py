@@ -12,6 +12,9 @@ Usage (after the rocprofv3 runs, on their CSV output):
   python -m paper_1701_04685_amd.profiling stats  RUN_kernel_stats.csv TITLE COMMAND > out.txt
   python -m paper_1701_04685_amd.profiling traffic --kernel NAME --fetch F.csv --write W.csv
          --copy-fetch CF.csv --copy-write CW.csv --copy-bytes N --commands CMDS --out profiles/X
+  python -m paper_1701_04685_amd.profiling passes --spec KERNEL=LABEL=READ=WRITE [--spec ...]
+         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv --copy-bytes N
+         --title T --commands CMDS --out profiles/X
 """
 from __future__ import annotations
 
@@ -82,6 +85,40 @@ def traffic_summary(kernel, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv
             "fetch_bytes": fetch, "write_bytes": write, "traffic_bytes": fetch + write, "commands": commands}
 
 
+def pass_traffic_table(specs, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, title, commands):
+    """Counted HBM traffic of several kernels of one run against their algorithmic
+    bytes.  specs: (kernel name substring, label, algorithmic read bytes,
+    algorithmic write bytes) per kernel.  Every kernel's counters are scaled by
+    the same copy calibration, so kernels whose bytes are known exactly (the
+    axis-2 passes read and write the state once) test that calibration on
+    access patterns other than the copy's."""
+    base = traffic_summary("elementwise", copy_fetch_csv, copy_write_csv, copy_fetch_csv, copy_write_csv,
+                           copy_bytes, commands)
+    fs, ws = base["fetch_scale"], base["write_scale"]
+    out = [f"# {title}", "", "Commands (FETCH_SIZE run, WRITE_SIZE run, copy calibration runs):", "", "```",
+           commands, "```", "",
+           f"Copy calibration ({copy_bytes:.0f} B each way): FETCH_SIZE x {fs:.4f}, WRITE_SIZE x {ws:.4f}.",
+           "Counted = the median dispatch's counter value times that scale; alg. = the bytes the pass must",
+           "read and write (the state, the phase map, the previous iterate).", "",
+           f"{'kernel':40s} {'pass':24s} {'n':>3s} {'read GB':>8s} {'alg.':>7s} {'ratio':>6s} "
+           f"{'write GB':>8s} {'alg.':>7s} {'ratio':>6s}"]
+    rows = []
+    for kern, label, ar, aw in specs:
+        kf = counter_kib(fetch_csv, "FETCH_SIZE", kern)
+        kw = counter_kib(write_csv, "WRITE_SIZE", kern)
+        if not kf or not kw:
+            continue
+        rd = statistics.median(kf) * 1024.0 * fs
+        wr = statistics.median(kw) * 1024.0 * ws
+        rows.append({"kernel": kern, "pass": label, "dispatches": [len(kf), len(kw)], "read_bytes": rd,
+                     "write_bytes": wr, "alg_read_bytes": ar, "alg_write_bytes": aw})
+        out.append(f"{kern[:40]:40s} {label[:24]:24s} {len(kf):3d} {rd / 1e9:8.4f} {ar / 1e9:7.4f} {rd / ar:6.3f} "
+                   f"{wr / 1e9:8.4f} {aw / 1e9:7.4f} {wr / aw:6.3f}")
+    out += ["", f"source fingerprint {source_fingerprint()}", ""]
+    return "\n".join(out), {"title": title, "fingerprint": source_fingerprint(), "fetch_scale": fs,
+                             "write_scale": ws, "rows": rows, "commands": commands}
+
+
 def load_traffic(kernel_substr: str, profiles_dir: str = os.path.join(ROOT, "profiles")):
     """Stored traffic (bytes per launch) for a kernel, or None if absent or stale."""
     if not os.path.isdir(profiles_dir):
@@ -112,7 +149,25 @@ def main():
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--commands", required=True)
     t.add_argument("--out", required=True, help="path prefix: writes PREFIX_traffic.json and PREFIX_traffic.md")
+    pt = sub.add_parser("passes", help="counted vs algorithmic bytes of several kernels of one run")
+    pt.add_argument("--spec", action="append", required=True,
+                    help="KERNEL_SUBSTRING=LABEL=ALG_READ_BYTES=ALG_WRITE_BYTES (repeat per kernel)")
+    for k in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--title", "--commands", "--out"):
+        pt.add_argument(k, required=True)
+    pt.add_argument("--copy-bytes", type=float, required=True)
     a = ap.parse_args()
+    if a.cmd == "passes":
+        specs = []
+        for sp in a.spec:
+            kern, label, ar, aw = sp.split("=")
+            specs.append((kern, label, float(ar), float(aw)))
+        text, d = pass_traffic_table(specs, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes, a.title,
+                                     a.commands)
+        with open(a.out + ".md", "w") as fh:
+            fh.write(text)
+        with open(a.out + ".json", "w") as fh:
+            json.dump(d, fh, indent=1)
+        return
     if a.cmd == "stats":
         print(kernel_stats_table(a.csv, a.title, a.command), end="")
         return
