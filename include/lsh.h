@@ -179,13 +179,17 @@ int lsh_set_scheme(lsh_pattern *p, lsh_scheme scheme);
 
 /* ------------------------------------------------------------- device binding ---
  * Bytes of persistent device memory for this pattern at precision prec: the
- * phase map, FFT twiddles and, for LSH_BOXSPLINE, the Gamma^p table (21
- * entries per half-spectrum bin, summed in double, stored at prec).
+ * phase map, FFT twiddles and the Green operator's table.  For LSH_BOXSPLINE,
+ * and for the other smoothed kernels with an anisotropic C0, it holds the 21
+ * entries of Gamma^p per half-spectrum bin; for the Dirichlet, modified
+ * Dirichlet and dlVP kernels with an isotropic C0, the 15 fourth moments of
+ * the alias directions per bin (the Dirichlet kernel with an anisotropic C0
+ * needs none).  Sums in double, stored at prec; sized for the 21-entry table.
  * Needs lsh_set_kernel first.                                                     */
 int lsh_persistent_bytes(const lsh_pattern *p, lsh_precision prec, size_t *bytes);
 
-/* Uploads the phase map and twiddles into dev_persistent and, for tabled
- * kernels, builds the Gamma^p table on the GPU (synchronises `stream`; checks
+/* Uploads the phase map and twiddles into dev_persistent and builds the Green
+ * operator's table on the GPU (synchronises `stream`; for the Box spline checks
  * every bracket sum is positive).  dev_persistent must stay alive while the
  * pattern is used at this precision.  Errors: LSH_ESTATE (kernel/stiffness not
  * set), LSH_EWORKSPACE, LSH_ENOINTERP, LSH_EUNSUPPORTED, LSH_EDEVICE.            */
